@@ -1,0 +1,38 @@
+"""CPU FP64 oracle for the energy-stable hydrodynamic CDFT/PFC scheme.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it, to check the HIP library against
+a plain, slow, obviously correct NumPy transcription of the paper
+(Baskaran, Guan & Lowengrub, "Energy stable multigrid method for local and
+non-local hydrodynamic models for freezing", arXiv 1503.07416).
+
+It shares no code with the HIP path.  Every function cites the passage of the
+paper it follows (section, equation label, appendix).  Modules:
+
+``grid``      discrete operators, inner products and norms (App. E)
+``models``    discrete PFC and CDFT free energies and their convex splittings
+              (Sec. 5.2, 5.3; Lemmas CDFT_ineq / PFC_ineq)
+``kernel``    the CDFT convolution kernel J, its split J = J_c - J_e, the
+              h^2-weighted periodic convolution (Eq. discrete_convolution,
+              Sec. 6) by direct sum and by DFT
+``scheme``    the fully discrete scheme, Eqs. discrete_a-d, written in vector
+              form with the App. E operators
+``system``    the same scheme as the nonlinear system N(g) = S of App. G
+              (typos corrected, see the readings list in the design doc)
+``smoother``  damped point-block nonlinear Gauss-Seidel (App. G, damping of
+              App. G "Damped Gauss-Seidel Iteration"), red-black ordered
+``fas``       FAS multigrid V-cycle and the time stepper (Sec. 6, App. G)
+``newton``    dense Newton on the system N(g) = S for tiny grids: the plain
+              definition of the implicit step's solution
+``linear``    closed forms of the linearised scheme (growth of small Fourier
+              modes about a uniform state, viscous shear decay)
+
+Pins (see tests/test_oracle_*.py): Fourier symbols and summation by parts of
+the operators; two transcriptions of the scheme agree; FAS equals dense Newton;
+discrete mass conservation and the discrete energy identity of App. F;
+convex-splitting gap >= 0; energy non-increase for s in 1e-3..1e3; closed-form
+linear growth and shear decay; uniform fixed points; symmetry equivariance;
+FFT convolution equals the direct sum; the Cauchy errors the paper prints in
+its convergence tables (tests/golden/).
+"""

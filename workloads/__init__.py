@@ -1,0 +1,171 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle
+checks.  This module only draws random numbers and fixes the constants of each
+workload; it holds none of the scheme's arithmetic.
+
+Constants follow the paper's own runs (Sec. 6), with the readings listed in
+the design doc:
+
+* PFC freezing run: eps = 0.025 (alpha = 1 - eps), gamma = 2, domain
+  [0,32)^2 on 128^2 (h = 0.25), s = 0.01; mean density 3/2 - 0.07 sqrt(3)
+  (the printed "+1/2" read as "+3/2", the offset of the map rho = sqrt(3) psi + 3/2
+  of App. B).
+* CDFT freezing run: nu = 2.362, gamma = 2, delta = 1e-10, domain [0,17)^2 on
+  128^2 (h = 17/128), s = 0.02; mean density 6 * 0.6 / pi (number density at
+  packing fraction 0.6; the printed "pi/6 x 0.6" makes the uniform state stable,
+  against the text).
+* Sheared-nanocrystal run: eps = 0.4, coexistence densities 0.72958 and 0.90073,
+  h = pi / (2 sqrt 3), s = 0.02.
+"""
+import math
+from dataclasses import dataclass, field, asdict
+
+import numpy as np
+
+PFC_EPS = 0.025
+PFC_RHO_BAR = 1.5 - 0.07 * math.sqrt(3.0)
+CDFT_NU = 2.362
+CDFT_RHO_BAR = 6.0 * 0.6 / math.pi
+NANO_EPS = 0.4
+NANO_RHO_L = 0.72958
+NANO_RHO_S = 0.90073
+NANO_H = math.pi / (2.0 * math.sqrt(3.0))
+
+
+@dataclass
+class Config:
+    """Parameters of one instance (the C ABI's parameter block carries the same
+    values)."""
+    model: str                 # "pfc" or "cdft"
+    n: int
+    h: float
+    s: float
+    gamma: float = 2.0
+    alpha: float = 1.0 - PFC_EPS
+    nu: float = CDFT_NU
+    delta: float = 1e-10
+    w: float = 0.5
+    tol: float = 1e-10
+    nu1: int = 2
+    nu2: int = 2
+    max_cycles: int = 200
+    coarsest_n: int = 4
+    coarse_sweeps: int = 16
+    sigma: float = 1.0
+    continuity_fix: bool = True
+    precision: str = "fp64"    # "fp64" or "mixed"
+
+    def oracle_kwargs(self):
+        d = asdict(self)
+        d.pop("precision")
+        d.pop("n"); d.pop("h"); d.pop("s"); d.pop("model")
+        if self.model == "pfc":
+            d.pop("nu"); d.pop("delta")
+        else:
+            d.pop("alpha")
+        return d
+
+
+def pfc_uniform_noise(n, h, s, seed, rho_bar=PFC_RHO_BAR, amp=0.05, **kw):
+    """rho = rho_bar + amp * U(-1, 1), u = v = 0."""
+    rng = np.random.default_rng(seed)
+    rho = rho_bar + amp * rng.uniform(-1.0, 1.0, (n, n))
+    z = np.zeros((n, n))
+    return Config("pfc", n, h, s, **kw), rho, z.copy(), z.copy()
+
+
+def cdft_gauss_noise(n, h, s, seed, rho_bar=CDFT_RHO_BAR, amp=0.02, **kw):
+    """rho = rho_bar + amp * N(0, 1), u = v = 0."""
+    rng = np.random.default_rng(seed)
+    rho = rho_bar + amp * rng.standard_normal((n, n))
+    z = np.zeros((n, n))
+    return Config("cdft", n, h, s, **kw), rho, z.copy(), z.copy()
+
+
+def random_velocity(n, seed, amp):
+    rng = np.random.default_rng(seed)
+    return amp * rng.uniform(-1.0, 1.0, (n, n)), amp * rng.uniform(-1.0, 1.0, (n, n))
+
+
+# ---- the five workloads of the benchmark / parity suite -------------------
+
+def config1(seed=0):
+    """PFC, 32^2, h = 0.25, s = 0.01, 10 steps, FP64, V(2,2), tol 1e-10."""
+    return pfc_uniform_noise(32, 0.25, 0.01, seed)
+
+
+def config2(seed=0, precision="fp64"):
+    """PFC, 512^2, h = 0.25, s = 0.01, 100 steps; FP64 or mixed precision."""
+    return pfc_uniform_noise(512, 0.25, 0.01, seed, precision=precision)
+
+
+def config3(seed=0, n=1024):
+    """CDFT, 1024^2, h = 17/128, s = 0.02, rho_bar + 0.02 N(0,1), 50 steps."""
+    return cdft_gauss_noise(n, 17.0 / 128.0, 0.02, seed)
+
+
+def config4(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
+    """Batch of independent PFC instances (eps = 0.4, h = pi/(2 sqrt 3), s = 0.02),
+    n ~ U{sizes}, rho_bar ~ U(rho_l, rho_s), rho = rho_bar + 0.05 U(-1,1);
+    instance i draws its field from seed 1000 + i."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    rbs = rng.uniform(NANO_RHO_L, NANO_RHO_S, size=count)
+    out = []
+    for i, (n, rb) in enumerate(zip(ns, rbs)):
+        cfg, rho, u, v = pfc_uniform_noise(int(n), NANO_H, 0.02, 1000 + i,
+                                           rho_bar=float(rb), alpha=1.0 - NANO_EPS,
+                                           precision=precision)
+        out.append((cfg, rho, u, v))
+    return out
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds after the stream starts
+    steps: int
+    cfg: Config
+    rho: np.ndarray = field(repr=False)
+    u: np.ndarray = field(repr=False)
+    v: np.ndarray = field(repr=False)
+
+
+def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
+                   steps=(10, 200), precision="fp64"):
+    """Poisson request stream: exponential inter-arrival times of mean 1/rate,
+    model PFC or CDFT with probability 1/2 each, n ~ U{sizes},
+    steps ~ U{steps[0]..steps[1]}.  PFC requests are drawn as in ``config4``,
+    CDFT requests as in ``config3`` at their own size."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.choice(np.asarray(sizes)))
+        nst = int(rng.integers(steps[0], steps[1] + 1))
+        if rng.uniform() < 0.5:
+            rb = float(rng.uniform(NANO_RHO_L, NANO_RHO_S))
+            cfg, rho, u, v = pfc_uniform_noise(n, NANO_H, 0.02, 5000 + i, rho_bar=rb,
+                                               alpha=1.0 - NANO_EPS, precision=precision)
+        else:
+            cfg, rho, u, v = cdft_gauss_noise(n, 17.0 / 128.0, 0.02, 5000 + i,
+                                              precision=precision)
+        reqs.append(Request(i, t, nst, cfg, rho, u, v))
+    return reqs
+
+
+def paper_convergence_ic(n, model, L=32.0):
+    """Smooth initial density of the paper's convergence tests (Sec. 6.1.1 for
+    CDFT with mean 6*0.6/pi, Sec. 6.1.2 for PFC with offset 3/2); u = v = 0."""
+    h = L / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x)
+    p = (-0.02 * np.cos(2 * np.pi * (X - 12) / 32) * np.sin(2 * np.pi * (Y - 1) / 32)
+         + 0.02 * np.cos(np.pi * (X + 10) / 32) ** 2 * np.cos(np.pi * (Y + 3) / 32) ** 2
+         - 0.01 * np.sin(4 * np.pi * X / 32) ** 2 * np.sin(4 * np.pi * (Y - 6) / 32) ** 2)
+    if model == "pfc":
+        rho = math.sqrt(3.0) * (-0.07 + p) + 1.5
+    else:
+        rho = CDFT_RHO_BAR + p
+    z = np.zeros((n, n))
+    return rho, z.copy(), z.copy()
