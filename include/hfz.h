@@ -1,0 +1,166 @@
+/*
+ * hfz — energy-stable FAS multigrid for the hydrodynamic PFC / CDFT freezing
+ * models on one AMD MI355X (gfx950).
+ *
+ * The library advances the fully discrete convex-splitting scheme of
+ * Baskaran, Guan & Lowengrub, "Energy stable multigrid method for local and
+ * non-local hydrodynamic models for freezing" (arXiv 1503.07416), Sec. 5,
+ * Eqs. discrete_a-d, on a periodic n x n nodal grid:
+ *
+ *   rho^{k+1} - rho^k = -s div_h(rho^k u^{k+1/2})
+ *   rho^k (u^{k+1} - u^k) = s[ -rho^k omega^k x u^{k+1/2} - (rho^k/2) grad_h|u^{k+1}|^2
+ *                              - rho^k grad_h mu^{k+1} + gamma Delta_h u^{k+1/2} ]
+ *   mu^{k+1} = dF_c[rho^{k+1}] - dF_e[rho^k],   omega^k = curl_h u^k
+ *
+ * with the discrete PFC free energy (Sec. 5.3) or the discrete CDFT free
+ * energy with the Sec. 6 kernel J (Sec. 5.2; the convolution is applied
+ * through a DFT).  Each implicit step is the nonlinear system N(g) = S of
+ * App. G, solved by FAS V-cycles with the damped point-block Gauss-Seidel
+ * smoother of App. G (red-black ordered), full-weighting restriction and
+ * bilinear prolongation, until ||S - N(g)||_2 <= tol.
+ *
+ * Conventions for every entry point
+ *  - Return value: HFZ_OK (0) or a negative HFZ_E* code; no exception or
+ *    abort crosses the ABI.  hfz_strerror() names a code.
+ *  - Fields are FP64, n*n values, row-major [j][i] with x (index i) fastest,
+ *    node (i, j) at (i h, j h).
+ *  - Device pointers are plain HIP device addresses on the device current
+ *    when hfz_init ran.  The caller owns all device memory: the workspace
+ *    (hfz_workspace_bytes) and the state buffers.  The library never
+ *    allocates device memory.
+ *  - All device work is enqueued on the stream given to hfz_init
+ *    (a hipStream_t passed as void*, NULL for the default stream).  Entry
+ *    points that return host values (hfz_step's convergence test, energy,
+ *    mass, residual) synchronise that stream.
+ *  - A handle is not thread safe; distinct handles with distinct workspaces
+ *    may be used concurrently.
+ */
+#ifndef HFZ_H
+#define HFZ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HFZ_OK = 0,
+  HFZ_EINVAL = -1,   /* bad parameter: n not a power of two >= 8, h/s/gamma <= 0, ... */
+  HFZ_ENOMEM = -2,   /* workspace smaller than hfz_workspace_bytes */
+  HFZ_EDOMAIN = -3,  /* CDFT state with rho <= 0 (ln rho undefined, Sec. 2.1) */
+  HFZ_ENOCONV = -4,  /* max_cycles V-cycles without reaching tol; state not advanced */
+  HFZ_ENAN = -5,     /* non-finite residual or energy; state not advanced */
+  HFZ_EHIP = -6,     /* HIP runtime error */
+  HFZ_ESTATE = -7    /* call out of order (e.g. step before set_state) */
+};
+
+enum { HFZ_PFC = 0, HFZ_CDFT = 1 };
+enum { HFZ_FP64 = 0, HFZ_MIXED = 1 };
+
+/* Parameters of one simulation.  Paper values: gamma = 2 (Sec. 6), w_damp =
+ * 0.5 (App. G, damped Gauss-Seidel), delta = 1e-10 for CDFT and unused for PFC
+ * (Sec. 6, positivity projection), alpha = 1 - eps (App. B). */
+typedef struct hfz_params {
+  int model;          /* HFZ_PFC or HFZ_CDFT */
+  int n;              /* grid is n x n, n a power of two, 8 <= n <= 8192 */
+  double h;           /* grid spacing (> 0) */
+  double s;           /* time step (> 0) */
+  double gamma;       /* viscosity (> 0) */
+  double alpha;       /* PFC: coefficient of the quadratic term */
+  double nu;          /* CDFT: kernel scale of J (Sec. 6) */
+  double delta;       /* CDFT: rho <- sqrt(rho^2 + delta^2) after each rho update */
+  double w_damp;      /* damping, x <- (1 - w) x_GS + w x_old, 0 <= w < 1 */
+  double tol;         /* residual tolerance on ||S - N(g)||_2 (h^2-weighted) */
+  int nu1, nu2;       /* pre / post smoothing sweeps per level (>= 0, sum >= 1) */
+  int max_cycles;     /* V-cycle cap per step (>= 1) */
+  int coarsest_n;     /* coarsest grid size, power of two, 4 <= coarsest_n <= n */
+  int coarse_sweeps;  /* sweeps on the coarsest grid per V-cycle (>= 1) */
+  int precision;      /* HFZ_FP64, or HFZ_MIXED: FP32 smoothing inside FP64 defect correction */
+  int sigma;          /* +1: -rho omega x u in vector form (default); -1: App. G sign */
+  int continuity_fix; /* 1: recompute rho^{k+1} from the continuity row after the solve */
+} hfz_params;
+
+typedef struct hfz_stats {
+  int steps_done;       /* steps completed by this call */
+  int cycles_last;      /* V-cycles (mixed: outer corrections) of the last step */
+  long long cycles_total;
+  double residual_last; /* final ||S - N(g)||_2 of the last step */
+} hfz_stats;
+
+typedef struct hfz_handle hfz_handle;
+
+/* Fills hfz_params with the paper's defaults for the given model (n, h, s
+ * still to be set by the caller).  Pure host function. */
+int hfz_default_params(int model, hfz_params* p);
+
+/* Bytes of device workspace hfz_init needs for *p.  Pure host function;
+ * validates *p (HFZ_EINVAL). */
+int hfz_workspace_bytes(const hfz_params* p, size_t* bytes);
+
+/* Creates a handle.  dev_ws: caller-owned device buffer of ws_bytes >=
+ * hfz_workspace_bytes (256-byte aligned); it must outlive the handle.
+ * For CDFT this tabulates the periodised kernel J_{k,l} = J(x_{k,l})
+ * (minimum image), computes (J_e * 1) = h^2 sum J_e (Lemma CDFT_ineq) and the
+ * DFT multiplier h^2 DFT(J) of Eq. discrete_convolution on the device. */
+int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
+             hfz_handle** out);
+
+/* Loads (rho^0, u^0, v^0) from device buffers of n*n doubles each (copied;
+ * the caller keeps ownership).  PFC: mu and kappa start consistent with
+ * rho^{k+1} = rho^k.  CDFT: fails with HFZ_EDOMAIN if min rho <= 0. */
+int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const double* v);
+
+/* Copies the current (rho^k, u^k, v^k) into caller device buffers. */
+int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v);
+
+/* Copies the PFC auxiliary unknowns (mu, kappa) of the last solve (or the
+ * initial guess) into caller device buffers; HFZ_EINVAL for CDFT. */
+int hfz_get_aux(hfz_handle* hd, double* mu, double* kappa);
+
+/* Advances nsteps time steps.  On HFZ_ENOCONV / HFZ_ENAN the failing step is
+ * rolled back: the state is that of the last completed step, and
+ * stats->steps_done says how many completed.  stats may be NULL. */
+int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats);
+
+/* Discrete energy of the current state (Thm. thm_energy_stability):
+ * out[0] = E = KE + F, out[1] = KE = (rho u || u)/2, out[2] = F,
+ * out[3], out[4] = F_id, F_ex for CDFT (0 for PFC).  Host array of 5. */
+int hfz_energy(hfz_handle* hd, double* out5);
+
+/* Discrete mass (rho || 1) = h^2 sum rho of the current state. */
+int hfz_mass(hfz_handle* hd, double* mass);
+
+/* ---- stage-level entry points (the same kernels hfz_step runs; for tests
+ *      and for callers that drive the solve themselves) ------------------- */
+
+/* Source and frozen coefficients of the step from the current state: S and
+ * omega^k (App. G), rho^k and omega^k restricted to every level, the CDFT
+ * convolution J * rho^k; the iterate g starts at the state. */
+int hfz_begin_step(hfz_handle* hd);
+/* `sweeps` damped red-black sweeps on level `level` (0 = finest). */
+int hfz_smooth(hfz_handle* hd, int level, int sweeps);
+/* `count` FAS V(nu1, nu2) cycles on the finest level without a stop test. */
+int hfz_vcycle(hfz_handle* hd, int count);
+/* ||f - N(g)||_2 on level 0 (host double). */
+int hfz_residual(hfz_handle* hd, double* norm);
+/* Ends the step: continuity fix, state <- g, next CDFT convolution. */
+int hfz_finish_step(hfz_handle* hd);
+
+/* Field access for tests.  which: 0 = iterate g, 1 = right-hand side f,
+ * 2 = restricted iterate R g (coarse levels), 3 = frozen coefficient
+ * (comp 0 rho^k, comp 1 omega^k), 4 = J * rho of the state (comp 0, level 0).
+ * dst / src: device buffers of n_l * n_l doubles, n_l = n >> level. */
+int hfz_read_field(hfz_handle* hd, int which, int level, int comp, double* dst);
+int hfz_write_field(hfz_handle* hd, int which, int level, int comp, const double* src);
+
+/* Number of grid levels and the CDFT scalar (J_e * 1) (0 for PFC). */
+int hfz_info(hfz_handle* hd, int* levels, double* ce);
+
+int hfz_destroy(hfz_handle* hd);
+const char* hfz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFZ_H */

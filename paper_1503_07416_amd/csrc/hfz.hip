@@ -1,0 +1,627 @@
+// Host side of the hfz library: parameter checks, workspace layout, the FAS
+// driver (V-cycles, stop test, step roll-back), the CDFT convolution set-up,
+// diagnostics and the C ABI declared in include/hfz.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hfz.h"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+using namespace hfz;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+int validate(const hfz_params* p) {
+  if (!p) return HFZ_EINVAL;
+  if (p->model != HFZ_PFC && p->model != HFZ_CDFT) return HFZ_EINVAL;
+  if (!is_pow2(p->n) || p->n < 8 || p->n > 8192) return HFZ_EINVAL;
+  if (p->model == HFZ_CDFT && p->n > 2048) return HFZ_EINVAL;  // LDS row FFT: 2 x 2048 complex doubles
+  if (!(p->h > 0) || !(p->s > 0) || !(p->gamma > 0)) return HFZ_EINVAL;
+  if (!(p->w_damp >= 0.0) || !(p->w_damp < 1.0)) return HFZ_EINVAL;
+  if (!(p->tol > 0)) return HFZ_EINVAL;
+  if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 < 1) return HFZ_EINVAL;
+  if (p->max_cycles < 1 || p->coarse_sweeps < 1) return HFZ_EINVAL;
+  if (!is_pow2(p->coarsest_n) || p->coarsest_n < 4 || p->coarsest_n > p->n) return HFZ_EINVAL;
+  if (p->sigma != 1 && p->sigma != -1) return HFZ_EINVAL;
+  if (p->precision != HFZ_FP64 && p->precision != HFZ_MIXED) return HFZ_EINVAL;
+  if (p->model == HFZ_CDFT && (!(p->nu > 0) || !(p->delta >= 0))) return HFZ_EINVAL;
+  if (p->model == HFZ_PFC && !std::isfinite(p->alpha)) return HFZ_EINVAL;
+  return HFZ_OK;
+}
+
+// Workspace carving: a bump allocator over the caller's buffer.  Run once
+// with base == nullptr to size the workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T> T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct Dims {
+  dim3 grid, block;
+};
+
+Dims dims2(int nx, int ny) {
+  const int bx = std::min(64, nx);
+  const int by = std::max(1, std::min(256 / bx, ny));
+  return {dim3((nx + bx - 1) / bx, (ny + by - 1) / by), dim3(bx, by)};
+}
+
+}  // namespace
+
+struct hfz_handle {
+  hfz_params p{};
+  hipStream_t stream = nullptr;
+  int nlev = 0;
+  int nc = 0;
+  double ce = 0.0;
+  bool has_state = false;
+  std::vector<Lvl<double>> L;
+  // state (rho^k is L[0].rk)
+  double* u = nullptr;
+  double* v = nullptr;
+  double* mu = nullptr;
+  double* ka = nullptr;
+  // CDFT
+  double* jrho = nullptr;
+  double* mult = nullptr;
+  double2* fa = nullptr;
+  double2* fb = nullptr;
+  // reductions
+  double* partial = nullptr;
+  double* result = nullptr;
+  size_t partial_cap = 0;
+  Phys<double> P{};
+};
+
+namespace {
+
+// Lays out every buffer of the handle; with ws == nullptr only sizes.
+size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
+  Carver c{static_cast<char*>(ws)};
+  const int nc = (p.model == HFZ_PFC) ? 5 : 3;
+  const int n = p.n;
+  const size_t N2 = (size_t)n * n;
+  std::vector<Lvl<double>> L;
+  for (int m = n; m >= p.coarsest_n; m >>= 1) {
+    Lvl<double> l{};
+    l.n = m;
+    l.lg = ilog2(m);
+    const size_t cnt = (size_t)m * m;
+    for (int k = 0; k < nc; ++k) l.g[k] = c.take<double>(cnt);
+    for (int k = 0; k < nc; ++k) l.f[k] = c.take<double>(cnt);
+    if (m != n)
+      for (int k = 0; k < nc; ++k) l.g0[k] = c.take<double>(cnt);
+    l.rk = c.take<double>(cnt);
+    l.om = c.take<double>(cnt);
+    L.push_back(l);
+  }
+  double* u = c.take<double>(N2);
+  double* v = c.take<double>(N2);
+  double *mu = nullptr, *ka = nullptr;
+  if (p.model == HFZ_PFC) {
+    mu = c.take<double>(N2);
+    ka = c.take<double>(N2);
+  }
+  double *jrho = nullptr, *mult = nullptr;
+  double2 *fa = nullptr, *fb = nullptr;
+  if (p.model == HFZ_CDFT) {
+    jrho = c.take<double>(N2);
+    mult = c.take<double>(N2);
+    fa = c.take<double2>(N2);
+    fb = c.take<double2>(N2);
+  }
+  const size_t pcap = std::max<size_t>(4096, N2 / 64 + 64);
+  double* partial = c.take<double>(pcap * 4);
+  double* result = c.take<double>(64);
+  if (hd) {
+    hd->nc = nc;
+    hd->nlev = (int)L.size();
+    double h = p.h;
+    for (auto& l : L) {
+      l.h = h;
+      h *= 2.0;
+    }
+    hd->L = L;
+    hd->u = u;
+    hd->v = v;
+    hd->mu = mu;
+    hd->ka = ka;
+    hd->jrho = jrho;
+    hd->mult = mult;
+    hd->fa = fa;
+    hd->fb = fb;
+    hd->partial = partial;
+    hd->result = result;
+    hd->partial_cap = pcap;
+  }
+  return c.off;
+}
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return HFZ_EHIP; \
+  } while (0)
+
+int last_error() { return hipGetLastError() == hipSuccess ? HFZ_OK : HFZ_EHIP; }
+
+// ---- launch helpers -------------------------------------------------------
+
+template <int MODEL> void smooth_level(hfz_handle* hd, int l, int sweeps) {
+  const Lvl<double>& L = hd->L[l];
+  const Dims d = dims2(L.n / 2, L.n);
+  for (int k = 0; k < sweeps; ++k) {
+    for (int colour = 0; colour < 2; ++colour)
+      k_smooth_colour<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
+  }
+}
+
+template <int MODEL> void vcycle_rec(hfz_handle* hd, int l) {
+  const int last = hd->nlev - 1;
+  if (l == last) {
+    smooth_level<MODEL>(hd, l, hd->p.coarse_sweeps);
+    return;
+  }
+  smooth_level<MODEL>(hd, l, hd->p.nu1);
+  const Lvl<double>& F = hd->L[l];
+  const Lvl<double>& C = hd->L[l + 1];
+  const Dims dc = dims2(C.n, C.n);
+  k_fas_restrict<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(F, C, hd->P);
+  k_fas_rhs<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(C, hd->P);
+  vcycle_rec<MODEL>(hd, l + 1);
+  const Dims df = dims2(F.n, F.n);
+  k_prolong<MODEL, double><<<df.grid, df.block, 0, hd->stream>>>(F, C, hd->P);
+  smooth_level<MODEL>(hd, l, hd->p.nu2);
+}
+
+template <int MODEL> int residual_impl(hfz_handle* hd, double* norm) {
+  const Lvl<double>& L = hd->L[0];
+  const Dims d = dims2(L.n, L.n);
+  const int nb = d.grid.x * d.grid.y;
+  k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, hd->partial);
+  k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, nb, 1, L.h * L.h, hd->result);
+  double r2 = 0.0;
+  HIPCHK(hipMemcpyAsync(&r2, hd->result, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  *norm = std::sqrt(r2);
+  return last_error();
+}
+
+int residual(hfz_handle* hd, double* norm) {
+  return hd->p.model == HFZ_PFC ? residual_impl<PFC>(hd, norm) : residual_impl<CDFT>(hd, norm);
+}
+
+void vcycle(hfz_handle* hd) {
+  if (hd->p.model == HFZ_PFC)
+    vcycle_rec<PFC>(hd, 0);
+  else
+    vcycle_rec<CDFT>(hd, 0);
+}
+
+// (J * rho) of Eq. discrete_convolution: jrho = IDFT(mult . DFT(rho)) / n^2.
+void convolve(hfz_handle* hd, const double* rho, double* out) {
+  const int n = hd->p.n;
+  const int thr = std::min(256, n / 2);
+  const size_t sh = 2 * (size_t)n * sizeof(double2);
+  const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
+  k_fft_rows_real_fwd<<<n, thr, sh, hd->stream>>>(rho, hd->fa, n);
+  k_transpose<<<tg, tb, 0, hd->stream>>>(hd->fa, hd->fb, n);
+  k_fft_rows_conv<<<n, thr, sh, hd->stream>>>(hd->fb, hd->mult, n);
+  k_transpose<<<tg, tb, 0, hd->stream>>>(hd->fb, hd->fa, n);
+  k_fft_rows_real_inv<<<n, thr, sh, hd->stream>>>(hd->fa, out, n, 1.0 / ((double)n * n));
+}
+
+// CDFT set-up: J on the grid, c_e = h^2 sum J_e, mult = h^2 Re DFT(J) in the
+// transposed spectral layout that `convolve` multiplies in.
+int cdft_setup(hfz_handle* hd) {
+  const int n = hd->p.n;
+  const size_t N2 = (size_t)n * n;
+  const double h = hd->p.h;
+  double* J = reinterpret_cast<double*>(hd->fb);
+  double* Je = J + N2;
+  const Dims d = dims2(n, n);
+  k_kernel_table<<<d.grid, d.block, 0, hd->stream>>>(J, Je, n, ilog2(n), h, hd->p.nu);
+  // deterministic sum of J_e: reuse the energy partial layout via a copy-free pass
+  const int nb = 256;
+  {
+    // sum in fixed order: k_reduce_final over N2 "partials" with nq = 1
+    k_reduce_final<<<1, 1024, 0, hd->stream>>>(Je, (int)N2, 1, h * h, hd->result);
+  }
+  double ce = 0.0;
+  HIPCHK(hipMemcpyAsync(&ce, hd->result, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  const int thr = std::min(256, n / 2);
+  const size_t sh = 2 * (size_t)n * sizeof(double2);
+  const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
+  k_fft_rows_real_fwd<<<n, thr, sh, hd->stream>>>(J, hd->fa, n);
+  k_transpose<<<tg, tb, 0, hd->stream>>>(hd->fa, hd->fb, n);
+  k_fft_rows_fwd<<<n, thr, sh, hd->stream>>>(hd->fb, n);
+  k_real_part<<<(unsigned)((N2 + 255) / 256), 256, 0, hd->stream>>>(hd->fb, hd->mult, N2, h * h);
+  (void)nb;
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  hd->ce = ce;
+  hd->P.ce = ce;
+  return last_error();
+}
+
+void copy_dev(hfz_handle* hd, const double* a, double* b, size_t count) {
+  k_copy<<<(unsigned)((count + 255) / 256), 256, 0, hd->stream>>>(a, b, count);
+}
+
+int begin_step(hfz_handle* hd) {
+  const int n = hd->p.n;
+  const size_t N2 = (size_t)n * n;
+  Lvl<double>& L0 = hd->L[0];
+  const Dims d = dims2(n, n);
+  if (hd->p.model == HFZ_PFC)
+    k_source<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, L0.om, L0.f[0], L0.f[1],
+                                                     L0.f[2], L0.f[3], L0.f[4], n, L0.lg, L0.h, hd->P);
+  else
+    k_source<CDFT><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, hd->jrho, L0.om, L0.f[0],
+                                                      L0.f[1], L0.f[2], nullptr, nullptr, n, L0.lg, L0.h, hd->P);
+  copy_dev(hd, L0.rk, L0.g[0], N2);
+  copy_dev(hd, hd->u, L0.g[1], N2);
+  copy_dev(hd, hd->v, L0.g[2], N2);
+  if (hd->p.model == HFZ_PFC) {
+    copy_dev(hd, hd->mu, L0.g[3], N2);
+    copy_dev(hd, hd->ka, L0.g[4], N2);
+  }
+  for (int l = 1; l < hd->nlev; ++l) {
+    const Dims dc = dims2(hd->L[l].n, hd->L[l].n);
+    k_restrict_coef<double><<<dc.grid, dc.block, 0, hd->stream>>>(hd->L[l - 1].rk, hd->L[l - 1].om,
+                                                                hd->L[l].rk, hd->L[l].om, hd->L[l].n,
+                                                                hd->L[l].lg);
+  }
+  return last_error();
+}
+
+int finish_step(hfz_handle* hd) {
+  const int n = hd->p.n;
+  const size_t N2 = (size_t)n * n;
+  Lvl<double>& L0 = hd->L[0];
+  const Dims d = dims2(n, n);
+  if (hd->p.continuity_fix)
+    k_continuity<<<d.grid, d.block, 0, hd->stream>>>(L0.f[0], L0.rk, L0.g[1], L0.g[2], L0.g[0], n, L0.lg,
+                                                     L0.h, hd->p.s);
+  copy_dev(hd, L0.g[0], L0.rk, N2);
+  copy_dev(hd, L0.g[1], hd->u, N2);
+  copy_dev(hd, L0.g[2], hd->v, N2);
+  if (hd->p.model == HFZ_PFC) {
+    copy_dev(hd, L0.g[3], hd->mu, N2);
+    copy_dev(hd, L0.g[4], hd->ka, N2);
+  } else {
+    convolve(hd, L0.rk, hd->jrho);
+  }
+  return last_error();
+}
+
+int energy_impl(hfz_handle* hd, double* out4) {
+  const int n = hd->p.n;
+  const Lvl<double>& L0 = hd->L[0];
+  const Dims d = dims2(n, n);
+  const int nb = d.grid.x * d.grid.y;
+  if (hd->p.model == HFZ_PFC)
+    k_energy_partial<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, n, L0.lg, L0.h,
+                                                             hd->p.alpha, hd->partial);
+  else
+    k_energy_partial<CDFT><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, hd->jrho, n, L0.lg, L0.h,
+                                                              0.0, hd->partial);
+  k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, nb, 4, L0.h * L0.h, hd->result);
+  HIPCHK(hipMemcpyAsync(out4, hd->result, 4 * sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  return last_error();
+}
+
+double* field_ptr(hfz_handle* hd, int which, int level, int comp) {
+  if (level < 0 || level >= hd->nlev) return nullptr;
+  Lvl<double>& L = hd->L[level];
+  switch (which) {
+    case 0:
+      return (comp >= 0 && comp < hd->nc) ? L.g[comp] : nullptr;
+    case 1:
+      return (comp >= 0 && comp < hd->nc) ? L.f[comp] : nullptr;
+    case 2:
+      return (level > 0 && comp >= 0 && comp < hd->nc) ? L.g0[comp] : nullptr;
+    case 3:
+      return comp == 0 ? L.rk : (comp == 1 ? L.om : nullptr);
+    case 4:
+      return (level == 0 && comp == 0) ? hd->jrho : nullptr;
+    default:
+      return nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int hfz_default_params(int model, hfz_params* p) {
+  if (!p || (model != HFZ_PFC && model != HFZ_CDFT)) return HFZ_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->model = model;
+  p->n = 32;
+  p->h = 0.25;
+  p->s = 0.01;
+  p->gamma = 2.0;
+  p->alpha = 0.975;
+  p->nu = 2.362;
+  p->delta = (model == HFZ_CDFT) ? 1e-10 : 0.0;
+  p->w_damp = 0.5;
+  p->tol = 1e-10;
+  p->nu1 = 2;
+  p->nu2 = 2;
+  p->max_cycles = 200;
+  p->coarsest_n = 4;
+  p->coarse_sweeps = 16;
+  p->precision = HFZ_FP64;
+  p->sigma = 1;
+  p->continuity_fix = 1;
+  return HFZ_OK;
+}
+
+int hfz_workspace_bytes(const hfz_params* p, size_t* bytes) {
+  const int rc = validate(p);
+  if (rc != HFZ_OK) return rc;
+  if (!bytes) return HFZ_EINVAL;
+  *bytes = layout(*p, nullptr, nullptr);
+  return HFZ_OK;
+}
+
+int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, hfz_handle** out) {
+  if (!out) return HFZ_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc != HFZ_OK) return rc;
+  const size_t need = layout(*p, nullptr, nullptr);
+  if (!dev_ws || ws_bytes < need) return HFZ_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return HFZ_EINVAL;
+  hfz_handle* hd = new (std::nothrow) hfz_handle();
+  if (!hd) return HFZ_ENOMEM;
+  hd->p = *p;
+  hd->stream = static_cast<hipStream_t>(hip_stream);
+  layout(*p, dev_ws, hd);
+  hd->P.s = p->s;
+  hd->P.gamma = p->gamma;
+  hd->P.sigma = (double)p->sigma;
+  hd->P.alpha = p->alpha;
+  hd->P.delta = p->delta;
+  hd->P.w = p->w_damp;
+  hd->P.ce = 0.0;
+  if (p->model == HFZ_CDFT) {
+    rc = cdft_setup(hd);
+    if (rc != HFZ_OK) {
+      delete hd;
+      return rc;
+    }
+  }
+  *out = hd;
+  return HFZ_OK;
+}
+
+int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const double* v) {
+  if (!hd || !rho || !u || !v) return HFZ_EINVAL;
+  const int n = hd->p.n;
+  const size_t N2 = (size_t)n * n;
+  Lvl<double>& L0 = hd->L[0];
+  if (hd->p.model == HFZ_CDFT) {
+    k_min_partial<<<256, 256, 0, hd->stream>>>(rho, N2, hd->partial);
+    double mins[256];
+    HIPCHK(hipMemcpyAsync(mins, hd->partial, sizeof(mins), hipMemcpyDeviceToHost, hd->stream));
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    double mn = mins[0];
+    for (double x : mins) mn = std::min(mn, x);
+    if (!(mn > 0.0)) return HFZ_EDOMAIN;
+  }
+  copy_dev(hd, rho, L0.rk, N2);
+  copy_dev(hd, u, hd->u, N2);
+  copy_dev(hd, v, hd->v, N2);
+  const Dims d = dims2(n, n);
+  if (hd->p.model == HFZ_PFC) {
+    k_pfc_kappa<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, n, L0.lg, L0.h);
+    k_pfc_mu<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, hd->mu, n, L0.lg, L0.h, hd->p.alpha);
+  } else {
+    convolve(hd, L0.rk, hd->jrho);
+  }
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  hd->has_state = true;
+  return last_error();
+}
+
+int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v) {
+  if (!hd || !rho || !u || !v) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  const size_t N2 = (size_t)hd->p.n * hd->p.n;
+  copy_dev(hd, hd->L[0].rk, rho, N2);
+  copy_dev(hd, hd->u, u, N2);
+  copy_dev(hd, hd->v, v, N2);
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  return last_error();
+}
+
+int hfz_get_aux(hfz_handle* hd, double* mu, double* kappa) {
+  if (!hd || !mu || !kappa || hd->p.model != HFZ_PFC) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  const size_t N2 = (size_t)hd->p.n * hd->p.n;
+  copy_dev(hd, hd->mu, mu, N2);
+  copy_dev(hd, hd->ka, kappa, N2);
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  return last_error();
+}
+
+int hfz_begin_step(hfz_handle* hd) {
+  if (!hd) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  return begin_step(hd);
+}
+
+int hfz_smooth(hfz_handle* hd, int level, int sweeps) {
+  if (!hd || level < 0 || level >= hd->nlev || sweeps < 0) return HFZ_EINVAL;
+  if (hd->p.model == HFZ_PFC)
+    smooth_level<PFC>(hd, level, sweeps);
+  else
+    smooth_level<CDFT>(hd, level, sweeps);
+  return last_error();
+}
+
+int hfz_vcycle(hfz_handle* hd, int count) {
+  if (!hd || count < 0) return HFZ_EINVAL;
+  for (int k = 0; k < count; ++k) vcycle(hd);
+  return last_error();
+}
+
+int hfz_residual(hfz_handle* hd, double* norm) {
+  if (!hd || !norm) return HFZ_EINVAL;
+  return residual(hd, norm);
+}
+
+int hfz_finish_step(hfz_handle* hd) {
+  if (!hd) return HFZ_EINVAL;
+  return finish_step(hd);
+}
+
+int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
+  if (!hd || nsteps < 0) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  hfz_stats st{};
+  int rc = HFZ_OK;
+  for (int k = 0; k < nsteps; ++k) {
+    rc = begin_step(hd);
+    if (rc != HFZ_OK) break;
+    double r = 0.0;
+    rc = residual(hd, &r);
+    if (rc != HFZ_OK) break;
+    int cycles = 0;
+    while (!(r <= hd->p.tol)) {
+      if (!std::isfinite(r)) {
+        rc = HFZ_ENAN;
+        break;
+      }
+      if (cycles >= hd->p.max_cycles) {
+        rc = HFZ_ENOCONV;
+        break;
+      }
+      vcycle(hd);
+      ++cycles;
+      rc = residual(hd, &r);
+      if (rc != HFZ_OK) break;
+    }
+    st.cycles_last = cycles;
+    st.residual_last = r;
+    if (rc != HFZ_OK) break;
+    rc = finish_step(hd);
+    if (rc != HFZ_OK) break;
+    st.steps_done++;
+    st.cycles_total += cycles;
+  }
+  if (rc == HFZ_OK) {
+    if (hipStreamSynchronize(hd->stream) != hipSuccess) rc = HFZ_EHIP;
+  }
+  if (stats) *stats = st;
+  return rc;
+}
+
+int hfz_energy(hfz_handle* hd, double* out5) {
+  if (!hd || !out5) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  double q[4];
+  const int rc = energy_impl(hd, q);
+  if (rc != HFZ_OK) return rc;
+  const double F = q[1] + q[2];
+  out5[0] = q[0] + F;
+  out5[1] = q[0];
+  out5[2] = F;
+  out5[3] = hd->p.model == HFZ_CDFT ? q[1] : 0.0;
+  out5[4] = hd->p.model == HFZ_CDFT ? q[2] : 0.0;
+  if (!std::isfinite(out5[0])) return HFZ_ENAN;
+  return HFZ_OK;
+}
+
+int hfz_mass(hfz_handle* hd, double* mass) {
+  if (!hd || !mass) return HFZ_EINVAL;
+  if (!hd->has_state) return HFZ_ESTATE;
+  double q[4];
+  const int rc = energy_impl(hd, q);
+  if (rc != HFZ_OK) return rc;
+  *mass = q[3];
+  return HFZ_OK;
+}
+
+int hfz_read_field(hfz_handle* hd, int which, int level, int comp, double* dst) {
+  if (!hd || !dst) return HFZ_EINVAL;
+  double* src = field_ptr(hd, which, level, comp);
+  if (!src) return HFZ_EINVAL;
+  const size_t cnt = (size_t)hd->L[level].n * hd->L[level].n;
+  copy_dev(hd, src, dst, cnt);
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  return last_error();
+}
+
+int hfz_write_field(hfz_handle* hd, int which, int level, int comp, const double* src) {
+  if (!hd || !src) return HFZ_EINVAL;
+  double* dst = field_ptr(hd, which, level, comp);
+  if (!dst) return HFZ_EINVAL;
+  const size_t cnt = (size_t)hd->L[level].n * hd->L[level].n;
+  copy_dev(hd, src, dst, cnt);
+  HIPCHK(hipStreamSynchronize(hd->stream));
+  return last_error();
+}
+
+int hfz_info(hfz_handle* hd, int* levels, double* ce) {
+  if (!hd) return HFZ_EINVAL;
+  if (levels) *levels = hd->nlev;
+  if (ce) *ce = hd->ce;
+  return HFZ_OK;
+}
+
+int hfz_destroy(hfz_handle* hd) {
+  if (!hd) return HFZ_EINVAL;
+  delete hd;
+  return HFZ_OK;
+}
+
+const char* hfz_strerror(int code) {
+  switch (code) {
+    case HFZ_OK:
+      return "ok";
+    case HFZ_EINVAL:
+      return "invalid argument";
+    case HFZ_ENOMEM:
+      return "workspace too small";
+    case HFZ_EDOMAIN:
+      return "density must be positive for the CDFT model";
+    case HFZ_ENOCONV:
+      return "FAS did not reach the tolerance within max_cycles";
+    case HFZ_ENAN:
+      return "non-finite residual or energy";
+    case HFZ_EHIP:
+      return "HIP runtime error";
+    case HFZ_ESTATE:
+      return "no state loaded";
+    default:
+      return "unknown error";
+  }
+}
+
+}  // extern "C"

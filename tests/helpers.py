@@ -1,0 +1,33 @@
+"""Shared test helpers: oracle construction from a workload config, error
+metrics, and the GPU availability switch."""
+import numpy as np
+
+from oracle.fas import Stepper
+
+
+def oracle_stepper(cfg):
+    return Stepper(cfg.model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
+
+
+def rel_err(a, b):
+    """||a - b||_inf / ||b||_inf (b is the oracle)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def state_errors(gpu_state, ora_state):
+    """Per-field relative errors; the two velocity components share the scale
+    max(|u|, |v|) of the oracle."""
+    r, u, v = [np.asarray(x) for x in gpu_state]
+    R, U, V = [np.asarray(x) for x in ora_state]
+    vs = max(np.abs(U).max(), np.abs(V).max(), 1e-300)
+    return (rel_err(r, R), float(np.abs(u - U).max() / vs), float(np.abs(v - V).max() / vs))
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

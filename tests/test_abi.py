@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and its pure host entry points validate parameters."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1503_07416_amd as pkg
+from paper_1503_07416_amd import hfz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "hfz.h")).read()
+    return sorted(set(re.findall(r"\b(hfz_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_header_symbols():
+    lib = hfz.load()
+    names = header_symbols()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hfz.SYMBOLS) == names
+
+
+def test_params_struct_matches_header_order():
+    txt = open(os.path.join(ROOT, "include", "hfz.h")).read()
+    body = txt[txt.index("typedef struct hfz_params"):txt.index("} hfz_params;")]
+    fields = re.findall(r"\b(?:int|double)\s+([a-z_0-9, ]+);", body)
+    names = [f.strip() for grp in fields for f in grp.split(",")]
+    assert names == [f[0] for f in hfz.Params._fields_]
+
+
+def ws(**kw):
+    lib = hfz.load()
+    p = hfz.Params()
+    model = kw.pop("model", 0)
+    assert lib.hfz_default_params(model if model in (0, 1) else 0, ctypes.byref(p)) == 0
+    p.model = model
+    for k, v in kw.items():
+        setattr(p, k, v)
+    nb = ctypes.c_size_t(0)
+    return lib.hfz_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)), nb.value
+
+
+def test_workspace_bytes_and_validation():
+    rc, nb = ws(n=512)
+    assert rc == 0 and nb > 17 * 512 * 512 * 8
+    rc2, nb2 = ws(n=1024)
+    assert rc2 == 0 and 3.5 < nb2 / nb < 4.5
+    rc3, nb3 = ws(model=1, n=1024)
+    assert rc3 == 0
+    for bad in [dict(n=100), dict(n=4), dict(h=0.0), dict(s=-1.0), dict(gamma=0.0),
+                dict(w_damp=1.0), dict(nu1=0, nu2=0), dict(max_cycles=0), dict(coarsest_n=2),
+                dict(coarsest_n=64, n=32), dict(sigma=0), dict(precision=3), dict(tol=0.0),
+                dict(model=1, n=4096), dict(model=7)]:
+        rc, _ = ws(**bad)
+        assert rc == -1, bad
+
+
+def test_strerror():
+    lib = hfz.load()
+    for code in range(-7, 1):
+        assert lib.hfz_strerror(code)
+
+
+def test_simulation_fails_loudly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(Exception):
+        pkg.Simulation(dict(model="pfc", n=32, h=0.25, s=0.01))
