@@ -174,8 +174,12 @@ template <int MODEL> void smooth_level(hfz_handle* hd, int l, int sweeps) {
   const Lvl<double>& L = hd->L[l];
   const Dims d = dims2(L.n / 2, L.n);
   for (int k = 0; k < sweeps; ++k) {
-    for (int colour = 0; colour < 2; ++colour)
-      k_smooth_colour<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
+    for (int colour = 0; colour < 2; ++colour) {
+      if (l == 0)
+        k_smooth_colour<MODEL, double, 1><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
+      else
+        k_smooth_colour<MODEL, double, 0><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
+    }
   }
 }
 

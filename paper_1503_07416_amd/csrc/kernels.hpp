@@ -75,8 +75,10 @@ __global__ void k_restrict_coef(const T* __restrict__ rf, const T* __restrict__ 
 // ---------------------------------------------------------- smoother ------
 // K4: one colour of a damped red-black point-block sweep.  Thread t of row j
 // updates node i = 2 t + ((j + colour) & 1); all its neighbours have the
-// other colour, so the update is a simultaneous one.
-template <int MODEL, typename T>
+// other colour, so the update is a simultaneous one.  FINE = 1 instantiates
+// a separate symbol for the finest level, so profiles report it apart from
+// the coarse levels.
+template <int MODEL, typename T, int FINE>
 __global__ void k_smooth_colour(Lvl<T> L, Phys<T> P, int colour) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
