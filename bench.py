@@ -37,26 +37,27 @@ def parse():
     return ap.parse_args()
 
 
-def smoother_roofline(sim, n, sweeps=50):
-    """Average duration of one finest-level smoother launch (one colour),
-    measured with HIP events on the stream the library launches on."""
+def smoother_roofline(sim, n, launches=25):
+    """Average duration of one finest-level smoother launch (the LDS-tiled
+    kernel doing two damped red-black sweeps, as in the V-cycle's
+    pre-smoothing), measured with HIP events on the stream the library
+    launches on."""
     import torch
     stream = sim.stream
     sim.begin_step()
     sim.smooth(0, 2)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    sim.smooth(0, sweeps)
+    sim.smooth(0, 2 * launches)
     stop.record(stream)
     stop.synchronize()
     ms = start.elapsed_time(stop)
-    launches = 2 * sweeps
     t_launch = ms * 1e-3 / launches
-    bytes_launch = SWEEP_BYTES_PFC * n * n / 2
+    bytes_launch = 2 * SWEEP_BYTES_PFC * n * n
     achieved = bytes_launch / t_launch / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_smooth_colour<PFC,double,FINE>", "launch_us": round(t_launch * 1e6, 3),
+            "kernel": "k_sweeps_tile<PFC,double,2 sweeps>", "launch_us": round(t_launch * 1e6, 3),
             "bytes_per_launch": bytes_launch}
 
 

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -13,12 +15,15 @@
 #include "hfz.h"
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "tail.hpp"
+#include "tile.hpp"
 
 using namespace hfz;
 
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr size_t kTailLdsMax = 160 * 1024;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -95,6 +100,14 @@ struct hfz_handle {
   double* result = nullptr;
   size_t partial_cap = 0;
   Phys<double> P{};
+  int tail_n = 32;  // levels of this size and below run in the one-workgroup tail kernel
+  bool use_graph = true;
+  bool use_tiles = true;  // LDS-tiled kernels on levels >= 32
+  int norm_partials = 0;  // > 0: the last V-cycle's post-sweep left this many residual partials
+  Lvl<double>* level_desc = nullptr;  // device copy of L (read by the tail kernel)
+  int graph_state = 0;  // 0: not built, 1: built, -1: unavailable
+  hipGraphExec_t cycle_exec = nullptr;
+  size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use (0: tail disabled)
 };
 
 namespace {
@@ -115,6 +128,10 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     for (int k = 0; k < nc; ++k) l.f[k] = c.take<double>(cnt);
     if (m != n)
       for (int k = 0; k < nc; ++k) l.g0[k] = c.take<double>(cnt);
+    if (m > p.coarsest_n)
+      for (int k = 0; k < nc; ++k) l.d[k] = c.take<double>(cnt);
+    if (m >= TILE_X && m > p.coarsest_n)
+      for (int k = 0; k < nc; ++k) l.gb[k] = c.take<double>(cnt);
     l.rk = c.take<double>(cnt);
     l.om = c.take<double>(cnt);
     L.push_back(l);
@@ -137,12 +154,16 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
   const size_t pcap = std::max<size_t>(4096, N2 / 64 + 64);
   double* partial = c.take<double>(pcap * 4);
   double* result = c.take<double>(64);
+  Lvl<double>* desc = c.take<Lvl<double>>(L.size());
   if (hd) {
     hd->nc = nc;
     hd->nlev = (int)L.size();
     double h = p.h;
     for (auto& l : L) {
       l.h = h;
+      l.k.c4 = p.s / (4.0 * h);
+      l.k.c2 = p.s / (2.0 * h);
+      l.k.ih2 = 1.0 / (h * h);
       h *= 2.0;
     }
     hd->L = L;
@@ -157,6 +178,7 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     hd->partial = partial;
     hd->result = result;
     hd->partial_cap = pcap;
+    hd->level_desc = desc;
   }
   return c.off;
 }
@@ -183,17 +205,108 @@ template <int MODEL> void smooth_level(hfz_handle* hd, int l, int sweeps) {
   }
 }
 
+// The V-cycle from level l down in one workgroup (levels l .. nlev-1).
+template <int MODEL> void tail_launch(hfz_handle* hd, int l) {
+  TailArgs<double> A{};
+  A.nt = hd->nlev - l;
+  A.Lg = hd->level_desc + l;
+  A.top_n = hd->L[l].n;
+  A.nu1 = hd->p.nu1;
+  A.nu2 = hd->p.nu2;
+  A.coarse_sweeps = hd->p.coarse_sweeps;
+  // as many of the coarsest tail levels in LDS as the opted-in LDS holds
+  A.nlds = 0;
+  for (int k = 1; k <= A.nt; ++k)
+    if (tail_lds_count<NC<MODEL>::value>(hd->L[l].n, A.nt, k) * sizeof(double) <= hd->tail_lds_max) A.nlds = k;
+  const size_t sh = tail_lds_count<NC<MODEL>::value>(hd->L[l].n, A.nt, A.nlds) * sizeof(double);
+  k_tail<MODEL, double><<<1, TAIL_THREADS, sh, hd->stream>>>(A, hd->P);
+}
+
+template <int MODEL> bool tail_fits(const hfz_handle* hd, int l) {
+  return hd->nlev - l <= TAIL_MAX_LEVELS;
+}
+
+// Tiled sweeps of level l: `sweeps` sweeps from *cur into the other buffer
+// and back (two per launch); the first launch applies the coarse-grid
+// correction from level l+1 when pro is set.  On return *cur names the buffer
+// holding the iterate.
+template <int MODEL, int NSW, bool PRO>
+void tile_launch_res(hfz_handle* hd, const Lvl<double>& L, const Fld<double>& in, const Fld<double>& out,
+                     const Lvl<double>& C, int res) {
+  const dim3 grid(L.n / TILE_X, L.n / TILE_Y);
+  if (res == 1)
+    k_sweeps_tile<MODEL, double, NSW, PRO, 1><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
+                                                                                     hd->partial);
+  else if (res == 2)
+    k_sweeps_tile<MODEL, double, NSW, PRO, 2><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
+                                                                                     hd->partial);
+  else
+    k_sweeps_tile<MODEL, double, NSW, PRO, 0><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
+                                                                                     hd->partial);
+}
+
+// Tiled sweeps of level l: `sweeps` sweeps from cur into the other buffer and
+// back (two per launch).  The first launch applies the coarse-grid correction
+// from level l+1 when pro is set; the last launch also computes the residual
+// (res_last: 1 field d, 2 stop-test partial sums).  On return cur names the
+// buffer holding the iterate.
+template <int MODEL> void tiled_sweeps(hfz_handle* hd, int l, int sweeps, bool pro, Fld<double>& cur,
+                                       Fld<double>& other, int res_last = 0) {
+  const Lvl<double>& L = hd->L[l];
+  const Lvl<double>& C = hd->L[std::min(l + 1, hd->nlev - 1)];
+  while (sweeps > 0) {
+    const int nsw = sweeps >= 2 ? 2 : 1;
+    const int res = (sweeps == nsw) ? res_last : 0;
+    if (nsw == 2) {
+      if (pro)
+        tile_launch_res<MODEL, 2, true>(hd, L, cur, other, C, res);
+      else
+        tile_launch_res<MODEL, 2, false>(hd, L, cur, other, C, res);
+    } else {
+      if (pro)
+        tile_launch_res<MODEL, 1, true>(hd, L, cur, other, C, res);
+      else
+        tile_launch_res<MODEL, 1, false>(hd, L, cur, other, C, res);
+    }
+    std::swap(cur, other);
+    sweeps -= nsw;
+    pro = false;
+  }
+}
+
+Fld<double> fld(double* const* p) {
+  Fld<double> f{};
+  for (int c = 0; c < 5; ++c) f.c[c] = p[c];
+  return f;
+}
+
+// One visit of the V-cycle to a large level with the tiled kernels:
+// pre-sweeps, residual, fused FAS restriction, coarser levels, prolongation
+// fused into the first post-sweep, post-sweeps.  The iterate starts and ends
+// in L.g.
+template <int MODEL> void vcycle_tiled(hfz_handle* hd, int l);
+
 template <int MODEL> void vcycle_rec(hfz_handle* hd, int l) {
   const int last = hd->nlev - 1;
+  if (hd->L[l].n <= hd->tail_n && tail_fits<MODEL>(hd, l)) {
+    tail_launch<MODEL>(hd, l);
+    return;
+  }
   if (l == last) {
     smooth_level<MODEL>(hd, l, hd->p.coarse_sweeps);
+    return;
+  }
+  if (hd->use_tiles && hd->L[l].n >= TILE_X && hd->L[l + 1].n >= RTILE) {
+    vcycle_tiled<MODEL>(hd, l);
     return;
   }
   smooth_level<MODEL>(hd, l, hd->p.nu1);
   const Lvl<double>& F = hd->L[l];
   const Lvl<double>& C = hd->L[l + 1];
   const Dims dc = dims2(C.n, C.n);
-  k_fas_restrict<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(F, C, hd->P);
+  const Dims dfr = dims2(F.n, F.n);
+  k_residual_field<MODEL, double><<<dfr.grid, dfr.block, 0, hd->stream>>>(F, hd->P);
+  k_restrict_gd<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(F, C);
   k_fas_rhs<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(C, hd->P);
   vcycle_rec<MODEL>(hd, l + 1);
   const Dims df = dims2(F.n, F.n);
@@ -201,12 +314,56 @@ template <int MODEL> void vcycle_rec(hfz_handle* hd, int l) {
   smooth_level<MODEL>(hd, l, hd->p.nu2);
 }
 
-template <int MODEL> int residual_impl(hfz_handle* hd, double* norm) {
+template <int MODEL> void vcycle_tiled(hfz_handle* hd, int l) {
+  const Lvl<double>& L = hd->L[l];
+  const Lvl<double>& C = hd->L[l + 1];
+  const int nc = hd->nc;
+  const Fld<double> home = fld(L.g);
+  Fld<double> cur = home, other = fld(L.gb);
+  // pre-sweeps; the last one also writes d = f - N(g) for the restriction
+  tiled_sweeps<MODEL>(hd, l, hd->p.nu1, false, cur, other, 1);
+  Lvl<double> F = L;  // descriptor of the current buffer
+  for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
+  if (hd->p.nu1 == 0) {
+    const Dims dfr = dims2(F.n, F.n);
+    k_residual_field<MODEL, double><<<dfr.grid, dfr.block, 0, hd->stream>>>(F, hd->P);
+  }
+  k_restrict_fas_tile<MODEL, double>
+      <<<dim3(C.n / RTILE, C.n / RTILE), RTILE * RTILE, 0, hd->stream>>>(F, C, hd->P);
+  vcycle_rec<MODEL>(hd, l + 1);
+  if (hd->p.nu2 > 0) {
+    // post-sweeps; on the finest level the last one also leaves the partial
+    // sums of the stop-test residual
+    tiled_sweeps<MODEL>(hd, l, hd->p.nu2, true, cur, other, l == 0 ? 2 : 0);
+    if (l == 0) hd->norm_partials = (L.n / TILE_X) * (L.n / TILE_Y);
+  } else {
+    const Dims df = dims2(F.n, F.n);
+    k_prolong<MODEL, double><<<df.grid, df.block, 0, hd->stream>>>(F, C, hd->P);
+  }
+  if (cur.c[0] != home.c[0]) {
+    const size_t cnt = (size_t)L.n * L.n;
+    for (int c = 0; c < nc; ++c)
+      k_copy<<<(unsigned)((cnt + 255) / 256), 256, 0, hd->stream>>>(cur.c[c], home.c[c], cnt);
+  }
+}
+
+// Enqueues h^2 sum (f - N(g))^2 on level 0 into result[0].
+template <int MODEL> void residual_launch_t(hfz_handle* hd) {
   const Lvl<double>& L = hd->L[0];
   const Dims d = dims2(L.n, L.n);
   const int nb = d.grid.x * d.grid.y;
   k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, hd->partial);
   k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, nb, 1, L.h * L.h, hd->result);
+}
+
+void residual_launch(hfz_handle* hd) {
+  if (hd->p.model == HFZ_PFC)
+    residual_launch_t<PFC>(hd);
+  else
+    residual_launch_t<CDFT>(hd);
+}
+
+int residual_read(hfz_handle* hd, double* norm) {
   double r2 = 0.0;
   HIPCHK(hipMemcpyAsync(&r2, hd->result, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
   HIPCHK(hipStreamSynchronize(hd->stream));
@@ -215,14 +372,65 @@ template <int MODEL> int residual_impl(hfz_handle* hd, double* norm) {
 }
 
 int residual(hfz_handle* hd, double* norm) {
-  return hd->p.model == HFZ_PFC ? residual_impl<PFC>(hd, norm) : residual_impl<CDFT>(hd, norm);
+  residual_launch(hd);
+  return residual_read(hd, norm);
 }
 
 void vcycle(hfz_handle* hd) {
+  hd->norm_partials = 0;
   if (hd->p.model == HFZ_PFC)
     vcycle_rec<PFC>(hd, 0);
   else
     vcycle_rec<CDFT>(hd, 0);
+}
+
+// A V-cycle and the stop-test residual norm after it (the last post-sweep
+// may already have left the partial sums).
+void vcycle_and_norm(hfz_handle* hd) {
+  vcycle(hd);
+  if (hd->norm_partials > 0)
+    k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, hd->norm_partials, 1, hd->L[0].h * hd->L[0].h,
+                                               hd->result);
+  else
+    residual_launch(hd);
+}
+
+// One V-cycle followed by the residual norm, captured once into a HIP graph
+// (on a private stream: capture records, it does not execute) and replayed on
+// the caller's stream.  Returns false when graphs are unavailable; callers
+// then launch the kernels one by one.
+bool cycle_graph(hfz_handle* hd) {
+  if (hd->graph_state == 1) return true;
+  if (hd->graph_state < 0) return false;
+  hipStream_t cap = nullptr;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+  if (ok) {
+    hipStream_t user = hd->stream;
+    hd->stream = cap;
+    ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      vcycle_and_norm(hd);
+      ok = hipStreamEndCapture(cap, &g) == hipSuccess;
+    }
+    hd->stream = user;
+  }
+  if (ok) ok = hipGraphInstantiate(&hd->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cap) (void)hipStreamDestroy(cap);
+  (void)hipGetLastError();
+  hd->graph_state = ok ? 1 : -1;
+  return ok;
+}
+
+// One V-cycle and the residual norm that follows it.
+int cycle_and_residual(hfz_handle* hd, double* norm) {
+  if (hd->use_graph && cycle_graph(hd)) {
+    if (hipGraphLaunch(hd->cycle_exec, hd->stream) != hipSuccess) return HFZ_EHIP;
+  } else {
+    vcycle_and_norm(hd);
+  }
+  return residual_read(hd, norm);
 }
 
 // (J * rho) of Eq. discrete_convolution: jrho = IDFT(mult . DFT(rho)) / n^2.
@@ -378,7 +586,7 @@ int hfz_default_params(int model, hfz_params* p) {
   p->nu2 = 2;
   p->max_cycles = 200;
   p->coarsest_n = 4;
-  p->coarse_sweeps = 16;
+  p->coarse_sweeps = 4;
   p->precision = HFZ_FP64;
   p->sigma = 1;
   p->continuity_fix = 1;
@@ -406,6 +614,12 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->p = *p;
   hd->stream = static_cast<hipStream_t>(hip_stream);
   layout(*p, dev_ws, hd);
+  if (hipMemcpyAsync(hd->level_desc, hd->L.data(), hd->L.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
+                     hd->stream) != hipSuccess ||
+      hipStreamSynchronize(hd->stream) != hipSuccess) {
+    delete hd;
+    return HFZ_EHIP;
+  }
   hd->P.s = p->s;
   hd->P.gamma = p->gamma;
   hd->P.sigma = (double)p->sigma;
@@ -413,6 +627,35 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->P.delta = p->delta;
   hd->P.w = p->w_damp;
   hd->P.ce = 0.0;
+  // opt in to the large LDS of a gfx950 CU for the tail and FFT kernels
+  {
+    const void* tk = (p->model == HFZ_PFC) ? reinterpret_cast<const void*>(&k_tail<PFC, double>)
+                                           : reinterpret_cast<const void*>(&k_tail<CDFT, double>);
+    int dev = 0, optin = 0;
+    hipFuncAttributes fa{};
+    size_t static_lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+      optin = 0;
+    if (hipFuncGetAttributes(&fa, tk) == hipSuccess) static_lds = fa.sharedSizeBytes;
+    const size_t want = std::min<size_t>(kTailLdsMax, optin > 0 ? (size_t)optin : 65536) - static_lds - 256;
+    for (size_t lim : {want, (size_t)65536 - static_lds - 256}) {
+      if (hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) == hipSuccess) {
+        hd->tail_lds_max = lim;
+        break;
+      }
+    }
+    (void)hipGetLastError();
+  }
+  if (const char* e = std::getenv("HFZ_TAIL_N")) {
+    const int t = std::atoi(e);
+    if (t == 0 || is_pow2(t)) hd->tail_n = t;
+  }
+  if (const char* e = std::getenv("HFZ_GRAPH")) hd->use_graph = std::atoi(e) != 0;
+  if (const char* e = std::getenv("HFZ_TILES")) hd->use_tiles = std::atoi(e) != 0;
+  if (std::getenv("HFZ_VERBOSE"))
+    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d\n", p->n, hd->nlev,
+                 hd->tail_n, hd->tail_lds_max, (int)hd->use_graph);
   if (p->model == HFZ_CDFT) {
     rc = cdft_setup(hd);
     if (rc != HFZ_OK) {
@@ -482,10 +725,24 @@ int hfz_begin_step(hfz_handle* hd) {
 
 int hfz_smooth(hfz_handle* hd, int level, int sweeps) {
   if (!hd || level < 0 || level >= hd->nlev || sweeps < 0) return HFZ_EINVAL;
-  if (hd->p.model == HFZ_PFC)
+  if (hd->use_tiles && hd->L[level].gb[0] != nullptr) {
+    // the sweeps the V-cycle runs on this level (tiled, double-buffered)
+    const Lvl<double>& L = hd->L[level];
+    const Fld<double> home = fld(L.g);
+    Fld<double> cur = home, other = fld(L.gb);
+    if (hd->p.model == HFZ_PFC)
+      tiled_sweeps<PFC>(hd, level, sweeps, false, cur, other);
+    else
+      tiled_sweeps<CDFT>(hd, level, sweeps, false, cur, other);
+    if (cur.c[0] != home.c[0]) {
+      const size_t cnt = (size_t)L.n * L.n;
+      for (int c = 0; c < hd->nc; ++c) copy_dev(hd, cur.c[c], home.c[c], cnt);
+    }
+  } else if (hd->p.model == HFZ_PFC) {
     smooth_level<PFC>(hd, level, sweeps);
-  else
+  } else {
     smooth_level<CDFT>(hd, level, sweeps);
+  }
   return last_error();
 }
 
@@ -526,9 +783,8 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
         rc = HFZ_ENOCONV;
         break;
       }
-      vcycle(hd);
       ++cycles;
-      rc = residual(hd, &r);
+      rc = cycle_and_residual(hd, &r);
       if (rc != HFZ_OK) break;
     }
     st.cycles_last = cycles;
@@ -601,6 +857,7 @@ int hfz_info(hfz_handle* hd, int* levels, double* ce) {
 
 int hfz_destroy(hfz_handle* hd) {
   if (!hd) return HFZ_EINVAL;
+  if (hd->cycle_exec) (void)hipGraphExecDestroy(hd->cycle_exec);
   delete hd;
   return HFZ_OK;
 }

@@ -87,7 +87,7 @@ __global__ void k_smooth_colour(Lvl<T> L, Phys<T> P, int colour) {
   const int i = 2 * t + ((j + colour) & 1);
   const Nbr q = nbr(i, j, n, L.lg);
   T out[NC<MODEL>::value];
-  block_update<MODEL, T>(L.g, L.f, L.rk, L.om, q, L.h, P, out);
+  block_update<MODEL, T>(L.g, L.f, L.rk, L.om, q, q.p, L.k, P, out);
 #pragma unroll
   for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][q.p] = out[c];
 }
@@ -111,7 +111,7 @@ __global__ void k_fas_restrict(Lvl<T> F, Lvl<T> C, Phys<T> P) {
       const int fi = (2 * I + di) & m, fj = (2 * J + dj) & m;
       const Nbr q = nbr(fi, fj, F.n, F.lg);
       T nv[NCm];
-      rows_N<MODEL, T>(F.g, F.rk, F.om, q, F.h, P, nv);
+      rows_N<MODEL, T>(F.g, F.rk, F.om, q, q.p, F.k, P, nv);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) {
         accg[c] += wgt * F.g[c][q.p];
@@ -128,6 +128,38 @@ __global__ void k_fas_restrict(Lvl<T> F, Lvl<T> C, Phys<T> P) {
   }
 }
 
+// K6a, split form for large levels: d = f - N(g) on the fine grid (one row
+// evaluation per node) ...
+template <int MODEL, typename T>
+__global__ void k_residual_field(Lvl<T> F, Phys<T> P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= F.n || j >= F.n) return;
+  constexpr int NCm = NC<MODEL>::value;
+  const Nbr q = nbr(i, j, F.n, F.lg);
+  T nv[NCm];
+  rows_N<MODEL, T>(F.g, F.rk, F.om, q, q.p, F.k, P, nv);
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) F.d[c][q.p] = F.f[c][q.p] - nv[c];
+}
+
+// ... then g_c = g0_c = R g and f_c = R d on the coarse grid.
+template <int MODEL, typename T>
+__global__ void k_restrict_gd(Lvl<T> F, Lvl<T> C) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= C.n || J >= C.n) return;
+  constexpr int NCm = NC<MODEL>::value;
+  const int pc = (J << C.lg) + I;
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) {
+    const T gr = fw9(F.g[c], 2 * I, 2 * J, F.n, F.lg);
+    C.g[c][pc] = gr;
+    C.g0[c][pc] = gr;
+    C.f[c][pc] = fw9(F.d[c], 2 * I, 2 * J, F.n, F.lg);
+  }
+}
+
 // K6b: f_c += N_c(R g), the FAS coarse right-hand side.
 template <int MODEL, typename T>
 __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
@@ -137,7 +169,7 @@ __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
   constexpr int NCm = NC<MODEL>::value;
   const Nbr q = nbr(I, J, C.n, C.lg);
   T nv[NCm];
-  rows_N<MODEL, T>(C.g0, C.rk, C.om, q, C.h, P, nv);
+  rows_N<MODEL, T>(C.g0, C.rk, C.om, q, q.p, C.k, P, nv);
 #pragma unroll
   for (int c = 0; c < NCm; ++c) C.f[c][q.p] += nv[c];
 }
@@ -206,7 +238,7 @@ __global__ void k_residual_partial(Lvl<T> L, Phys<T> P, double* __restrict__ par
     constexpr int NCm = NC<MODEL>::value;
     const Nbr q = nbr(i, j, L.n, L.lg);
     T nv[NCm];
-    rows_N<MODEL, T>(L.g, L.rk, L.om, q, L.h, P, nv);
+    rows_N<MODEL, T>(L.g, L.rk, L.om, q, q.p, L.k, P, nv);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) {
       const double d = double(L.f[c][q.p]) - double(nv[c]);

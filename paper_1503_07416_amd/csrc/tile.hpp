@@ -1,0 +1,203 @@
+// LDS-tiled kernels for the large grid levels.
+//
+// k_sweeps_tile: NSW damped red-black sweeps in one launch.  A workgroup owns a
+// TILE_X x TILE_Y block of nodes and loads it with a halo of 2 NSW nodes (the
+// iterate g and the frozen rho^k into LDS).  Each half sweep updates the
+// nodes of one colour in a box that shrinks by one node per half sweep, so
+// after 2 NSW half sweeps the owned block holds exactly the values the
+// whole-grid sweeps produce; the halo work is recomputed, not exchanged.  The
+// iterate is double-buffered in global memory (read gin, write gout) so that
+// no workgroup reads a neighbour's halo after that neighbour wrote it.  With
+// PRO the FAS coarse-grid correction g += P(g_c - R g) is applied to every
+// node as it is loaded (the prolongation fused into the first post-sweep).
+//
+// k_restrict_fas_tile: the FAS coarse problem of one level in one launch:
+// R g on a coarse tile plus a one-node halo (into LDS), then
+// f_c = N_c(R g) + R d with d = f - N(g) precomputed on the fine grid.
+#pragma once
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace hfz {
+
+constexpr int TILE_X = 32;
+constexpr int TILE_Y = 16;
+constexpr int TILE_THREADS = 256;
+constexpr int RTILE = 16;  // coarse tile edge of the restriction kernel
+
+template <typename T> struct Fld {
+  T* c[5];
+};
+
+// RES selects what follows the sweeps on the owned block: 0 nothing, 1 the
+// residual d = f - N(g) written to L.d (the input of the FAS restriction),
+// 2 the block's partial sum of |d|^2 written to partial[block] (the stop test).
+// A residual needs the swept values one node beyond the block, hence the
+// extra halo node.
+template <int MODEL, typename T, int NSW, bool PRO, int RES>
+__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
+                                                              Phys<T> P, double* partial) {
+  constexpr int NCm = NC<MODEL>::value;
+  constexpr int H = 2 * NSW + (RES ? 1 : 0);
+  constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
+  // coarse patch under the region (prolongation staging)
+  constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2, CRN = CRX * CRY;
+  __shared__ T sg[NCm][RN];
+  __shared__ T srk[RN];
+  __shared__ T se[PRO ? NCm : 1][PRO ? CRN : 1];
+  const int m = L.n - 1, lg = L.lg;
+  // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
+  const int x0 = (int)blockIdx.x * TILE_X - H, y0 = (int)blockIdx.y * TILE_Y - H;
+  const int X0c = x0 >> 1, Y0c = y0 >> 1;  // floor halves (arithmetic shift)
+  if constexpr (PRO) {
+    const int mc = C.n - 1;
+    for (int w = threadIdx.x; w < CRN; w += TILE_THREADS) {
+      const int cy = w / CRX, cx = w - cy * CRX;
+      const int pc = (((Y0c + cy) & mc) << C.lg) + ((X0c + cx) & mc);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) se[c][w] = C.g[c][pc] - C.g0[c][pc];
+    }
+    __syncthreads();
+  }
+  for (int w = threadIdx.x; w < RN; w += TILE_THREADS) {
+    const int ly = w / RX, lx = w - ly * RX;
+    const int gi = (x0 + lx) & m, gj = (y0 + ly) & m;
+    const int gp = (gj << lg) + gi;
+    srk[w] = L.rk[gp];
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) {
+      T x = gin.c[c][gp];
+      if constexpr (PRO) {
+        // bilinear prolongation of e (same arithmetic as k_prolong)
+        const int gu = x0 + lx, gv = y0 + ly;
+        const int cp = ((gv >> 1) - Y0c) * CRX + ((gu >> 1) - X0c);
+        const int pi = gu & 1, pj = gv & 1;
+        const T e00 = se[c][cp];
+        T e;
+        if (!pi && !pj)
+          e = e00;
+        else if (pi && !pj)
+          e = T(0.5) * (e00 + se[c][cp + 1]);
+        else if (!pi && pj)
+          e = T(0.5) * (e00 + se[c][cp + CRX]);
+        else
+          e = T(0.25) * (e00 + se[c][cp + 1] + se[c][cp + CRX] + se[c][cp + CRX + 1]);
+        x += e;
+        if constexpr (MODEL == CDFT) {
+          if (c == 0) x = fsqrt(x * x + P.delta * P.delta);
+        }
+      }
+      sg[c][w] = x;
+    }
+  }
+  __syncthreads();
+  const T* gl[NCm];
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
+  for (int k = 1; k <= 2 * NSW; ++k) {
+    const int colour = (k - 1) & 1;
+    const int half = (RX - 2 * k) >> 1, cnt = half * (RY - 2 * k);
+    for (int w = threadIdx.x; w < cnt; w += TILE_THREADS) {
+      const int r = w / half, t = w - r * half;
+      const int ly = k + r;
+      const int lx = k + 2 * t + ((k + ly + colour) & 1);
+      Nbr q;
+      q.p = ly * RX + lx;
+      q.e = q.p + 1;
+      q.w = q.p - 1;
+      q.n = q.p + RX;
+      q.s = q.p - RX;
+      const int pf = (((y0 + ly) & m) << lg) + ((x0 + lx) & m);
+      T out[NCm];
+      block_update<MODEL, T>(gl, L.f, srk, L.om, q, pf, L.k, P, out);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
+    }
+    __syncthreads();
+  }
+  double acc = 0.0;
+  for (int w = threadIdx.x; w < TILE_X * TILE_Y; w += TILE_THREADS) {
+    const int ty = w / TILE_X, tx = w - ty * TILE_X;
+    const int lp = (ty + H) * RX + tx + H;
+    const int gp = (((y0 + H + ty) & m) << lg) + ((x0 + H + tx) & m);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) gout.c[c][gp] = sg[c][lp];
+    if constexpr (RES != 0) {
+      Nbr q;
+      q.p = lp;
+      q.e = lp + 1;
+      q.w = lp - 1;
+      q.n = lp + RX;
+      q.s = lp - RX;
+      T nv[NCm];
+      rows_N<MODEL, T>(gl, srk, L.om, q, gp, L.k, P, nv);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        const T d = L.f[c][gp] - nv[c];
+        if constexpr (RES == 1) {
+          L.d[c][gp] = d;
+        } else {
+          acc += double(d) * double(d);
+        }
+      }
+    }
+  }
+  if constexpr (RES == 2) {
+    __shared__ double red[TILE_THREADS / 64];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
+  const int m = n - 1;
+  const int ie = (i + 1) & m, iw = (i - 1) & m;
+  const int rc = j << lg, rn = ((j + 1) & m) << lg, rs = ((j - 1) & m) << lg;
+  return (T(4) * f[rc + i] + T(2) * (f[rc + ie] + f[rc + iw] + f[rn + i] + f[rs + i]) +
+          (f[rn + ie] + f[rn + iw] + f[rs + ie] + f[rs + iw])) *
+         T(0.0625);
+}
+
+// F.g must point at the current fine iterate and F.d at f - N(g) of it.
+template <int MODEL, typename T>
+__global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  constexpr int NCm = NC<MODEL>::value;
+  constexpr int RX = RTILE + 2, RN = RX * RX;
+  __shared__ T sg[NCm][RN];
+  __shared__ T srk[RN];
+  const int mc = C.n - 1;
+  const int X0 = (int)blockIdx.x * RTILE - 1, Y0 = (int)blockIdx.y * RTILE - 1;
+  for (int w = threadIdx.x; w < RN; w += RTILE * RTILE) {
+    const int ly = w / RX, lx = w - ly * RX;
+    const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
+    srk[w] = C.rk[(J << C.lg) + I];
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) sg[c][w] = fw9g(F.g[c], 2 * I, 2 * J, F.n, F.lg);
+  }
+  __syncthreads();
+  const T* gl[NCm];
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
+  const int ty = threadIdx.x / RTILE, tx = threadIdx.x - ty * RTILE;
+  const int ly = ty + 1, lx = tx + 1;
+  const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
+  const int pc = (J << C.lg) + I;
+  Nbr q;
+  q.p = ly * RX + lx;
+  q.e = q.p + 1;
+  q.w = q.p - 1;
+  q.n = q.p + RX;
+  q.s = q.p - RX;
+  T nv[NCm];
+  rows_N<MODEL, T>(gl, srk, C.om, q, pc, C.k, P, nv);
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) {
+    const T gr = sg[c][q.p];
+    C.g[c][pc] = gr;
+    C.g0[c][pc] = gr;
+    C.f[c][pc] = fw9g(F.d[c], 2 * I, 2 * J, F.n, F.lg) + nv[c];
+  }
+}
+
+}  // namespace hfz

@@ -36,6 +36,7 @@ def cdft_small(seed=0, n=64):
 
 
 CASES = {"pfc": pfc_small, "cdft": cdft_small}
+SIZES = [("pfc", 32), ("pfc", 128), ("cdft", 64), ("cdft", 128)]
 
 
 @pytest.mark.parametrize("model", ["pfc", "cdft"])
@@ -60,9 +61,10 @@ def test_source_and_coefficients(model):
     assert sim.levels() == len(sol.levels)
 
 
-@pytest.mark.parametrize("model", ["pfc", "cdft"])
-def test_one_sweep_and_residual(model):
-    cfg, rho, u, v = CASES[model]()
+@pytest.mark.parametrize("model,n", SIZES)
+def test_one_sweep_and_residual(model, n):
+    """One and two sweeps on the finest level (the LDS-tiled kernel from 32^2 up)."""
+    cfg, rho, u, v = CASES[model](n=n)
     sim = sim_for(cfg, rho, u, v)
     ora = oracle_stepper(cfg)
     ora.set_state(rho, u, v)
@@ -78,11 +80,16 @@ def test_one_sweep_and_residual(model):
         assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
     r1 = fas.resnorm(g, S, sol.levels[0])
     assert abs(sim.residual() - r1) < 1e-11 * r1
+    sim.smooth(0, 2)
+    smoother.sweep(g, S, sol.levels[0], cfg.w)
+    smoother.sweep(g, S, sol.levels[0], cfg.w)
+    for c in range(g.shape[0]):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
 
 
-@pytest.mark.parametrize("model", ["pfc", "cdft"])
-def test_vcycles(model):
-    cfg, rho, u, v = CASES[model]()
+@pytest.mark.parametrize("model,n", SIZES)
+def test_vcycles(model, n):
+    cfg, rho, u, v = CASES[model](n=n)
     sim = sim_for(cfg, rho, u, v)
     ora = oracle_stepper(cfg)
     ora.set_state(rho, u, v)

@@ -49,7 +49,7 @@ class Config:
     nu2: int = 2
     max_cycles: int = 200
     coarsest_n: int = 4
-    coarse_sweeps: int = 16
+    coarse_sweeps: int = 4
     sigma: float = 1.0
     continuity_fix: bool = True
     precision: str = "fp64"    # "fp64" or "mixed"
