@@ -1,0 +1,198 @@
+// Host-side FAS V-cycle driver: enqueues one V(nu1, nu2) cycle over a level
+// hierarchy.  Large levels use the LDS-tiled kernels (tile.hpp), the small
+// levels at the bottom the one-workgroup tail kernel (tail.hpp); the plain
+// per-level kernels (kernels.hpp) remain for configurations the tiled ones do
+// not cover (full form only).  The same driver runs the FP64 solve
+// (T = double, full form) and the FP32 inner solve of the mixed-precision
+// step (T = float, correction form).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tail.hpp"
+#include "tile.hpp"
+
+namespace hfz {
+
+template <typename T> struct Hier {
+  std::vector<Lvl<T>> L;    // finest first
+  Lvl<T>* desc = nullptr;   // device copy of L (the tail kernel reads it)
+  size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use
+  Phys<T> P{};
+};
+
+struct Cycle {
+  hipStream_t stream = nullptr;
+  int nu1 = 2, nu2 = 2, coarse_sweeps = 4;
+  int tail_n = 32;
+  bool use_tiles = true;
+  double* partial = nullptr;  // stop-test partial sums of the finest level
+  int norm_partials = 0;      // out: > 0 when the last post-sweep left that many partials
+};
+
+inline dim3 grid2(int nx, int ny, dim3 b) { return dim3((nx + b.x - 1) / b.x, (ny + b.y - 1) / b.y); }
+inline dim3 block2(int nx, int ny) {
+  const int bx = std::min(64, nx);
+  return dim3(bx, std::max(1, std::min(256 / bx, ny)));
+}
+
+template <typename T> Fld<T> fld(T* const* p) {
+  Fld<T> f{};
+  for (int c = 0; c < 5; ++c) f.c[c] = p[c];
+  return f;
+}
+
+// Damped red-black sweeps with the per-colour kernels (full form).
+template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, int sweeps) {
+  const Lvl<T>& L = H.L[l];
+  const dim3 b = block2(L.n / 2, L.n), g = grid2(L.n / 2, L.n, b);
+  for (int k = 0; k < sweeps; ++k) {
+    for (int colour = 0; colour < 2; ++colour) {
+      if (l == 0)
+        k_smooth_colour<MODEL, T, 1><<<g, b, 0, K.stream>>>(L, H.P, colour);
+      else
+        k_smooth_colour<MODEL, T, 0><<<g, b, 0, K.stream>>>(L, H.P, colour);
+    }
+  }
+}
+
+template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l) {
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
+  TailArgs<T> A{};
+  A.nt = (int)H.L.size() - l;
+  A.Lg = H.desc + l;
+  A.top_n = H.L[l].n;
+  A.nu1 = K.nu1;
+  A.nu2 = K.nu2;
+  A.coarse_sweeps = K.coarse_sweeps;
+  // as many of the coarsest tail levels in LDS as the opted-in LDS holds
+  A.nlds = 0;
+  for (int k = 1; k <= A.nt; ++k)
+    if (tail_lds_count<NCm, NB>(A.top_n, A.nt, k) * sizeof(T) <= H.tail_lds_max) A.nlds = k;
+  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.nlds) * sizeof(T);
+  k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
+}
+
+template <int MODEL, typename T, bool CORR, int NSW, bool PRO>
+void tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out, const Lvl<T>& C,
+                 int res) {
+  const dim3 grid(L.n / TILE_X, L.n / TILE_Y);
+  if (res == 1)
+    k_sweeps_tile<MODEL, T, NSW, PRO, 1, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+  else if (res == 2)
+    k_sweeps_tile<MODEL, T, NSW, PRO, 2, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+  else
+    k_sweeps_tile<MODEL, T, NSW, PRO, 0, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+}
+
+// `sweeps` tiled sweeps of level l from cur into the other buffer and back
+// (two per launch).  The first launch applies the coarse-grid correction from
+// level l+1 when pro is set; the last launch also computes the residual
+// (res_last: 1 the field d, 2 stop-test partial sums).  On return cur names
+// the buffer holding the iterate.
+template <int MODEL, typename T, bool CORR>
+void tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur, Fld<T>& other,
+                  int res_last = 0) {
+  const Lvl<T>& L = H.L[l];
+  const Lvl<T>& C = H.L[std::min<size_t>(l + 1, H.L.size() - 1)];
+  while (sweeps > 0) {
+    const int nsw = sweeps >= 2 ? 2 : 1;
+    const int res = (sweeps == nsw) ? res_last : 0;
+    if (nsw == 2) {
+      if (pro)
+        tile_launch<MODEL, T, CORR, 2, true>(H, K, L, cur, other, C, res);
+      else
+        tile_launch<MODEL, T, CORR, 2, false>(H, K, L, cur, other, C, res);
+    } else {
+      if (pro)
+        tile_launch<MODEL, T, CORR, 1, true>(H, K, L, cur, other, C, res);
+      else
+        tile_launch<MODEL, T, CORR, 1, false>(H, K, L, cur, other, C, res);
+    }
+    std::swap(cur, other);
+    sweeps -= nsw;
+    pro = false;
+  }
+}
+
+template <typename T> void copy_fields(Cycle& K, const Fld<T>& a, const Fld<T>& b, int nc, size_t cnt) {
+  for (int c = 0; c < nc; ++c)
+    k_copy_t<T><<<(unsigned)((cnt + 255) / 256), 256, 0, K.stream>>>(a.c[c], b.c[c], cnt);
+}
+
+template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l);
+
+// One visit to a large level with the tiled kernels: pre-sweeps (the last also
+// writes d = f - N(g)), the fused FAS restriction, the coarser levels, the
+// prolongation fused into the first post-sweep, post-sweeps.  The iterate
+// starts and ends in L.g.
+template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle& K, int l) {
+  constexpr int NCm = NC<MODEL>::value;
+  const Lvl<T>& L = H.L[l];
+  const Lvl<T>& C = H.L[l + 1];
+  const Fld<T> home = fld<T>(L.g);
+  Fld<T> cur = home, other = fld<T>(L.gb);
+  tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 1);
+  Lvl<T> F = L;  // descriptor of the buffer holding the iterate
+  for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
+  if (K.nu1 == 0) {
+    if constexpr (!CORR) {
+      const dim3 b = block2(F.n, F.n);
+      k_residual_field<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.P);
+    }
+  }
+  k_restrict_fas_tile<MODEL, T, CORR><<<dim3(C.n / RTILE, C.n / RTILE), RTILE * RTILE, 0, K.stream>>>(F, C, H.P);
+  vcycle_rec<MODEL, T, CORR>(H, K, l + 1);
+  if (K.nu2 > 0) {
+    // post-sweeps; on the finest level of the FP64 solve the last one also
+    // leaves the partial sums of the stop-test residual
+    const bool norm = (l == 0 && !CORR);
+    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
+    if (norm) K.norm_partials = (L.n / TILE_X) * (L.n / TILE_Y);
+  } else {
+    if constexpr (!CORR) {
+      const dim3 b = block2(F.n, F.n);
+      k_prolong<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, C, H.P);
+    }
+  }
+  if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.n);
+}
+
+template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l) {
+  const int nlev = (int)H.L.size(), last = nlev - 1;
+  if (H.L[l].n <= K.tail_n && nlev - l <= TAIL_MAX_LEVELS) {
+    tail_launch<MODEL, T, CORR>(H, K, l);
+    return;
+  }
+  if (K.use_tiles && l < last && H.L[l].n >= TILE_X && H.L[l + 1].n >= RTILE) {
+    vcycle_tiled<MODEL, T, CORR>(H, K, l);
+    return;
+  }
+  if constexpr (!CORR) {
+    if (l == last) {
+      smooth_level<MODEL, T>(H, K, l, K.coarse_sweeps);
+      return;
+    }
+    smooth_level<MODEL, T>(H, K, l, K.nu1);
+    const Lvl<T>& F = H.L[l];
+    const Lvl<T>& C = H.L[l + 1];
+    const dim3 bc = block2(C.n, C.n), bf = block2(F.n, F.n);
+    k_residual_field<MODEL, T><<<grid2(F.n, F.n, bf), bf, 0, K.stream>>>(F, H.P);
+    k_restrict_gd<MODEL, T><<<grid2(C.n, C.n, bc), bc, 0, K.stream>>>(F, C);
+    k_fas_rhs<MODEL, T><<<grid2(C.n, C.n, bc), bc, 0, K.stream>>>(C, H.P);
+    vcycle_rec<MODEL, T, CORR>(H, K, l + 1);
+    k_prolong<MODEL, T><<<grid2(F.n, F.n, bf), bf, 0, K.stream>>>(F, C, H.P);
+    smooth_level<MODEL, T>(H, K, l, K.nu2);
+  }
+}
+
+// One V-cycle from the finest level.
+template <int MODEL, typename T, bool CORR> void vcycle(Hier<T>& H, Cycle& K) {
+  K.norm_partials = 0;
+  vcycle_rec<MODEL, T, CORR>(H, K, 0);
+}
+
+}  // namespace hfz

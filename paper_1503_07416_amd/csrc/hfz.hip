@@ -15,8 +15,7 @@
 #include "hfz.h"
 #include "fft.hpp"
 #include "kernels.hpp"
-#include "tail.hpp"
-#include "tile.hpp"
+#include "driver.hpp"
 
 using namespace hfz;
 
@@ -84,8 +83,8 @@ struct hfz_handle {
   int nc = 0;
   double ce = 0.0;
   bool has_state = false;
-  std::vector<Lvl<double>> L;
-  // state (rho^k is L[0].rk)
+  Hier<double> H;   // FP64 hierarchy (H.L[0].rk is the state rho^k)
+  Hier<float> H32;  // FP32 correction hierarchy of the mixed-precision step
   double* u = nullptr;
   double* v = nullptr;
   double* mu = nullptr;
@@ -99,15 +98,14 @@ struct hfz_handle {
   double* partial = nullptr;
   double* result = nullptr;
   size_t partial_cap = 0;
-  Phys<double> P{};
   int tail_n = 32;  // levels of this size and below run in the one-workgroup tail kernel
   bool use_graph = true;
   bool use_tiles = true;  // LDS-tiled kernels on levels >= 32
   int norm_partials = 0;  // > 0: the last V-cycle's post-sweep left this many residual partials
-  Lvl<double>* level_desc = nullptr;  // device copy of L (read by the tail kernel)
   int graph_state = 0;  // 0: not built, 1: built, -1: unavailable
   hipGraphExec_t cycle_exec = nullptr;
-  size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use (0: tail disabled)
+  int mp_graph_state = 0;  // the same for the mixed-precision outer iteration
+  hipGraphExec_t mp_exec = nullptr;
 };
 
 namespace {
@@ -166,7 +164,7 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
       l.k.ih2 = 1.0 / (h * h);
       h *= 2.0;
     }
-    hd->L = L;
+    hd->H.L = L;
     hd->u = u;
     hd->v = v;
     hd->mu = mu;
@@ -178,7 +176,42 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     hd->partial = partial;
     hd->result = result;
     hd->partial_cap = pcap;
-    hd->level_desc = desc;
+    hd->H.desc = desc;
+  }
+  if (p.precision == HFZ_MIXED) {
+    // FP32 correction hierarchy: e (the iterate), f, R e, d, the second sweep
+    // buffer, FP32 copies of rho^k and omega^k, and the base state (rho, u, v)
+    std::vector<Lvl<float>> E;
+    for (int m = n; m >= p.coarsest_n; m >>= 1) {
+      Lvl<float> l{};
+      l.n = m;
+      l.lg = ilog2(m);
+      const size_t cnt = (size_t)m * m;
+      for (int k = 0; k < nc; ++k) l.g[k] = c.take<float>(cnt);
+      for (int k = 0; k < nc; ++k) l.f[k] = c.take<float>(cnt);
+      for (int k = 0; k < nc; ++k) l.g0[k] = c.take<float>(cnt);
+      if (m > p.coarsest_n)
+        for (int k = 0; k < nc; ++k) l.d[k] = c.take<float>(cnt);
+      if (m >= TILE_X && m > p.coarsest_n)
+        for (int k = 0; k < nc; ++k) l.gb[k] = c.take<float>(cnt);
+      l.rk = c.take<float>(cnt);
+      l.om = c.take<float>(cnt);
+      for (int k = 0; k < 3; ++k) l.bg[k] = c.take<float>(cnt);
+      E.push_back(l);
+    }
+    Lvl<float>* desc32 = c.take<Lvl<float>>(E.size());
+    if (hd) {
+      double h = p.h;
+      for (auto& l : E) {
+        l.h = (float)h;
+        l.k.c4 = (float)(p.s / (4.0 * h));
+        l.k.c2 = (float)(p.s / (2.0 * h));
+        l.k.ih2 = (float)(1.0 / (h * h));
+        h *= 2.0;
+      }
+      hd->H32.L = E;
+      hd->H32.desc = desc32;
+    }
   }
   return c.off;
 }
@@ -190,169 +223,48 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
 
 int last_error() { return hipGetLastError() == hipSuccess ? HFZ_OK : HFZ_EHIP; }
 
-// ---- launch helpers -------------------------------------------------------
-
-template <int MODEL> void smooth_level(hfz_handle* hd, int l, int sweeps) {
-  const Lvl<double>& L = hd->L[l];
-  const Dims d = dims2(L.n / 2, L.n);
-  for (int k = 0; k < sweeps; ++k) {
-    for (int colour = 0; colour < 2; ++colour) {
-      if (l == 0)
-        k_smooth_colour<MODEL, double, 1><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
-      else
-        k_smooth_colour<MODEL, double, 0><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
+// Raises a kernel's dynamic LDS limit to what a gfx950 CU offers (minus the
+// kernel's static LDS); returns the limit in force.
+size_t lds_optin(const void* kernel) {
+  int dev = 0, optin = 0;
+  hipFuncAttributes fa{};
+  size_t static_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+    optin = 0;
+  if (hipFuncGetAttributes(&fa, kernel) == hipSuccess) static_lds = fa.sharedSizeBytes;
+  const size_t want = std::min<size_t>(kTailLdsMax, optin > 0 ? (size_t)optin : 65536) - static_lds - 256;
+  size_t got = 0;
+  for (size_t lim : {want, (size_t)65536 - static_lds - 256}) {
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) == hipSuccess) {
+      got = lim;
+      break;
     }
   }
+  (void)hipGetLastError();
+  return got;
 }
 
-// The V-cycle from level l down in one workgroup (levels l .. nlev-1).
-template <int MODEL> void tail_launch(hfz_handle* hd, int l) {
-  TailArgs<double> A{};
-  A.nt = hd->nlev - l;
-  A.Lg = hd->level_desc + l;
-  A.top_n = hd->L[l].n;
-  A.nu1 = hd->p.nu1;
-  A.nu2 = hd->p.nu2;
-  A.coarse_sweeps = hd->p.coarse_sweeps;
-  // as many of the coarsest tail levels in LDS as the opted-in LDS holds
-  A.nlds = 0;
-  for (int k = 1; k <= A.nt; ++k)
-    if (tail_lds_count<NC<MODEL>::value>(hd->L[l].n, A.nt, k) * sizeof(double) <= hd->tail_lds_max) A.nlds = k;
-  const size_t sh = tail_lds_count<NC<MODEL>::value>(hd->L[l].n, A.nt, A.nlds) * sizeof(double);
-  k_tail<MODEL, double><<<1, TAIL_THREADS, sh, hd->stream>>>(A, hd->P);
-}
+// ---- V-cycle entry points (driver.hpp) -------------------------------------
 
-template <int MODEL> bool tail_fits(const hfz_handle* hd, int l) {
-  return hd->nlev - l <= TAIL_MAX_LEVELS;
-}
-
-// Tiled sweeps of level l: `sweeps` sweeps from *cur into the other buffer
-// and back (two per launch); the first launch applies the coarse-grid
-// correction from level l+1 when pro is set.  On return *cur names the buffer
-// holding the iterate.
-template <int MODEL, int NSW, bool PRO>
-void tile_launch_res(hfz_handle* hd, const Lvl<double>& L, const Fld<double>& in, const Fld<double>& out,
-                     const Lvl<double>& C, int res) {
-  const dim3 grid(L.n / TILE_X, L.n / TILE_Y);
-  if (res == 1)
-    k_sweeps_tile<MODEL, double, NSW, PRO, 1><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
-                                                                                     hd->partial);
-  else if (res == 2)
-    k_sweeps_tile<MODEL, double, NSW, PRO, 2><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
-                                                                                     hd->partial);
-  else
-    k_sweeps_tile<MODEL, double, NSW, PRO, 0><<<grid, TILE_THREADS, 0, hd->stream>>>(L, in, out, C, hd->P,
-                                                                                     hd->partial);
-}
-
-// Tiled sweeps of level l: `sweeps` sweeps from cur into the other buffer and
-// back (two per launch).  The first launch applies the coarse-grid correction
-// from level l+1 when pro is set; the last launch also computes the residual
-// (res_last: 1 field d, 2 stop-test partial sums).  On return cur names the
-// buffer holding the iterate.
-template <int MODEL> void tiled_sweeps(hfz_handle* hd, int l, int sweeps, bool pro, Fld<double>& cur,
-                                       Fld<double>& other, int res_last = 0) {
-  const Lvl<double>& L = hd->L[l];
-  const Lvl<double>& C = hd->L[std::min(l + 1, hd->nlev - 1)];
-  while (sweeps > 0) {
-    const int nsw = sweeps >= 2 ? 2 : 1;
-    const int res = (sweeps == nsw) ? res_last : 0;
-    if (nsw == 2) {
-      if (pro)
-        tile_launch_res<MODEL, 2, true>(hd, L, cur, other, C, res);
-      else
-        tile_launch_res<MODEL, 2, false>(hd, L, cur, other, C, res);
-    } else {
-      if (pro)
-        tile_launch_res<MODEL, 1, true>(hd, L, cur, other, C, res);
-      else
-        tile_launch_res<MODEL, 1, false>(hd, L, cur, other, C, res);
-    }
-    std::swap(cur, other);
-    sweeps -= nsw;
-    pro = false;
-  }
-}
-
-Fld<double> fld(double* const* p) {
-  Fld<double> f{};
-  for (int c = 0; c < 5; ++c) f.c[c] = p[c];
-  return f;
-}
-
-// One visit of the V-cycle to a large level with the tiled kernels:
-// pre-sweeps, residual, fused FAS restriction, coarser levels, prolongation
-// fused into the first post-sweep, post-sweeps.  The iterate starts and ends
-// in L.g.
-template <int MODEL> void vcycle_tiled(hfz_handle* hd, int l);
-
-template <int MODEL> void vcycle_rec(hfz_handle* hd, int l) {
-  const int last = hd->nlev - 1;
-  if (hd->L[l].n <= hd->tail_n && tail_fits<MODEL>(hd, l)) {
-    tail_launch<MODEL>(hd, l);
-    return;
-  }
-  if (l == last) {
-    smooth_level<MODEL>(hd, l, hd->p.coarse_sweeps);
-    return;
-  }
-  if (hd->use_tiles && hd->L[l].n >= TILE_X && hd->L[l + 1].n >= RTILE) {
-    vcycle_tiled<MODEL>(hd, l);
-    return;
-  }
-  smooth_level<MODEL>(hd, l, hd->p.nu1);
-  const Lvl<double>& F = hd->L[l];
-  const Lvl<double>& C = hd->L[l + 1];
-  const Dims dc = dims2(C.n, C.n);
-  const Dims dfr = dims2(F.n, F.n);
-  k_residual_field<MODEL, double><<<dfr.grid, dfr.block, 0, hd->stream>>>(F, hd->P);
-  k_restrict_gd<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(F, C);
-  k_fas_rhs<MODEL, double><<<dc.grid, dc.block, 0, hd->stream>>>(C, hd->P);
-  vcycle_rec<MODEL>(hd, l + 1);
-  const Dims df = dims2(F.n, F.n);
-  k_prolong<MODEL, double><<<df.grid, df.block, 0, hd->stream>>>(F, C, hd->P);
-  smooth_level<MODEL>(hd, l, hd->p.nu2);
-}
-
-template <int MODEL> void vcycle_tiled(hfz_handle* hd, int l) {
-  const Lvl<double>& L = hd->L[l];
-  const Lvl<double>& C = hd->L[l + 1];
-  const int nc = hd->nc;
-  const Fld<double> home = fld(L.g);
-  Fld<double> cur = home, other = fld(L.gb);
-  // pre-sweeps; the last one also writes d = f - N(g) for the restriction
-  tiled_sweeps<MODEL>(hd, l, hd->p.nu1, false, cur, other, 1);
-  Lvl<double> F = L;  // descriptor of the current buffer
-  for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
-  if (hd->p.nu1 == 0) {
-    const Dims dfr = dims2(F.n, F.n);
-    k_residual_field<MODEL, double><<<dfr.grid, dfr.block, 0, hd->stream>>>(F, hd->P);
-  }
-  k_restrict_fas_tile<MODEL, double>
-      <<<dim3(C.n / RTILE, C.n / RTILE), RTILE * RTILE, 0, hd->stream>>>(F, C, hd->P);
-  vcycle_rec<MODEL>(hd, l + 1);
-  if (hd->p.nu2 > 0) {
-    // post-sweeps; on the finest level the last one also leaves the partial
-    // sums of the stop-test residual
-    tiled_sweeps<MODEL>(hd, l, hd->p.nu2, true, cur, other, l == 0 ? 2 : 0);
-    if (l == 0) hd->norm_partials = (L.n / TILE_X) * (L.n / TILE_Y);
-  } else {
-    const Dims df = dims2(F.n, F.n);
-    k_prolong<MODEL, double><<<df.grid, df.block, 0, hd->stream>>>(F, C, hd->P);
-  }
-  if (cur.c[0] != home.c[0]) {
-    const size_t cnt = (size_t)L.n * L.n;
-    for (int c = 0; c < nc; ++c)
-      k_copy<<<(unsigned)((cnt + 255) / 256), 256, 0, hd->stream>>>(cur.c[c], home.c[c], cnt);
-  }
+Cycle cycle_ctx(hfz_handle* hd) {
+  Cycle K;
+  K.stream = hd->stream;
+  K.nu1 = hd->p.nu1;
+  K.nu2 = hd->p.nu2;
+  K.coarse_sweeps = hd->p.coarse_sweeps;
+  K.tail_n = hd->tail_n;
+  K.use_tiles = hd->use_tiles;
+  K.partial = hd->partial;
+  return K;
 }
 
 // Enqueues h^2 sum (f - N(g))^2 on level 0 into result[0].
 template <int MODEL> void residual_launch_t(hfz_handle* hd) {
-  const Lvl<double>& L = hd->L[0];
+  const Lvl<double>& L = hd->H.L[0];
   const Dims d = dims2(L.n, L.n);
   const int nb = d.grid.x * d.grid.y;
-  k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, hd->partial);
+  k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->H.P, hd->partial);
   k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, nb, 1, L.h * L.h, hd->result);
 }
 
@@ -377,11 +289,12 @@ int residual(hfz_handle* hd, double* norm) {
 }
 
 void vcycle(hfz_handle* hd) {
-  hd->norm_partials = 0;
+  Cycle K = cycle_ctx(hd);
   if (hd->p.model == HFZ_PFC)
-    vcycle_rec<PFC>(hd, 0);
+    hfz::vcycle<PFC, double, false>(hd->H, K);
   else
-    vcycle_rec<CDFT>(hd, 0);
+    hfz::vcycle<CDFT, double, false>(hd->H, K);
+  hd->norm_partials = K.norm_partials;
 }
 
 // A V-cycle and the stop-test residual norm after it (the last post-sweep
@@ -389,7 +302,7 @@ void vcycle(hfz_handle* hd) {
 void vcycle_and_norm(hfz_handle* hd) {
   vcycle(hd);
   if (hd->norm_partials > 0)
-    k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, hd->norm_partials, 1, hd->L[0].h * hd->L[0].h,
+    k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, hd->norm_partials, 1, hd->H.L[0].h * hd->H.L[0].h,
                                                hd->result);
   else
     residual_launch(hd);
@@ -429,6 +342,79 @@ int cycle_and_residual(hfz_handle* hd, double* norm) {
     if (hipGraphLaunch(hd->cycle_exec, hd->stream) != hipSuccess) return HFZ_EHIP;
   } else {
     vcycle_and_norm(hd);
+  }
+  return residual_read(hd, norm);
+}
+
+// ---- mixed precision: FP32 correction V-cycles inside FP64 defect correction
+
+// FP32 copies of the frozen coefficients of every level (once per step).
+void mp_begin(hfz_handle* hd) {
+  for (int l = 0; l < hd->nlev; ++l) {
+    const size_t cnt = (size_t)hd->H.L[l].n * hd->H.L[l].n;
+    const unsigned nb = (unsigned)((cnt + 255) / 256);
+    k_cast<<<nb, 256, 0, hd->stream>>>(hd->H.L[l].rk, hd->H32.L[l].rk, cnt);
+    k_cast<<<nb, 256, 0, hd->stream>>>(hd->H.L[l].om, hd->H32.L[l].om, cnt);
+  }
+}
+
+// d = S - N(g) in FP64 -> inner right-hand side, base state, e = 0, and the
+// outer stop-test norm into result[0].
+void mp_prepare_launch(hfz_handle* hd) {
+  const Lvl<double>& L = hd->H.L[0];
+  const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
+  if (hd->p.model == HFZ_PFC)
+    k_mp_prepare<PFC><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
+  else
+    k_mp_prepare<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
+  k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, (int)(g.x * g.y), 1, L.h * L.h, hd->result);
+}
+
+// One outer iteration: an FP32 V-cycle on the correction problem, g += e,
+// and the next outer residual.
+void mp_cycle(hfz_handle* hd) {
+  Cycle K = cycle_ctx(hd);
+  const Lvl<double>& L = hd->H.L[0];
+  const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
+  if (hd->p.model == HFZ_PFC) {
+    hfz::vcycle<PFC, float, true>(hd->H32, K);
+    k_mp_update<PFC><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
+  } else {
+    hfz::vcycle<CDFT, float, true>(hd->H32, K);
+    k_mp_update<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
+  }
+  mp_prepare_launch(hd);
+}
+
+bool mp_graph(hfz_handle* hd) {
+  if (hd->mp_graph_state == 1) return true;
+  if (hd->mp_graph_state < 0) return false;
+  hipStream_t cap = nullptr;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+  if (ok) {
+    hipStream_t user = hd->stream;
+    hd->stream = cap;
+    ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      mp_cycle(hd);
+      ok = hipStreamEndCapture(cap, &g) == hipSuccess;
+    }
+    hd->stream = user;
+  }
+  if (ok) ok = hipGraphInstantiate(&hd->mp_exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cap) (void)hipStreamDestroy(cap);
+  (void)hipGetLastError();
+  hd->mp_graph_state = ok ? 1 : -1;
+  return ok;
+}
+
+int mp_cycle_and_residual(hfz_handle* hd, double* norm) {
+  if (hd->use_graph && mp_graph(hd)) {
+    if (hipGraphLaunch(hd->mp_exec, hd->stream) != hipSuccess) return HFZ_EHIP;
+  } else {
+    mp_cycle(hd);
   }
   return residual_read(hd, norm);
 }
@@ -474,7 +460,8 @@ int cdft_setup(hfz_handle* hd) {
   (void)nb;
   HIPCHK(hipStreamSynchronize(hd->stream));
   hd->ce = ce;
-  hd->P.ce = ce;
+  hd->H.P.ce = ce;
+  hd->H32.P.ce = (float)ce;
   return last_error();
 }
 
@@ -485,14 +472,14 @@ void copy_dev(hfz_handle* hd, const double* a, double* b, size_t count) {
 int begin_step(hfz_handle* hd) {
   const int n = hd->p.n;
   const size_t N2 = (size_t)n * n;
-  Lvl<double>& L0 = hd->L[0];
+  Lvl<double>& L0 = hd->H.L[0];
   const Dims d = dims2(n, n);
   if (hd->p.model == HFZ_PFC)
     k_source<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, L0.om, L0.f[0], L0.f[1],
-                                                     L0.f[2], L0.f[3], L0.f[4], n, L0.lg, L0.h, hd->P);
+                                                     L0.f[2], L0.f[3], L0.f[4], n, L0.lg, L0.h, hd->H.P);
   else
     k_source<CDFT><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, hd->jrho, L0.om, L0.f[0],
-                                                      L0.f[1], L0.f[2], nullptr, nullptr, n, L0.lg, L0.h, hd->P);
+                                                      L0.f[1], L0.f[2], nullptr, nullptr, n, L0.lg, L0.h, hd->H.P);
   copy_dev(hd, L0.rk, L0.g[0], N2);
   copy_dev(hd, hd->u, L0.g[1], N2);
   copy_dev(hd, hd->v, L0.g[2], N2);
@@ -501,10 +488,10 @@ int begin_step(hfz_handle* hd) {
     copy_dev(hd, hd->ka, L0.g[4], N2);
   }
   for (int l = 1; l < hd->nlev; ++l) {
-    const Dims dc = dims2(hd->L[l].n, hd->L[l].n);
-    k_restrict_coef<double><<<dc.grid, dc.block, 0, hd->stream>>>(hd->L[l - 1].rk, hd->L[l - 1].om,
-                                                                hd->L[l].rk, hd->L[l].om, hd->L[l].n,
-                                                                hd->L[l].lg);
+    const Dims dc = dims2(hd->H.L[l].n, hd->H.L[l].n);
+    k_restrict_coef<double><<<dc.grid, dc.block, 0, hd->stream>>>(hd->H.L[l - 1].rk, hd->H.L[l - 1].om,
+                                                                hd->H.L[l].rk, hd->H.L[l].om, hd->H.L[l].n,
+                                                                hd->H.L[l].lg);
   }
   return last_error();
 }
@@ -512,7 +499,7 @@ int begin_step(hfz_handle* hd) {
 int finish_step(hfz_handle* hd) {
   const int n = hd->p.n;
   const size_t N2 = (size_t)n * n;
-  Lvl<double>& L0 = hd->L[0];
+  Lvl<double>& L0 = hd->H.L[0];
   const Dims d = dims2(n, n);
   if (hd->p.continuity_fix)
     k_continuity<<<d.grid, d.block, 0, hd->stream>>>(L0.f[0], L0.rk, L0.g[1], L0.g[2], L0.g[0], n, L0.lg,
@@ -531,7 +518,7 @@ int finish_step(hfz_handle* hd) {
 
 int energy_impl(hfz_handle* hd, double* out4) {
   const int n = hd->p.n;
-  const Lvl<double>& L0 = hd->L[0];
+  const Lvl<double>& L0 = hd->H.L[0];
   const Dims d = dims2(n, n);
   const int nb = d.grid.x * d.grid.y;
   if (hd->p.model == HFZ_PFC)
@@ -548,7 +535,7 @@ int energy_impl(hfz_handle* hd, double* out4) {
 
 double* field_ptr(hfz_handle* hd, int which, int level, int comp) {
   if (level < 0 || level >= hd->nlev) return nullptr;
-  Lvl<double>& L = hd->L[level];
+  Lvl<double>& L = hd->H.L[level];
   switch (which) {
     case 0:
       return (comp >= 0 && comp < hd->nc) ? L.g[comp] : nullptr;
@@ -614,38 +601,36 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->p = *p;
   hd->stream = static_cast<hipStream_t>(hip_stream);
   layout(*p, dev_ws, hd);
-  if (hipMemcpyAsync(hd->level_desc, hd->L.data(), hd->L.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
-                     hd->stream) != hipSuccess ||
-      hipStreamSynchronize(hd->stream) != hipSuccess) {
+  bool ok = hipMemcpyAsync(hd->H.desc, hd->H.L.data(), hd->H.L.size() * sizeof(Lvl<double>),
+                           hipMemcpyHostToDevice, hd->stream) == hipSuccess;
+  if (ok && p->precision == HFZ_MIXED)
+    ok = hipMemcpyAsync(hd->H32.desc, hd->H32.L.data(), hd->H32.L.size() * sizeof(Lvl<float>),
+                        hipMemcpyHostToDevice, hd->stream) == hipSuccess;
+  if (!ok || hipStreamSynchronize(hd->stream) != hipSuccess) {
     delete hd;
     return HFZ_EHIP;
   }
-  hd->P.s = p->s;
-  hd->P.gamma = p->gamma;
-  hd->P.sigma = (double)p->sigma;
-  hd->P.alpha = p->alpha;
-  hd->P.delta = p->delta;
-  hd->P.w = p->w_damp;
-  hd->P.ce = 0.0;
-  // opt in to the large LDS of a gfx950 CU for the tail and FFT kernels
-  {
-    const void* tk = (p->model == HFZ_PFC) ? reinterpret_cast<const void*>(&k_tail<PFC, double>)
-                                           : reinterpret_cast<const void*>(&k_tail<CDFT, double>);
-    int dev = 0, optin = 0;
-    hipFuncAttributes fa{};
-    size_t static_lds = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
-      optin = 0;
-    if (hipFuncGetAttributes(&fa, tk) == hipSuccess) static_lds = fa.sharedSizeBytes;
-    const size_t want = std::min<size_t>(kTailLdsMax, optin > 0 ? (size_t)optin : 65536) - static_lds - 256;
-    for (size_t lim : {want, (size_t)65536 - static_lds - 256}) {
-      if (hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) == hipSuccess) {
-        hd->tail_lds_max = lim;
-        break;
-      }
-    }
-    (void)hipGetLastError();
+  hd->H.P.s = p->s;
+  hd->H.P.gamma = p->gamma;
+  hd->H.P.sigma = (double)p->sigma;
+  hd->H.P.alpha = p->alpha;
+  hd->H.P.delta = p->delta;
+  hd->H.P.w = p->w_damp;
+  hd->H.P.ce = 0.0;
+  hd->H32.P.s = (float)p->s;
+  hd->H32.P.gamma = (float)p->gamma;
+  hd->H32.P.sigma = (float)p->sigma;
+  hd->H32.P.alpha = (float)p->alpha;
+  hd->H32.P.delta = (float)p->delta;
+  hd->H32.P.w = (float)p->w_damp;
+  hd->H32.P.ce = 0.0f;
+  // opt in to the large LDS of a gfx950 CU for the tail kernels
+  if (p->model == HFZ_PFC) {
+    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<PFC, double, false>));
+    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<PFC, float, true>));
+  } else {
+    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<CDFT, double, false>));
+    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<CDFT, float, true>));
   }
   if (const char* e = std::getenv("HFZ_TAIL_N")) {
     const int t = std::atoi(e);
@@ -653,9 +638,15 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   }
   if (const char* e = std::getenv("HFZ_GRAPH")) hd->use_graph = std::atoi(e) != 0;
   if (const char* e = std::getenv("HFZ_TILES")) hd->use_tiles = std::atoi(e) != 0;
+  if (p->precision == HFZ_MIXED) {
+    // the correction-form inner solve runs only on the tiled and tail kernels:
+    // every level above the tail must be tileable (>= 32 with a >= 16 coarse)
+    hd->use_tiles = true;
+    if (hd->tail_n < 16) hd->tail_n = 32;
+  }
   if (std::getenv("HFZ_VERBOSE"))
     std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d\n", p->n, hd->nlev,
-                 hd->tail_n, hd->tail_lds_max, (int)hd->use_graph);
+                 hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
   if (p->model == HFZ_CDFT) {
     rc = cdft_setup(hd);
     if (rc != HFZ_OK) {
@@ -671,7 +662,7 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
   if (!hd || !rho || !u || !v) return HFZ_EINVAL;
   const int n = hd->p.n;
   const size_t N2 = (size_t)n * n;
-  Lvl<double>& L0 = hd->L[0];
+  Lvl<double>& L0 = hd->H.L[0];
   if (hd->p.model == HFZ_CDFT) {
     k_min_partial<<<256, 256, 0, hd->stream>>>(rho, N2, hd->partial);
     double mins[256];
@@ -700,7 +691,7 @@ int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v) {
   if (!hd || !rho || !u || !v) return HFZ_EINVAL;
   if (!hd->has_state) return HFZ_ESTATE;
   const size_t N2 = (size_t)hd->p.n * hd->p.n;
-  copy_dev(hd, hd->L[0].rk, rho, N2);
+  copy_dev(hd, hd->H.L[0].rk, rho, N2);
   copy_dev(hd, hd->u, u, N2);
   copy_dev(hd, hd->v, v, N2);
   HIPCHK(hipStreamSynchronize(hd->stream));
@@ -725,23 +716,21 @@ int hfz_begin_step(hfz_handle* hd) {
 
 int hfz_smooth(hfz_handle* hd, int level, int sweeps) {
   if (!hd || level < 0 || level >= hd->nlev || sweeps < 0) return HFZ_EINVAL;
-  if (hd->use_tiles && hd->L[level].gb[0] != nullptr) {
+  Cycle K = cycle_ctx(hd);
+  if (hd->use_tiles && hd->H.L[level].gb[0] != nullptr) {
     // the sweeps the V-cycle runs on this level (tiled, double-buffered)
-    const Lvl<double>& L = hd->L[level];
-    const Fld<double> home = fld(L.g);
-    Fld<double> cur = home, other = fld(L.gb);
+    const Lvl<double>& L = hd->H.L[level];
+    const Fld<double> home = fld<double>(L.g);
+    Fld<double> cur = home, other = fld<double>(L.gb);
     if (hd->p.model == HFZ_PFC)
-      tiled_sweeps<PFC>(hd, level, sweeps, false, cur, other);
+      tiled_sweeps<PFC, double, false>(hd->H, K, level, sweeps, false, cur, other);
     else
-      tiled_sweeps<CDFT>(hd, level, sweeps, false, cur, other);
-    if (cur.c[0] != home.c[0]) {
-      const size_t cnt = (size_t)L.n * L.n;
-      for (int c = 0; c < hd->nc; ++c) copy_dev(hd, cur.c[c], home.c[c], cnt);
-    }
+      tiled_sweeps<CDFT, double, false>(hd->H, K, level, sweeps, false, cur, other);
+    if (cur.c[0] != home.c[0]) copy_fields<double>(K, cur, home, hd->nc, (size_t)L.n * L.n);
   } else if (hd->p.model == HFZ_PFC) {
-    smooth_level<PFC>(hd, level, sweeps);
+    smooth_level<PFC, double>(hd->H, K, level, sweeps);
   } else {
-    smooth_level<CDFT>(hd, level, sweeps);
+    smooth_level<CDFT, double>(hd->H, K, level, sweeps);
   }
   return last_error();
 }
@@ -770,8 +759,15 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
   for (int k = 0; k < nsteps; ++k) {
     rc = begin_step(hd);
     if (rc != HFZ_OK) break;
+    const bool mixed = hd->p.precision == HFZ_MIXED;
     double r = 0.0;
-    rc = residual(hd, &r);
+    if (mixed) {
+      mp_begin(hd);
+      mp_prepare_launch(hd);
+      rc = residual_read(hd, &r);
+    } else {
+      rc = residual(hd, &r);
+    }
     if (rc != HFZ_OK) break;
     int cycles = 0;
     while (!(r <= hd->p.tol)) {
@@ -784,7 +780,7 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
         break;
       }
       ++cycles;
-      rc = cycle_and_residual(hd, &r);
+      rc = mixed ? mp_cycle_and_residual(hd, &r) : cycle_and_residual(hd, &r);
       if (rc != HFZ_OK) break;
     }
     st.cycles_last = cycles;
@@ -832,7 +828,7 @@ int hfz_read_field(hfz_handle* hd, int which, int level, int comp, double* dst) 
   if (!hd || !dst) return HFZ_EINVAL;
   double* src = field_ptr(hd, which, level, comp);
   if (!src) return HFZ_EINVAL;
-  const size_t cnt = (size_t)hd->L[level].n * hd->L[level].n;
+  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].n;
   copy_dev(hd, src, dst, cnt);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
@@ -842,7 +838,7 @@ int hfz_write_field(hfz_handle* hd, int which, int level, int comp, const double
   if (!hd || !src) return HFZ_EINVAL;
   double* dst = field_ptr(hd, which, level, comp);
   if (!dst) return HFZ_EINVAL;
-  const size_t cnt = (size_t)hd->L[level].n * hd->L[level].n;
+  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].n;
   copy_dev(hd, src, dst, cnt);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
@@ -858,6 +854,7 @@ int hfz_info(hfz_handle* hd, int* levels, double* ce) {
 int hfz_destroy(hfz_handle* hd) {
   if (!hd) return HFZ_EINVAL;
   if (hd->cycle_exec) (void)hipGraphExecDestroy(hd->cycle_exec);
+  if (hd->mp_exec) (void)hipGraphExecDestroy(hd->mp_exec);
   delete hd;
   return HFZ_OK;
 }

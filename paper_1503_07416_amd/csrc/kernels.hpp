@@ -281,6 +281,58 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
   if (t < count) b[t] = a[t];
 }
 
+template <typename T>
+__global__ void k_copy_t(const T* __restrict__ a, T* __restrict__ b, size_t count) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) b[t] = a[t];
+}
+
+__global__ void k_cast(const double* __restrict__ a, float* __restrict__ b, size_t count) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) b[t] = (float)a[t];
+}
+
+// ------------------------------------------- mixed precision, outer loop --
+// Before each inner FP32 V-cycle: d = S - N(g) in FP64 on the finest level
+// becomes the inner right-hand side (FP32), the current FP64 iterate's
+// (rho, u, v) the inner base state, the inner correction starts at 0; the
+// per-block partial sums of |d|^2 are the outer stop test.
+template <int MODEL>
+__global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double* __restrict__ partial) {
+  __shared__ double lds[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  double acc = 0.0;
+  if (i < L.n && j < L.n) {
+    constexpr int NCm = NC<MODEL>::value;
+    const Nbr q = nbr(i, j, L.n, L.lg);
+    double nv[NCm];
+    rows_N<MODEL, double>(L.g, L.rk, L.om, q, q.p, L.k, P, nv);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) {
+      const double d = L.f[c][q.p] - nv[c];
+      acc += d * d;
+      E.f[c][q.p] = (float)d;
+      E.g[c][q.p] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
+  }
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+}
+
+// After the inner V-cycle: g += e (the FP32 correction added in FP64).
+template <int MODEL>
+__global__ void k_mp_update(Lvl<double> L, Lvl<float> E) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const int p = (j << L.lg) + i;
+#pragma unroll
+  for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][p] += (double)E.g[c][p];
+}
+
 // K9: per-block partials of (KE, F part 1, F part 2, mass, min rho) before the
 // h^2 factor.  PFC: part 1 = phi^4/12 + alpha phi^2/2 + (Delta_h rho)^2/2 +
 // rho Delta_h rho, part 2 = 0.  CDFT: part 1 = rho (ln rho - 1) (F_id),

@@ -36,6 +36,7 @@ template <typename T> struct Lvl {
   T* gb[5];   // second buffer of the iterate (double-buffered tiled sweeps)
   T* rk;      // frozen rho^k
   T* om;      // frozen omega^k
+  T* bg[3];   // correction form only: base state (rho, u, v) the correction is taken about
   int n;      // grid size n_l
   int lg;     // log2 n_l
   T h;        // spacing h_l
@@ -153,6 +154,160 @@ __device__ __forceinline__ void block_update(const T* const* g, const T* const* 
                  (ka[q.e] + ka[q.w] + ka[q.n] + ka[q.s]) * ih2 - T(4) * kh * ih2;
     out[3] = w1 * mh + w * mu[q.p];
     out[4] = w1 * kh + w * ka[q.p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Correction form (the inner FP32 solve of the mixed-precision step).
+//
+// With the outer FP64 iterate g held fixed as the base b = (rho_b, u_b, v_b),
+// the inner unknown is the correction e and the inner operator is
+//   N_d(e) = N(b + e) - N(b),
+// written so that every term is formed from e directly (no difference of two
+// nearly equal FP32 numbers): the linear rows are N's own rows applied to e;
+// the nonlinear pieces are
+//   |u|^2:  (u_b + e_u)^2 - u_b^2 = e_u (2 u_b + e_u)   (and v)
+//   PFC cubic: c(e) = ((phi_b + e)^3 - phi_b^3)/3 = e (phi_b^2 + phi_b e + e^2/3)
+//   CDFT potential: ln((rho_b + e)/rho_b) + 2 c_e e = log1p(e/rho_b) + 2 c_e e.
+// N_d(e) = d with d = S - N(b) has the root e = g* - b.  The smoother is the
+// block solve of the rows above, the cubic linearised about the current
+// correction e_l, c(e) ~ c(e_l) + (phi_b + e_l)^2 (e - e_l) (the same
+// linearisation as the full form), damped like the full form.
+
+__device__ __forceinline__ float flog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double flog1p(double x) { return log1p(x); }
+
+template <int MODEL, typename T>
+__device__ __forceinline__ T potential_d(const T* const* e, const T* const* b, int q, const Phys<T>& P) {
+  if constexpr (MODEL == PFC) {
+    return e[3][q];
+  } else {
+    const T x = e[0][q];
+    return flog1p(x / b[0][q]) + T(2) * P.ce * x;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T dq(const T* const* e, const T* const* b, int q) {
+  const T eu = e[1][q], ev = e[2][q];
+  return eu * (T(2) * b[1][q] + eu) + ev * (T(2) * b[2][q] + ev);
+}
+
+template <int MODEL, typename T>
+__device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, const T* rk, const T* om,
+                                        const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out) {
+  const T s = P.s;
+  const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
+  const T* er = e[0];
+  const T* u = e[1];
+  const T* v = e[2];
+  const T rkP = rk[q.p], omP = om[pf];
+  const T uP = u[q.p], vP = v[q.p];
+  const T uE = u[q.e], uW = u[q.w], uN = u[q.n], uS = u[q.s];
+  const T vE = v[q.e], vW = v[q.w], vN = v[q.n], vS = v[q.s];
+  out[0] = er[q.p] + c4 * (rk[q.e] * uE - rk[q.w] * uW + rk[q.n] * vN - rk[q.s] * vS);
+  const T qE = dq(e, b, q.e), qW = dq(e, b, q.w), qN = dq(e, b, q.n), qS = dq(e, b, q.s);
+  const T ME = potential_d<MODEL>(e, b, q.e, P), MW = potential_d<MODEL>(e, b, q.w, P);
+  const T MN = potential_d<MODEL>(e, b, q.n, P), MS = potential_d<MODEL>(e, b, q.s, P);
+  const T lapu = (uE + uW + uN + uS - T(4) * uP) * ih2;
+  const T lapv = (vE + vW + vN + vS - T(4) * vP) * ih2;
+  const T bb = T(0.5) * s * P.sigma * rkP * omP;
+  out[1] = rkP * uP - bb * vP + c4 * rkP * (qE - qW) + c2 * rkP * (ME - MW) - T(0.5) * s * P.gamma * lapu;
+  out[2] = rkP * vP + bb * uP + c4 * rkP * (qN - qS) + c2 * rkP * (MN - MS) - T(0.5) * s * P.gamma * lapv;
+  if constexpr (MODEL == PFC) {
+    const T* mu = e[3];
+    const T* ka = e[4];
+    const T x = er[q.p];
+    const T pb = b[0][q.p] - T(1.5);
+    const T cub = x * (pb * pb + pb * x + x * x * T(1.0 / 3.0));
+    const T lapk = (ka[q.e] + ka[q.w] + ka[q.n] + ka[q.s] - T(4) * ka[q.p]) * ih2;
+    const T lapr = (er[q.e] + er[q.w] + er[q.n] + er[q.s] - T(4) * x) * ih2;
+    out[3] = mu[q.p] - cub - P.alpha * x - lapk;
+    out[4] = ka[q.p] - lapr;
+  }
+}
+
+template <int MODEL, typename T>
+__device__ __forceinline__ void block_update_d(const T* const* e, const T* const* f, const T* const* b,
+                                               const T* rk, const T* om, const Nbr& q, int pf,
+                                               const Coef<T>& K, const Phys<T>& P, T* out) {
+  const T s = P.s;
+  const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
+  const T* er = e[0];
+  const T* u = e[1];
+  const T* v = e[2];
+  const T rkP = rk[q.p], omP = om[pf];
+  const T uE = u[q.e], uW = u[q.w], uN = u[q.n], uS = u[q.s];
+  const T vE = v[q.e], vW = v[q.w], vN = v[q.n], vS = v[q.s];
+  T rh = f[0][pf] - c4 * (rk[q.e] * uE - rk[q.w] * uW + rk[q.n] * vN - rk[q.s] * vS);
+  if constexpr (MODEL == CDFT) {
+    // positivity projection of rho = rho_b + e; a no-op in this precision
+    // unless rho_b + e is within a few orders of magnitude of delta or below
+    const T rb = b[0][q.p];
+    const T t = rb + rh;
+    if (!(t > T(0) && t * t > T(1e6) * P.delta * P.delta)) rh = fsqrt(t * t + P.delta * P.delta) - rb;
+  }
+  const T qE = dq(e, b, q.e), qW = dq(e, b, q.w), qN = dq(e, b, q.n), qS = dq(e, b, q.s);
+  const T ME = potential_d<MODEL>(e, b, q.e, P), MW = potential_d<MODEL>(e, b, q.w, P);
+  const T MN = potential_d<MODEL>(e, b, q.n, P), MS = potential_d<MODEL>(e, b, q.s, P);
+  const T cg = T(0.5) * s * P.gamma * ih2;
+  const T a = rkP + T(4) * cg;
+  const T bb = T(0.5) * s * P.sigma * rkP * omP;
+  const T ru = f[1][pf] - c4 * rkP * (qE - qW) - c2 * rkP * (ME - MW) + cg * (uE + uW + uN + uS);
+  const T rv = f[2][pf] - c4 * rkP * (qN - qS) - c2 * rkP * (MN - MS) + cg * (vE + vW + vN + vS);
+  const T idet = T(1) / (a * a + bb * bb);
+  const T uh = (a * ru + bb * rv) * idet;
+  const T vh = (a * rv - bb * ru) * idet;
+  const T w = P.w, w1 = T(1) - P.w;
+  const T el = er[q.p];
+  out[0] = w1 * rh + w * el;
+  out[1] = w1 * uh + w * u[q.p];
+  out[2] = w1 * vh + w * v[q.p];
+  if constexpr (MODEL == PFC) {
+    const T* mu = e[3];
+    const T* ka = e[4];
+    const T kh = f[4][pf] + (er[q.e] + er[q.w] + er[q.n] + er[q.s]) * ih2 - T(4) * rh * ih2;
+    const T pb = b[0][q.p] - T(1.5);
+    const T pl = pb + el;
+    const T cl = el * (pb * pb + pb * el + el * el * T(1.0 / 3.0));
+    const T mh = f[3][pf] + cl + pl * pl * (rh - el) + P.alpha * rh +
+                 (ka[q.e] + ka[q.w] + ka[q.n] + ka[q.s]) * ih2 - T(4) * kh * ih2;
+    out[3] = w1 * mh + w * mu[q.p];
+    out[4] = w1 * kh + w * ka[q.p];
+  }
+}
+
+// Mode dispatch: CORR = false is the full form, CORR = true the correction
+// form about the base fields b.
+template <int MODEL, typename T, bool CORR>
+__device__ __forceinline__ void rows_any(const T* const* g, const T* const* b, const T* rk, const T* om,
+                                         const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out) {
+  if constexpr (CORR)
+    rows_Nd<MODEL, T>(g, b, rk, om, q, pf, K, P, out);
+  else
+    rows_N<MODEL, T>(g, rk, om, q, pf, K, P, out);
+}
+
+template <int MODEL, typename T, bool CORR>
+__device__ __forceinline__ void update_any(const T* const* g, const T* const* f, const T* const* b, const T* rk,
+                                           const T* om, const Nbr& q, int pf, const Coef<T>& K,
+                                           const Phys<T>& P, T* out) {
+  if constexpr (CORR)
+    block_update_d<MODEL, T>(g, f, b, rk, om, q, pf, K, P, out);
+  else
+    block_update<MODEL, T>(g, f, rk, om, q, pf, K, P, out);
+}
+
+// CDFT projection of an iterate value after the coarse-grid correction: full
+// form rho <- sqrt(rho^2 + delta^2); correction form the same on rho_b + e.
+template <typename T, bool CORR>
+__device__ __forceinline__ T project_any(T x, T base, T delta) {
+  if constexpr (CORR) {
+    const T t = base + x;
+    if (!(t > T(0) && t * t > T(1e6) * delta * delta)) return fsqrt(t * t + delta * delta) - base;
+    return x;
+  } else {
+    return fsqrt(x * x + delta * delta);
   }
 }
 

@@ -26,13 +26,14 @@ template <typename T> struct TailArgs {
 
 // T values of LDS that the bottom `nlds` of `nt` tail levels need (top size
 // top_n): g, f, rk, om per level, plus g0 for all but the tail top.
-template <int NCm>
+// NB = 3 in the correction form (the base state rho, u, v), else 0.
+template <int NCm, int NB = 0>
 __host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int nlds) {
   size_t tot = 0;
   int n = top_n;
   for (int l = 0; l < nt; ++l) {
     const size_t cnt = (size_t)n * n;
-    if (l >= nt - nlds) tot += cnt * (2 * NCm + 2 + (l > 0 ? NCm : 0));
+    if (l >= nt - nlds) tot += cnt * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
     n >>= 1;
   }
   return tot;
@@ -41,7 +42,7 @@ __host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int nlds) {
 // Level descriptors of the tail: S = the arrays the phases use (LDS for the
 // bottom nlds levels, global above them), G = the global arrays.  Thread t
 // builds level t (same LDS order as tail_lds_count).
-template <int NCm, typename T>
+template <int NCm, int NB, typename T>
 __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S, Lvl<T>* G) {
   const int t = threadIdx.x;
   if (t >= A.nt) return;
@@ -52,7 +53,7 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
     size_t off = 0;
     for (int l = first; l < t; ++l) {
       const size_t nl = (size_t)(A.top_n >> l);
-      off += nl * nl * (2 * NCm + 2 + (l > 0 ? NCm : 0));
+      off += nl * nl * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
     }
     T* p = base + off;
     const int cnt = s.n * s.n;
@@ -69,11 +70,14 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
     }
     s.rk = p;
     s.om = p + cnt;
+    p += 2 * cnt;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) s.bg[c] = p + c * cnt;
   }
   S[t] = s;
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour) {
   const int n = L.n, half = n >> 1, cnt = half * n;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
@@ -81,22 +85,22 @@ __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, in
     const int i = 2 * t + ((j + colour) & 1);
     const Nbr q = nbr(i, j, n, L.lg);
     T out[NC<MODEL>::value];
-    block_update<MODEL, T>(L.g, L.f, L.rk, L.om, q, q.p, L.k, P, out);
+    update_any<MODEL, T, CORR>(L.g, L.f, L.bg, L.rk, L.om, q, q.p, L.k, P, out);
 #pragma unroll
     for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][q.p] = out[c];
   }
   __syncthreads();
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_sweeps(const Lvl<T> L, const Phys<T>& P, int sweeps) {
   for (int k = 0; k < sweeps; ++k) {
-    tail_smooth<MODEL, T>(L, P, 0);
-    tail_smooth<MODEL, T>(L, P, 1);
+    tail_smooth<MODEL, T, CORR>(L, P, 0);
+    tail_smooth<MODEL, T, CORR>(L, P, 1);
   }
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
   // d = f - N(g) on the fine level (into F.d, a global scratch array) ...
@@ -104,7 +108,7 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
   for (int w = threadIdx.x; w < fcnt; w += blockDim.x) {
     const Nbr q = nbr(w & (F.n - 1), w >> F.lg, F.n, F.lg);
     T nv[NCm];
-    rows_N<MODEL, T>(F.g, F.rk, F.om, q, q.p, F.k, P, nv);
+    rows_any<MODEL, T, CORR>(F.g, F.bg, F.rk, F.om, q, q.p, F.k, P, nv);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) F.d[c][q.p] = F.f[c][q.p] - nv[c];
   }
@@ -120,6 +124,10 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
       C.g0[c][w] = gr;
       C.f[c][w] = fw9(F.d[c], 2 * I, 2 * J, F.n, F.lg);
     }
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) C.bg[c][w] = fw9(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
+    }
   }
   __syncthreads();
   // ... and f_c += N_c(R g)
@@ -127,14 +135,14 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
     const int J = w >> C.lg, I = w & (C.n - 1);
     const Nbr q = nbr(I, J, C.n, C.lg);
     T nv[NCm];
-    rows_N<MODEL, T>(C.g0, C.rk, C.om, q, q.p, C.k, P, nv);
+    rows_any<MODEL, T, CORR>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) C.f[c][w] += nv[c];
   }
   __syncthreads();
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
   const int cnt = F.n * F.n, mc = C.n - 1;
@@ -160,7 +168,7 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
       }
       T x = F.g[c][w] + e;
       if constexpr (MODEL == CDFT) {
-        if (c == 0) x = fsqrt(x * x + P.delta * P.delta);
+        if (c == 0) x = project_any<T, CORR>(x, CORR ? F.bg[0][w] : T(0), P.delta);
       }
       F.g[c][w] = x;
     }
@@ -173,14 +181,15 @@ __device__ __forceinline__ void tail_copy(T* dst, const T* src, int cnt) {
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) dst[w] = src[w];
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool CORR>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P) {
   constexpr int NCm = NC<MODEL>::value;
+  constexpr int NB = CORR ? 3 : 0;
   extern __shared__ __align__(16) unsigned char tail_smem[];
   // level descriptors in LDS: S = LDS copies, G = the global arrays
   __shared__ Lvl<T> S[TAIL_MAX_LEVELS];
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
-  tail_lds_levels<NCm, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
+  tail_lds_levels<NCm, NB, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
   __syncthreads();
   const bool top_in_lds = A.nlds == A.nt;
   if (top_in_lds) {
@@ -189,6 +198,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P)
       tail_copy(S[0].g[c], G[0].g[c], cnt);
       tail_copy(S[0].f[c], G[0].f[c], cnt);
     }
+    for (int c = 0; c < NB; ++c) tail_copy(S[0].bg[c], G[0].bg[c], cnt);
   }
   for (int l = A.nt - A.nlds; l < A.nt; ++l) {
     const int cnt = G[l].n * G[l].n;
@@ -198,13 +208,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P)
   __syncthreads();
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
-    tail_sweeps<MODEL, T>(S[l], P, A.nu1);
-    tail_restrict<MODEL, T>(S[l], S[l + 1], P);
+    tail_sweeps<MODEL, T, CORR>(S[l], P, A.nu1);
+    tail_restrict<MODEL, T, CORR>(S[l], S[l + 1], P);
   }
-  tail_sweeps<MODEL, T>(S[last], P, A.coarse_sweeps);
+  tail_sweeps<MODEL, T, CORR>(S[last], P, A.coarse_sweeps);
   for (int l = last - 1; l >= 0; --l) {
-    tail_prolong<MODEL, T>(S[l], S[l + 1], P);
-    tail_sweeps<MODEL, T>(S[l], P, A.nu2);
+    tail_prolong<MODEL, T, CORR>(S[l], S[l + 1], P);
+    tail_sweeps<MODEL, T, CORR>(S[l], P, A.nu2);
   }
   if (top_in_lds) {
     const int cnt = G[0].n * G[0].n;

@@ -14,6 +14,10 @@
 // k_restrict_fas_tile: the FAS coarse problem of one level in one launch:
 // R g on a coarse tile plus a one-node halo (into LDS), then
 // f_c = N_c(R g) + R d with d = f - N(g) precomputed on the fine grid.
+//
+// CORR = true runs the same kernels on the correction form of the
+// mixed-precision inner solve (stencil.hpp); the base state is then staged
+// in LDS beside the iterate, and restricted along with it.
 #pragma once
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -34,16 +38,18 @@ template <typename T> struct Fld {
 // 2 the block's partial sum of |d|^2 written to partial[block] (the stop test).
 // A residual needs the swept values one node beyond the block, hence the
 // extra halo node.
-template <int MODEL, typename T, int NSW, bool PRO, int RES>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
 __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
                                                               Phys<T> P, double* partial) {
   constexpr int NCm = NC<MODEL>::value;
+  constexpr int NB = CORR ? 3 : 1;
   constexpr int H = 2 * NSW + (RES ? 1 : 0);
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2, CRN = CRX * CRY;
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RN];
+  __shared__ T sb[NB][CORR ? RN : 1];
   __shared__ T se[PRO ? NCm : 1][PRO ? CRN : 1];
   const int m = L.n - 1, lg = L.lg;
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
@@ -64,6 +70,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
     const int gi = (x0 + lx) & m, gj = (y0 + ly) & m;
     const int gp = (gj << lg) + gi;
     srk[w] = L.rk[gp];
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sb[c][w] = L.bg[c][gp];
+    }
 #pragma unroll
     for (int c = 0; c < NCm; ++c) {
       T x = gin.c[c][gp];
@@ -84,7 +94,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
           e = T(0.25) * (e00 + se[c][cp + 1] + se[c][cp + CRX] + se[c][cp + CRX + 1]);
         x += e;
         if constexpr (MODEL == CDFT) {
-          if (c == 0) x = fsqrt(x * x + P.delta * P.delta);
+          if (c == 0) x = project_any<T, CORR>(x, CORR ? L.bg[0][gp] : T(0), P.delta);
         }
       }
       sg[c][w] = x;
@@ -94,6 +104,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
   const T* gl[NCm];
 #pragma unroll
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
+  const T* bl[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
     const int half = (RX - 2 * k) >> 1, cnt = half * (RY - 2 * k);
@@ -109,7 +122,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
       q.s = q.p - RX;
       const int pf = (((y0 + ly) & m) << lg) + ((x0 + lx) & m);
       T out[NCm];
-      block_update<MODEL, T>(gl, L.f, srk, L.om, q, pf, L.k, P, out);
+      update_any<MODEL, T, CORR>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
     }
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
       q.n = lp + RX;
       q.s = lp - RX;
       T nv[NCm];
-      rows_N<MODEL, T>(gl, srk, L.om, q, gp, L.k, P, nv);
+      rows_any<MODEL, T, CORR>(gl, bl, srk, L.om, q, gp, L.k, P, nv);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) {
         const T d = L.f[c][gp] - nv[c];
@@ -159,13 +172,16 @@ __device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
          T(0.0625);
 }
 
-// F.g must point at the current fine iterate and F.d at f - N(g) of it.
-template <int MODEL, typename T>
+// F.g must point at the current fine iterate and F.d at f - N(g) of it.  In
+// the correction form the coarse base C.bg = R F.bg is written here too.
+template <int MODEL, typename T, bool CORR>
 __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lvl<T> C, Phys<T> P) {
   constexpr int NCm = NC<MODEL>::value;
+  constexpr int NB = CORR ? 3 : 1;
   constexpr int RX = RTILE + 2, RN = RX * RX;
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RN];
+  __shared__ T sb[NB][CORR ? RN : 1];
   const int mc = C.n - 1;
   const int X0 = (int)blockIdx.x * RTILE - 1, Y0 = (int)blockIdx.y * RTILE - 1;
   for (int w = threadIdx.x; w < RN; w += RTILE * RTILE) {
@@ -174,11 +190,18 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lv
     srk[w] = C.rk[(J << C.lg) + I];
 #pragma unroll
     for (int c = 0; c < NCm; ++c) sg[c][w] = fw9g(F.g[c], 2 * I, 2 * J, F.n, F.lg);
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sb[c][w] = fw9g(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
+    }
   }
   __syncthreads();
   const T* gl[NCm];
 #pragma unroll
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
+  const T* bl[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
   const int ty = threadIdx.x / RTILE, tx = threadIdx.x - ty * RTILE;
   const int ly = ty + 1, lx = tx + 1;
   const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
@@ -190,13 +213,17 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lv
   q.n = q.p + RX;
   q.s = q.p - RX;
   T nv[NCm];
-  rows_N<MODEL, T>(gl, srk, C.om, q, pc, C.k, P, nv);
+  rows_any<MODEL, T, CORR>(gl, bl, srk, C.om, q, pc, C.k, P, nv);
 #pragma unroll
   for (int c = 0; c < NCm; ++c) {
     const T gr = sg[c][q.p];
     C.g[c][pc] = gr;
     C.g0[c][pc] = gr;
     C.f[c][pc] = fw9g(F.d[c], 2 * I, 2 * J, F.n, F.lg) + nv[c];
+  }
+  if constexpr (CORR) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) C.bg[c][pc] = sb[c][q.p];
   }
 }
 

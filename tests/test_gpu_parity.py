@@ -202,3 +202,28 @@ def test_determinism_bitwise():
         outs.append([np_(x) for x in sim.get_state()] + [sim.energy()[0]])
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("model,n,steps", [("pfc", 32, 10), ("pfc", 128, 3), ("cdft", 64, 3), ("cdft", 128, 2)])
+def test_mixed_precision_steps(model, n, steps):
+    """FP32 correction V-cycles inside FP64 defect correction: every step meets
+    the same FP64 residual tolerance, so the state matches the FP64 oracle
+    within 1e-6 relative (the bar for the mixed solver); in practice much closer."""
+    if model == "pfc":
+        cfg, rho, u, v = workloads.pfc_uniform_noise(n, 0.25, 0.01, 7, precision="mixed")
+    else:
+        cfg, rho, u, v = workloads.cdft_gauss_noise(n, 17.0 / 128.0 * 2, 0.02, 7, precision="mixed")
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    worst = 0.0
+    for k in range(steps):
+        st = sim.step(1)
+        c, r = ora.step()
+        assert st.residual_last <= cfg.tol
+        errs = state_errors([np_(x) for x in sim.get_state()], (ora.rho, ora.u, ora.v))
+        worst = max(worst, max(errs))
+        assert max(errs) < 1e-6, (k, errs)
+    print(f"mixed {model} {n}^2: max rel err vs FP64 oracle {worst:.2e}")
+    E = sim.energy()
+    assert abs(E[0] - ora.energy()[0]) < 1e-6 * abs(ora.energy()[0])
