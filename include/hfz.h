@@ -160,6 +160,32 @@ int hfz_info(hfz_handle* hd, int* levels, double* ce);
 int hfz_destroy(hfz_handle* hd);
 const char* hfz_strerror(int code);
 
+/* ---- batched solve ------------------------------------------------------
+ * `count` independent instances advance together: each V-cycle phase of all
+ * instances is one kernel launch (instance index in the grid), the coarse
+ * tail one workgroup per instance.  All instances share model, n, precision,
+ * nu1, nu2 (both >= 1), coarsest_n and coarse_sweeps; h, s, gamma and the
+ * model constants may differ.  Each instance keeps its own stop test and
+ * leaves the launches when it converges, so its result is bitwise the one
+ * the single-instance solver produces.  Ownership, streams and errors as for
+ * the single-instance calls. */
+typedef struct hfz_batch hfz_batch;
+
+/* Bytes of device workspace for a batch over params[0..count-1]. */
+int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes);
+int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                   hfz_batch** out);
+/* State of instance i (device buffers of n*n doubles), as hfz_set_state / hfz_get_state. */
+int hfz_batch_set_state(hfz_batch* b, int i, const double* rho, const double* u, const double* v);
+int hfz_batch_get_state(hfz_batch* b, int i, double* rho, double* u, double* v);
+/* Energy of instance i, as hfz_energy. */
+int hfz_batch_energy(hfz_batch* b, int i, double* out5);
+/* Advances every instance nsteps steps.  stats: NULL or an array of count.
+ * An instance that fails a step (HFZ_ENOCONV / HFZ_ENAN) keeps its previous
+ * state, the others complete the step; the first failure code is returned. */
+int hfz_batch_step(hfz_batch* b, int nsteps, hfz_stats* stats);
+int hfz_batch_destroy(hfz_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,110 @@
+// Kernels of the batched solve: many equally sized instances per launch,
+// instance = blockIdx.z (or blockIdx.x for one workgroup per instance),
+// descriptors in device arrays, instances whose flag in `active` is 0 skipped.
+// The arithmetic is the single-instance device code.
+#pragma once
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace hfz {
+
+// Per-block partial sums of sum_c (f - N(g))^2 on each instance's finest level.
+template <int MODEL>
+__global__ void k_residual_partial_b(const Lvl<double>* Ls, const Phys<double>* Ps, const int* active,
+                                     double* __restrict__ partial, int pstride) {
+  __shared__ double lds[16];
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  const Lvl<double> L = Ls[z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  double acc = 0.0;
+  if (i < L.n && j < L.n) {
+    constexpr int NCm = NC<MODEL>::value;
+    const Nbr q = nbr(i, j, L.n, L.lg);
+    double nv[NCm];
+    rows_N<MODEL, double>(L.g, L.rk, L.om, q, q.p, L.k, Ps[z], nv);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) {
+      const double d = L.f[c][q.p] - nv[c];
+      acc += d * d;
+    }
+  }
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[(size_t)z * pstride + blockIdx.y * gridDim.x + blockIdx.x] = r;
+}
+
+// Mixed precision: k_mp_prepare per instance (the outer FP64 residual into
+// the inner right-hand side, base state, e = 0, partial sums).
+template <int MODEL>
+__global__ void k_mp_prepare_b(const Lvl<double>* Ls, const Phys<double>* Ps, const Lvl<float>* Es,
+                               const int* active, double* __restrict__ partial, int pstride) {
+  __shared__ double lds[16];
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  const Lvl<double> L = Ls[z];
+  const Lvl<float> E = Es[z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  double acc = 0.0;
+  if (i < L.n && j < L.n) {
+    constexpr int NCm = NC<MODEL>::value;
+    const Nbr q = nbr(i, j, L.n, L.lg);
+    double nv[NCm];
+    rows_N<MODEL, double>(L.g, L.rk, L.om, q, q.p, L.k, Ps[z], nv);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) {
+      const double d = L.f[c][q.p] - nv[c];
+      acc += d * d;
+      E.f[c][q.p] = (float)d;
+      E.g[c][q.p] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
+  }
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[(size_t)z * pstride + blockIdx.y * gridDim.x + blockIdx.x] = r;
+}
+
+template <int MODEL>
+__global__ void k_mp_update_b(const Lvl<double>* Ls, const Lvl<float>* Es, const int* active) {
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  const Lvl<double> L = Ls[z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const int p = (j << L.lg) + i;
+  const Lvl<float> E = Es[z];
+#pragma unroll
+  for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][p] += (double)E.g[c][p];
+}
+
+// g <- gb for every component (the iterate ended in the second buffer).
+template <typename T>
+__global__ void k_swap_back_b(const Lvl<T>* Ls, const int* active, int nc) {
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  const Lvl<T> L = Ls[z];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.n * L.n) return;
+  for (int c = 0; c < nc; ++c) L.g[c][t] = L.gb[c][t];
+}
+
+// norm2[z] = h_z^2 * (sum of instance z's `count` partials), fixed order;
+// one workgroup per instance.
+__global__ void k_reduce_b(const double* __restrict__ partial, int count, int pstride, const Lvl<double>* Ls,
+                           const int* active, double* __restrict__ norm2) {
+  __shared__ double lds[16];
+  const int z = blockIdx.x;
+  if (!active[z]) return;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < count; t += blockDim.x) acc += partial[(size_t)z * pstride + t];
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0) {
+    const double h = Ls[z].h;
+    norm2[z] = h * h * r;
+  }
+}
+
+}  // namespace hfz

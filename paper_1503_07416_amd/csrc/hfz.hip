@@ -15,6 +15,7 @@
 #include "hfz.h"
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "batchk.hpp"
 #include "driver.hpp"
 
 using namespace hfz;
@@ -880,6 +881,413 @@ const char* hfz_strerror(int code) {
     default:
       return "unknown error";
   }
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solve: many independent instances of one model, grid size and
+// precision advance together.  Every instance is an ordinary handle over its
+// own slice of the batch workspace (so set/get state, energy and the per-step
+// kernels are the single-instance ones); the V-cycles of all instances run in
+// shared launches, one per grid level and phase, with the instance in
+// blockIdx.z (the coarse tail: one workgroup per instance).  Each instance
+// keeps its own stop test; converged instances drop out of the launches.
+// ===========================================================================
+
+struct hfz_batch {
+  int count = 0;
+  hfz_params p{};  // model, n, precision, nu1, nu2, ... shared by all instances
+  hipStream_t stream = nullptr;
+  std::vector<hfz_handle*> inst;
+  int nlev = 0;
+  // device arrays
+  Lvl<double>* D64 = nullptr;  // [level][instance]
+  Lvl<float>* D32 = nullptr;
+  Lvl<double>* T64 = nullptr;  // [instance][level] (tail descriptors)
+  Lvl<float>* T32 = nullptr;
+  Phys<double>* P64 = nullptr;  // [instance]
+  Phys<float>* P32 = nullptr;
+  int* active = nullptr;
+  double* norm2 = nullptr;
+  double* partial = nullptr;
+  int pstride = 0;
+  size_t lds64 = 0, lds32 = 0;
+  std::vector<int> h_active;
+  std::vector<double> h_norm2;
+  int graph_state = 0;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+};
+
+namespace {
+
+bool batch_compatible(const hfz_params& a, const hfz_params& b) {
+  return a.model == b.model && a.n == b.n && a.precision == b.precision && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
+         a.coarsest_n == b.coarsest_n && a.coarse_sweeps == b.coarse_sweeps;
+}
+
+struct BatchLayout {
+  size_t inst_bytes = 0, total = 0;
+  size_t off_arrays = 0;
+};
+
+BatchLayout batch_layout(const hfz_params* ps, int count) {
+  BatchLayout bl;
+  bl.inst_bytes = align_up(layout(ps[0], nullptr, nullptr));
+  bl.off_arrays = bl.inst_bytes * count;
+  Carver c{nullptr};
+  const int nlev = ilog2(ps[0].n) - ilog2(ps[0].coarsest_n) + 1;
+  const size_t N2 = (size_t)ps[0].n * ps[0].n;
+  c.take<Lvl<double>>((size_t)nlev * count * 2);
+  c.take<Lvl<float>>((size_t)nlev * count * 2);
+  c.take<Phys<double>>(count);
+  c.take<Phys<float>>(count);
+  c.take<int>(count);
+  c.take<double>(count);
+  c.take<double>((N2 / 256 + 64) * count);
+  bl.total = bl.off_arrays + c.off;
+  return bl;
+}
+
+template <int MODEL, typename T, bool CORR>
+void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_max,
+                 const Cycle& K, int l) {
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
+  const int nlev = (int)R.size(), count = B->count;
+  if (R[l].n <= K.tail_n && nlev - l <= TAIL_MAX_LEVELS) {
+    TailArgs<T> A{};
+    A.Lg = Tl + l;
+    A.nt = nlev - l;
+    A.top_n = R[l].n;
+    A.nu1 = K.nu1;
+    A.nu2 = K.nu2;
+    A.coarse_sweeps = K.coarse_sweeps;
+    A.nlds = 0;
+    for (int k = 1; k <= A.nt; ++k)
+      if (tail_lds_count<NCm, NB>(A.top_n, A.nt, k) * sizeof(T) <= lds_max) A.nlds = k;
+    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.nlds) * sizeof(T);
+    k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
+    return;
+  }
+  Lvl<T>* Dl = D + (size_t)l * count;
+  Lvl<T>* Dc = D + (size_t)(l + 1) * count;
+  const int n = R[l].n, nc = R[l + 1].n;
+  const dim3 grid(n / TILE_X, n / TILE_Y, count);
+  int inb = 0;
+  auto sweeps = [&](int total, bool pro, int res_last) {
+    while (total > 0) {
+      const int nsw = total >= 2 ? 2 : 1;
+      const int res = (total == nsw) ? res_last : 0;
+#define HFZ_BT(NSW, PRO, RES)                                                                                 \
+  k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(Dl, Dc, Ps, B->active, inb, \
+                                                                                      B->partial, B->pstride)
+      if (nsw == 2) {
+        if (pro) {
+          if (res == 2) HFZ_BT(2, true, 2); else if (res == 1) HFZ_BT(2, true, 1); else HFZ_BT(2, true, 0);
+        } else {
+          if (res == 2) HFZ_BT(2, false, 2); else if (res == 1) HFZ_BT(2, false, 1); else HFZ_BT(2, false, 0);
+        }
+      } else {
+        if (pro) {
+          if (res == 2) HFZ_BT(1, true, 2); else if (res == 1) HFZ_BT(1, true, 1); else HFZ_BT(1, true, 0);
+        } else {
+          if (res == 2) HFZ_BT(1, false, 2); else if (res == 1) HFZ_BT(1, false, 1); else HFZ_BT(1, false, 0);
+        }
+      }
+#undef HFZ_BT
+      inb ^= 1;
+      total -= nsw;
+      pro = false;
+    }
+  };
+  sweeps(K.nu1, false, 1);
+  k_restrict_fas_tile_b<MODEL, T, CORR><<<dim3(nc / RTILE, nc / RTILE, count), RTILE * RTILE, 0, K.stream>>>(
+      Dl, Dc, Ps, B->active, inb);
+  bvcycle_rec<MODEL, T, CORR>(B, R, D, Tl, Ps, lds_max, K, l + 1);
+  sweeps(K.nu2, true, (l == 0 && !CORR) ? 2 : 0);
+  if (inb) k_swap_back_b<T><<<dim3((n * n + 255) / 256, 1, count), 256, 0, K.stream>>>(Dl, B->active, NCm);
+}
+
+// Enqueues one batched V-cycle (mixed: one outer iteration) and the
+// per-instance stop-test norms into B->norm2.
+template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
+  hfz_handle* h0 = B->inst[0];
+  Cycle K = cycle_ctx(h0);
+  K.stream = stream;
+  K.partial = B->partial;
+  const int n = B->p.n;
+  const dim3 b = block2(n, n);
+  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, B->count);
+  if (B->p.precision == HFZ_MIXED) {
+    bvcycle_rec<MODEL, float, true>(B, h0->H32.L, B->D32, B->T32, B->P32, B->lds32, K, 0);
+    k_mp_update_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->D32, B->active);
+    k_mp_prepare_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
+    k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                              B->norm2);
+  } else {
+    bvcycle_rec<MODEL, double, false>(B, h0->H.L, B->D64, B->T64, B->P64, B->lds64, K, 0);
+    const bool tiled_top = n > K.tail_n;
+    if (tiled_top) {
+      k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / TILE_X) * (n / TILE_Y), B->pstride, B->D64,
+                                                B->active, B->norm2);
+    } else {
+      k_residual_partial_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
+      k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                                B->norm2);
+    }
+  }
+}
+
+// The first stop test of a step (before any V-cycle).
+template <int MODEL> void batch_first_norm(hfz_batch* B) {
+  const int n = B->p.n;
+  const dim3 b = block2(n, n);
+  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, B->count);
+  if (B->p.precision == HFZ_MIXED)
+    k_mp_prepare_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
+  else
+    k_residual_partial_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
+  k_reduce_b<<<B->count, 1024, 0, B->stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                               B->norm2);
+}
+
+void batch_cycle_any(hfz_batch* B, hipStream_t s) {
+  if (B->p.model == HFZ_PFC)
+    batch_cycle<PFC>(B, s);
+  else
+    batch_cycle<CDFT>(B, s);
+}
+
+int batch_launch_cycle(hfz_batch* B) {
+  if (B->use_graph && B->graph_state == 0) {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      batch_cycle_any(B, cap);
+      ok = hipStreamEndCapture(cap, &g) == hipSuccess;
+    }
+    if (ok) ok = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
+    (void)hipGetLastError();
+    B->graph_state = ok ? 1 : -1;
+  }
+  if (B->graph_state == 1) return hipGraphLaunch(B->exec, B->stream) == hipSuccess ? HFZ_OK : HFZ_EHIP;
+  batch_cycle_any(B, B->stream);
+  return last_error();
+}
+
+int batch_read_norms(hfz_batch* B) {
+  HIPCHK(hipMemcpyAsync(B->h_norm2.data(), B->norm2, B->count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+  HIPCHK(hipStreamSynchronize(B->stream));
+  return last_error();
+}
+
+int batch_write_active(hfz_batch* B) {
+  HIPCHK(hipMemcpyAsync(B->active, B->h_active.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  return HFZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes) {
+  if (!params || count < 1 || !bytes) return HFZ_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    const int rc = validate(&params[i]);
+    if (rc != HFZ_OK) return rc;
+    if (!batch_compatible(params[0], params[i])) return HFZ_EINVAL;
+  }
+  if (params[0].nu1 < 1 || params[0].nu2 < 1) return HFZ_EINVAL;
+  *bytes = batch_layout(params, count).total;
+  return HFZ_OK;
+}
+
+int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                   hfz_batch** out) {
+  if (!out) return HFZ_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  int rc = hfz_batch_workspace_bytes(params, count, &need);
+  if (rc != HFZ_OK) return rc;
+  if (!dev_ws || ws_bytes < need) return HFZ_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return HFZ_EINVAL;
+  hfz_batch* B = new (std::nothrow) hfz_batch();
+  if (!B) return HFZ_ENOMEM;
+  B->count = count;
+  B->p = params[0];
+  B->stream = static_cast<hipStream_t>(hip_stream);
+  const BatchLayout bl = batch_layout(params, count);
+  char* base = static_cast<char*>(dev_ws);
+  for (int i = 0; i < count; ++i) {
+    hfz_handle* h = nullptr;
+    rc = hfz_init(&params[i], base + bl.inst_bytes * i, bl.inst_bytes, hip_stream, &h);
+    if (rc != HFZ_OK) {
+      hfz_batch_destroy(B);
+      return rc;
+    }
+    // the batched cycle needs every level above the tail tileable
+    if (h->tail_n < 16) h->tail_n = 32;
+    h->use_tiles = true;
+    B->inst.push_back(h);
+  }
+  B->nlev = B->inst[0]->nlev;
+  Carver c{base + bl.off_arrays};
+  const int nl = B->nlev;
+  B->D64 = c.take<Lvl<double>>((size_t)nl * count);
+  B->T64 = c.take<Lvl<double>>((size_t)nl * count);
+  B->D32 = c.take<Lvl<float>>((size_t)nl * count);
+  B->T32 = c.take<Lvl<float>>((size_t)nl * count);
+  B->P64 = c.take<Phys<double>>(count);
+  B->P32 = c.take<Phys<float>>(count);
+  B->active = c.take<int>(count);
+  B->norm2 = c.take<double>(count);
+  B->pstride = (int)((size_t)params[0].n * params[0].n / 256 + 64);
+  B->partial = c.take<double>((size_t)B->pstride * count);
+  const bool mixed = params[0].precision == HFZ_MIXED;
+  std::vector<Lvl<double>> d64((size_t)nl * count), t64((size_t)nl * count);
+  std::vector<Lvl<float>> d32(mixed ? (size_t)nl * count : 0), t32(mixed ? (size_t)nl * count : 0);
+  std::vector<Phys<double>> p64(count);
+  std::vector<Phys<float>> p32(count);
+  for (int i = 0; i < count; ++i) {
+    hfz_handle* h = B->inst[i];
+    for (int l = 0; l < nl; ++l) {
+      d64[(size_t)l * count + i] = h->H.L[l];
+      t64[(size_t)i * nl + l] = h->H.L[l];
+      if (mixed) {
+        d32[(size_t)l * count + i] = h->H32.L[l];
+        t32[(size_t)i * nl + l] = h->H32.L[l];
+      }
+    }
+    p64[i] = h->H.P;
+    p32[i] = h->H32.P;
+  }
+  B->lds64 = B->inst[0]->H.tail_lds_max;
+  B->lds32 = B->inst[0]->H32.tail_lds_max;
+  B->h_active.assign(count, 1);
+  B->h_norm2.assign(count, 0.0);
+  bool ok = hipMemcpyAsync(B->D64, d64.data(), d64.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
+                           B->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(B->T64, t64.data(), t64.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
+                            B->stream) == hipSuccess;
+  if (mixed) {
+    ok = ok && hipMemcpyAsync(B->D32, d32.data(), d32.size() * sizeof(Lvl<float>), hipMemcpyHostToDevice,
+                              B->stream) == hipSuccess;
+    ok = ok && hipMemcpyAsync(B->T32, t32.data(), t32.size() * sizeof(Lvl<float>), hipMemcpyHostToDevice,
+                              B->stream) == hipSuccess;
+  }
+  ok = ok && hipMemcpyAsync(B->P64, p64.data(), count * sizeof(Phys<double>), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(B->P32, p32.data(), count * sizeof(Phys<float>), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  ok = ok && hipStreamSynchronize(B->stream) == hipSuccess;
+  if (!ok) {
+    hfz_batch_destroy(B);
+    return HFZ_EHIP;
+  }
+  if (const char* e = std::getenv("HFZ_GRAPH")) B->use_graph = std::atoi(e) != 0;
+  *out = B;
+  return HFZ_OK;
+}
+
+int hfz_batch_set_state(hfz_batch* B, int i, const double* rho, const double* u, const double* v) {
+  if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
+  return hfz_set_state(B->inst[i], rho, u, v);
+}
+
+int hfz_batch_get_state(hfz_batch* B, int i, double* rho, double* u, double* v) {
+  if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
+  return hfz_get_state(B->inst[i], rho, u, v);
+}
+
+int hfz_batch_energy(hfz_batch* B, int i, double* out5) {
+  if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
+  return hfz_energy(B->inst[i], out5);
+}
+
+int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
+  if (!B || nsteps < 0) return HFZ_EINVAL;
+  for (auto* h : B->inst)
+    if (!h->has_state) return HFZ_ESTATE;
+  const int count = B->count;
+  const bool mixed = B->p.precision == HFZ_MIXED;
+  std::vector<hfz_stats> st(count);
+  std::vector<int> cycles(count), failed(count, 0);
+  int rc = HFZ_OK;
+  for (int k = 0; k < nsteps && rc == HFZ_OK; ++k) {
+    for (int i = 0; i < count; ++i) {
+      rc = begin_step(B->inst[i]);
+      if (rc != HFZ_OK) break;
+      if (mixed) mp_begin(B->inst[i]);
+    }
+    if (rc != HFZ_OK) break;
+    std::fill(B->h_active.begin(), B->h_active.end(), 1);
+    std::fill(cycles.begin(), cycles.end(), 0);
+    rc = batch_write_active(B);
+    if (rc != HFZ_OK) break;
+    if (B->p.model == HFZ_PFC)
+      batch_first_norm<PFC>(B);
+    else
+      batch_first_norm<CDFT>(B);
+    rc = batch_read_norms(B);
+    while (rc == HFZ_OK) {
+      bool changed = false;
+      int live = 0;
+      for (int i = 0; i < count; ++i) {
+        if (!B->h_active[i]) continue;
+        const double r = std::sqrt(B->h_norm2[i]);
+        int fail = 0;
+        if (r <= B->inst[i]->p.tol) {
+        } else if (!std::isfinite(r)) {
+          fail = HFZ_ENAN;
+        } else if (cycles[i] >= B->inst[i]->p.max_cycles) {
+          fail = HFZ_ENOCONV;
+        } else {
+          ++live;
+          continue;
+        }
+        B->h_active[i] = 0;
+        changed = true;
+        failed[i] = fail;
+        st[i].cycles_last = cycles[i];
+        st[i].residual_last = r;
+      }
+      if (live == 0) break;
+      if (changed) rc = batch_write_active(B);
+      if (rc != HFZ_OK) break;
+      for (int i = 0; i < count; ++i)
+        if (B->h_active[i]) ++cycles[i];
+      rc = batch_launch_cycle(B);
+      if (rc == HFZ_OK) rc = batch_read_norms(B);
+    }
+    if (rc != HFZ_OK) break;
+    for (int i = 0; i < count; ++i) {
+      if (failed[i]) continue;  // rolled back: the state is that of the previous step
+      rc = finish_step(B->inst[i]);
+      if (rc != HFZ_OK) break;
+      st[i].steps_done++;
+      st[i].cycles_total += cycles[i];
+    }
+    if (rc != HFZ_OK) break;
+    for (int i = 0; i < count; ++i)
+      if (failed[i] && rc == HFZ_OK) rc = failed[i];
+  }
+  if (rc == HFZ_OK && hipStreamSynchronize(B->stream) != hipSuccess) rc = HFZ_EHIP;
+  if (stats)
+    for (int i = 0; i < count; ++i) stats[i] = st[i];
+  return rc;
+}
+
+int hfz_batch_destroy(hfz_batch* B) {
+  if (!B) return HFZ_EINVAL;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  for (auto* h : B->inst) hfz_destroy(h);
+  delete B;
+  return HFZ_OK;
 }
 
 }  // extern "C"

@@ -182,7 +182,7 @@ __device__ __forceinline__ void tail_copy(T* dst, const T* src, int cnt) {
 }
 
 template <int MODEL, typename T, bool CORR>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P) {
+__device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? 3 : 0;
   extern __shared__ __align__(16) unsigned char tail_smem[];
@@ -220,6 +220,23 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P)
     const int cnt = G[0].n * G[0].n;
     for (int c = 0; c < NCm; ++c) tail_copy(G[0].g[c], S[0].g[c], cnt);
   }
+}
+
+template <int MODEL, typename T, bool CORR>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P) {
+  tail_body<MODEL, T, CORR>(A, P);
+}
+
+// Batched form: workgroup z runs the tail of instance z, whose level
+// descriptors start at A.Lg + z * stride.
+template <int MODEL, typename T, bool CORR>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail_b(TailArgs<T> A, int stride, const Phys<T>* Ps,
+                                                         const int* active) {
+  const int z = blockIdx.x;
+  if (!active[z]) return;
+  TailArgs<T> B = A;
+  B.Lg = A.Lg + (size_t)z * stride;
+  tail_body<MODEL, T, CORR>(B, Ps[z]);
 }
 
 }  // namespace hfz

@@ -39,8 +39,8 @@ template <typename T> struct Fld {
 // A residual needs the swept values one node beyond the block, hence the
 // extra halo node.
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
-__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
-                                                              Phys<T> P, double* partial) {
+__device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
+                                                 const Lvl<T>& C, const Phys<T>& P, double* partial) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? 3 : 1;
   constexpr int H = 2 * NSW + (RES ? 1 : 0);
@@ -162,6 +162,34 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> g
   }
 }
 
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
+__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
+                                                              Phys<T> P, double* partial) {
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR>(L, gin, gout, C, P, partial);
+}
+
+// Batched form: instance blockIdx.z of equally sized instances, descriptors in
+// device arrays, skipped when not active.  The iterate is read from g (inb =
+// 0) or gb (inb = 1) and written to the other buffer; partial sums go to
+// partial + z * pstride.
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
+__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile_b(const Lvl<T>* Ls, const Lvl<T>* Cs,
+                                                                const Phys<T>* Ps, const int* active, int inb,
+                                                                double* partial, int pstride) {
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  const Lvl<T> L = Ls[z];
+  Fld<T> a{}, b{};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    a.c[c] = L.g[c];
+    b.c[c] = L.gb[c];
+  }
+  const Lvl<T> C = PRO ? Cs[z] : L;
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR>(L, inb ? b : a, inb ? a : b, C, Ps[z],
+                                                  partial + (size_t)z * pstride);
+}
+
 template <typename T>
 __device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
   const int m = n - 1;
@@ -175,7 +203,7 @@ __device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
 // F.g must point at the current fine iterate and F.d at f - N(g) of it.  In
 // the correction form the coarse base C.bg = R F.bg is written here too.
 template <int MODEL, typename T, bool CORR>
-__global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+__device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? 3 : 1;
   constexpr int RX = RTILE + 2, RN = RX * RX;
@@ -225,6 +253,26 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lv
 #pragma unroll
     for (int c = 0; c < 3; ++c) C.bg[c][pc] = sb[c][q.p];
   }
+}
+
+template <int MODEL, typename T, bool CORR>
+__global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  restrict_fas_body<MODEL, T, CORR>(F, C, P);
+}
+
+// Batched form (instance blockIdx.z); the fine iterate is in g (inb = 0) or gb.
+template <int MODEL, typename T, bool CORR>
+__global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile_b(const Lvl<T>* Fs, const Lvl<T>* Cs,
+                                                                      const Phys<T>* Ps, const int* active,
+                                                                      int inb) {
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  Lvl<T> F = Fs[z];
+  if (inb) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F.g[c] = F.gb[c];
+  }
+  restrict_fas_body<MODEL, T, CORR>(F, Cs[z], Ps[z]);
 }
 
 }  // namespace hfz

@@ -25,6 +25,8 @@ SYMBOLS = [
     "hfz_get_state", "hfz_get_aux", "hfz_step", "hfz_energy", "hfz_mass",
     "hfz_begin_step", "hfz_smooth", "hfz_vcycle", "hfz_residual", "hfz_finish_step",
     "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_destroy", "hfz_strerror",
+    "hfz_batch_workspace_bytes", "hfz_batch_init", "hfz_batch_set_state", "hfz_batch_get_state",
+    "hfz_batch_energy", "hfz_batch_step", "hfz_batch_destroy",
 ]
 
 
@@ -84,6 +86,13 @@ def load():
         "hfz_info": [vp, P(i), P(d)],
         "hfz_destroy": [vp],
         "hfz_strerror": [i],
+        "hfz_batch_workspace_bytes": [P(Params), i, P(ctypes.c_size_t)],
+        "hfz_batch_init": [P(Params), i, vp, ctypes.c_size_t, vp, P(vp)],
+        "hfz_batch_set_state": [vp, i, vp, vp, vp],
+        "hfz_batch_get_state": [vp, i, vp, vp, vp],
+        "hfz_batch_energy": [vp, i, P(d)],
+        "hfz_batch_step": [vp, i, P(Stats)],
+        "hfz_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -236,6 +245,63 @@ class Simulation:
     def close(self):
         if self.h is not None:
             self.lib.hfz_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many instances of one model, grid size and precision stepped together
+    (hfz_batch_* of the C ABI)."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        self.lib = load()
+        self.count = len(cfgs)
+        self.params = (Params * self.count)(*[make_params(c) for c in cfgs])
+        self.n = self.params[0].n
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = ctypes.c_size_t(0)
+        check(self.lib.hfz_batch_workspace_bytes(self.params, self.count, ctypes.byref(nb)),
+              "hfz_batch_workspace_bytes")
+        self.nbytes = nb.value
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(self.lib.hfz_batch_init(self.params, self.count, _ptr(self.ws), self.nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "hfz_batch_init")
+        self.h = h
+
+    def set_state(self, i, rho, u, v):
+        t = [torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous() for a in (rho, u, v)]
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.hfz_batch_set_state(self.h, i, *[_ptr(x) for x in t]), "hfz_batch_set_state")
+
+    def get_state(self, i):
+        t = [torch.empty((self.n, self.n), dtype=torch.float64, device=self.device) for _ in range(3)]
+        check(self.lib.hfz_batch_get_state(self.h, i, *[_ptr(x) for x in t]), "hfz_batch_get_state")
+        return t
+
+    def energy(self, i):
+        out = (ctypes.c_double * 5)()
+        check(self.lib.hfz_batch_energy(self.h, i, out), "hfz_batch_energy")
+        return list(out)
+
+    def step(self, nsteps=1, raise_on_error=True):
+        st = (Stats * self.count)()
+        rc = self.lib.hfz_batch_step(self.h, int(nsteps), st)
+        if raise_on_error:
+            check(rc, "hfz_batch_step")
+            return list(st)
+        return rc, list(st)
+
+    def close(self):
+        if self.h is not None:
+            self.lib.hfz_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,71 @@
+"""GPU: the batched solver gives, for every instance, the result the
+single-instance solver gives for that instance alone (same device code, same
+per-instance stop test, same V-cycle count; the two kernels are compiled
+separately, so floating-point contraction may differ in the last bit), for
+both precisions and both models; it also agrees with the CPU oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.helpers import oracle_stepper, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def np_(t):
+    return t.cpu().numpy()
+
+
+def instances(model, n, count, precision, seed=0):
+    out = []
+    rng = np.random.default_rng(seed)
+    for i in range(count):
+        if model == "pfc":
+            rb = float(rng.uniform(workloads.NANO_RHO_L, workloads.NANO_RHO_S))
+            amp = 0.05 * (0.2 + i / count)   # uneven: different cycle counts
+            out.append(workloads.pfc_uniform_noise(n, workloads.NANO_H, 0.02, 100 + i, rho_bar=rb, amp=amp,
+                                                   alpha=1.0 - workloads.NANO_EPS, precision=precision))
+        else:
+            out.append(workloads.cdft_gauss_noise(n, 17.0 / 64.0, 0.02, 100 + i, amp=0.01 + 0.01 * i / count,
+                                                  precision=precision))
+    return out
+
+
+@pytest.mark.parametrize("model,n,precision", [("pfc", 64, "fp64"), ("pfc", 128, "mixed"),
+                                               ("pfc", 32, "mixed"), ("cdft", 64, "mixed"),
+                                               ("cdft", 128, "fp64")])
+def test_batch_equals_alone(model, n, precision):
+    import paper_1503_07416_amd as pkg
+    inst = instances(model, n, 5, precision)
+    B = pkg.Batch([c for c, _, _, _ in inst])
+    for i, (c, r, u, v) in enumerate(inst):
+        B.set_state(i, r, u, v)
+    stats = B.step(3)
+    cyc = [s.cycles_total for s in stats]
+    for i, (c, r, u, v) in enumerate(inst):
+        sim = pkg.Simulation(c)
+        sim.set_state(r, u, v)
+        st = sim.step(3)
+        assert st.cycles_total == cyc[i]
+        a = [np_(x) for x in B.get_state(i)]
+        b = [np_(x) for x in sim.get_state()]
+        for x, y in zip(a, b):
+            scale = max(np.abs(y).max(), 1e-300)
+            assert np.abs(x - y).max() <= 1e-13 * scale, (i, np.abs(x - y).max())
+        assert abs(B.energy(i)[0] - sim.energy()[0]) <= 1e-13 * abs(sim.energy()[0])
+
+
+def test_batch_matches_oracle():
+    import paper_1503_07416_amd as pkg
+    inst = instances("pfc", 64, 3, "mixed", seed=5)
+    B = pkg.Batch([c for c, _, _, _ in inst])
+    for i, (c, r, u, v) in enumerate(inst):
+        B.set_state(i, r, u, v)
+    B.step(2)
+    for i, (c, r, u, v) in enumerate(inst):
+        ora = oracle_stepper(c)
+        ora.set_state(r, u, v)
+        ora.step()
+        ora.step()
+        errs = state_errors([np_(x) for x in B.get_state(i)], (ora.rho, ora.u, ora.v))
+        assert max(errs) < 1e-6, (i, errs)
