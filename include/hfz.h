@@ -180,9 +180,14 @@ int hfz_batch_set_state(hfz_batch* b, int i, const double* rho, const double* u,
 int hfz_batch_get_state(hfz_batch* b, int i, double* rho, double* u, double* v);
 /* Energy of instance i, as hfz_energy. */
 int hfz_batch_energy(hfz_batch* b, int i, double* out5);
-/* Advances every instance nsteps steps.  stats: NULL or an array of count.
- * An instance that fails a step (HFZ_ENOCONV / HFZ_ENAN) keeps its previous
- * state, the others complete the step; the first failure code is returned. */
+/* Marks instance i empty: hfz_batch_step skips it until hfz_batch_set_state
+ * fills it again (a slot of a serving pool).  Its memory stays reserved. */
+int hfz_batch_release(hfz_batch* b, int i);
+/* Advances every filled instance (state set and not released) nsteps steps;
+ * empty instances are skipped and get zeroed stats.  stats: NULL or an array
+ * of count.  An instance that fails a step (HFZ_ENOCONV / HFZ_ENAN) keeps its
+ * previous state, the others complete the step, the call returns the first
+ * failure code after that step. */
 int hfz_batch_step(hfz_batch* b, int nsteps, hfz_stats* stats);
 int hfz_batch_destroy(hfz_batch* b);
 

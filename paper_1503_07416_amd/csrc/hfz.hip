@@ -1209,23 +1209,33 @@ int hfz_batch_energy(hfz_batch* B, int i, double* out5) {
   return hfz_energy(B->inst[i], out5);
 }
 
+int hfz_batch_release(hfz_batch* B, int i) {
+  if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
+  B->inst[i]->has_state = false;
+  return HFZ_OK;
+}
+
 int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
   if (!B || nsteps < 0) return HFZ_EINVAL;
-  for (auto* h : B->inst)
-    if (!h->has_state) return HFZ_ESTATE;
   const int count = B->count;
+  std::vector<char> filled(count);
+  int nfilled = 0;
+  for (int i = 0; i < count; ++i) nfilled += filled[i] = B->inst[i]->has_state ? 1 : 0;
+  if (stats)
+    for (int i = 0; i < count; ++i) stats[i] = hfz_stats{};
+  if (nfilled == 0) return HFZ_OK;
   const bool mixed = B->p.precision == HFZ_MIXED;
   std::vector<hfz_stats> st(count);
   std::vector<int> cycles(count), failed(count, 0);
   int rc = HFZ_OK;
   for (int k = 0; k < nsteps && rc == HFZ_OK; ++k) {
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < count && rc == HFZ_OK; ++i) {
+      if (!filled[i]) continue;
       rc = begin_step(B->inst[i]);
-      if (rc != HFZ_OK) break;
-      if (mixed) mp_begin(B->inst[i]);
+      if (rc == HFZ_OK && mixed) mp_begin(B->inst[i]);
     }
     if (rc != HFZ_OK) break;
-    std::fill(B->h_active.begin(), B->h_active.end(), 1);
+    for (int i = 0; i < count; ++i) B->h_active[i] = filled[i];
     std::fill(cycles.begin(), cycles.end(), 0);
     rc = batch_write_active(B);
     if (rc != HFZ_OK) break;
@@ -1266,7 +1276,7 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
     }
     if (rc != HFZ_OK) break;
     for (int i = 0; i < count; ++i) {
-      if (failed[i]) continue;  // rolled back: the state is that of the previous step
+      if (!filled[i] || failed[i]) continue;  // failed: rolled back to the previous step's state
       rc = finish_step(B->inst[i]);
       if (rc != HFZ_OK) break;
       st[i].steps_done++;

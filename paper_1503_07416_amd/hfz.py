@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhfz.so")
 
 PFC, CDFT = 0, 1
 FP64, MIXED = 0, 1
+OK, EINVAL, ENOMEM, EDOMAIN, ENOCONV, ENAN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 
 ERRORS = {0: "HFZ_OK", -1: "HFZ_EINVAL", -2: "HFZ_ENOMEM", -3: "HFZ_EDOMAIN",
           -4: "HFZ_ENOCONV", -5: "HFZ_ENAN", -6: "HFZ_EHIP", -7: "HFZ_ESTATE"}
@@ -26,7 +27,7 @@ SYMBOLS = [
     "hfz_begin_step", "hfz_smooth", "hfz_vcycle", "hfz_residual", "hfz_finish_step",
     "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_destroy", "hfz_strerror",
     "hfz_batch_workspace_bytes", "hfz_batch_init", "hfz_batch_set_state", "hfz_batch_get_state",
-    "hfz_batch_energy", "hfz_batch_step", "hfz_batch_destroy",
+    "hfz_batch_energy", "hfz_batch_release", "hfz_batch_step", "hfz_batch_destroy",
 ]
 
 
@@ -91,6 +92,7 @@ def load():
         "hfz_batch_set_state": [vp, i, vp, vp, vp],
         "hfz_batch_get_state": [vp, i, vp, vp, vp],
         "hfz_batch_energy": [vp, i, P(d)],
+        "hfz_batch_release": [vp, i],
         "hfz_batch_step": [vp, i, P(Stats)],
         "hfz_batch_destroy": [vp],
     }
@@ -290,6 +292,9 @@ class Batch:
         out = (ctypes.c_double * 5)()
         check(self.lib.hfz_batch_energy(self.h, i, out), "hfz_batch_energy")
         return list(out)
+
+    def release(self, i):
+        check(self.lib.hfz_batch_release(self.h, i), "hfz_batch_release")
 
     def step(self, nsteps=1, raise_on_error=True):
         st = (Stats * self.count)()

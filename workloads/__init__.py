@@ -131,11 +131,12 @@ class Request:
 
 
 def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
-                   steps=(10, 200), precision="fp64"):
+                   steps=(10, 200), pfc_precision="mixed", cdft_precision="fp64"):
     """Poisson request stream: exponential inter-arrival times of mean 1/rate,
     model PFC or CDFT with probability 1/2 each, n ~ U{sizes},
-    steps ~ U{steps[0]..steps[1]}.  PFC requests are drawn as in ``config4``,
-    CDFT requests as in ``config3`` at their own size."""
+    steps ~ U{steps[0]..steps[1]}.  PFC requests are drawn as in ``config4``
+    (mixed precision by default), CDFT requests as in ``config3`` at their own
+    size (FP64 by default)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     reqs = []
@@ -146,10 +147,10 @@ def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
         if rng.uniform() < 0.5:
             rb = float(rng.uniform(NANO_RHO_L, NANO_RHO_S))
             cfg, rho, u, v = pfc_uniform_noise(n, NANO_H, 0.02, 5000 + i, rho_bar=rb,
-                                               alpha=1.0 - NANO_EPS, precision=precision)
+                                               alpha=1.0 - NANO_EPS, precision=pfc_precision)
         else:
             cfg, rho, u, v = cdft_gauss_noise(n, 17.0 / 128.0, 0.02, 5000 + i,
-                                              precision=precision)
+                                              precision=cdft_precision)
         reqs.append(Request(i, t, nst, cfg, rho, u, v))
     return reqs
 
