@@ -1,18 +1,36 @@
-"""Benchmark: time steps per second of the PFC 512^2 workload on one MI355X.
+"""Benchmark of the energy-stable FAS step on one MI355X.
 
-Workload (the paper's PFC freezing run scaled to 512^2): eps = 0.025, gamma = 2,
-h = 0.25, s = 0.01, rho = (3/2 - 0.07 sqrt 3) + 0.05 U(-1,1) (seed 0), u = v = 0,
-FAS V(2,2) with the damped red-black smoother to ||S - N(g)||_2 <= 1e-10, FP64.
+Headline (`value`): time steps per second of the PFC 512^2 workload: the
+paper's PFC freezing run scaled to 512^2, eps = 0.025, gamma = 2, h = 0.25,
+s = 0.01, rho = (3/2 - 0.07 sqrt 3) + 0.05 U(-1,1) (seed 0), u = v = 0, FAS
+V(2,2) with the damped red-black smoother to ||S - N(g)||_2 <= 1e-10, FP64.
 
-Prints ONE JSON line with the step throughput, the roofline figure of the
-dominant kernel (the finest-level smoother, timed with HIP events on the
-library's stream) and the CPU oracle timed on a bounded sample of the same
-workload.
+Also reported on the same JSON line:
+  roofline      the finest-level smoother (the LDS-tiled kernel doing two damped
+                red-black sweeps), algorithmic bytes / average launch time from
+                HIP events on the library's stream; `traffic` from the committed
+                FETCH_SIZE / WRITE_SIZE counter summary when it was taken from
+                the current kernel sources, else null;
+  cpu_baseline  the CPU oracle (NumPy FP64) on a bounded sample;
+  mixed         the same workload with FP32 smoothing inside FP64 defect
+                correction: steps/s and its distance from the FP64 result;
+  batched       256 PFC instances (eps = 0.4, n ~ U{64,128,256}, 20 steps,
+                mixed precision): instance-steps/s against the unbatched FP64
+                path, and the per-step energy check;
+  serving       a Poisson stream of PFC and CDFT requests (n ~ U{64..1024},
+                10-200 steps) through the continuous-batching server under a
+                device-memory budget: p50/p99 per-step latency, throughput;
+  cdft          CDFT 1024^2 (h = 17/128, s = 0.02), 50 steps with the energy
+                and mass read after every step.
 """
 import argparse
+import dataclasses
+import hashlib
 import json
 import os
+import re
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -22,26 +40,54 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one damped red-black sweep per fine node: read g (5),
 # f (5), rho^k, omega^k, write g (5), FP64
 SWEEP_BYTES_PFC = 17 * 8
+KERNEL_SOURCES = ["paper_1503_07416_amd/csrc/tile.hpp", "paper_1503_07416_amd/csrc/stencil.hpp",
+                  "paper_1503_07416_amd/csrc/kernels.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_pfc512_fp64_hbm_counters.md")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-cycles", type=int, default=10,
-                    help="V-cycles of the oracle sample")
+    ap.add_argument("--no-extras", action="store_true", help="headline and roofline only")
+    ap.add_argument("--cpu-cycles", type=int, default=10, help="V-cycles of the oracle sample")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="only launch the smoother and a reference copy kernel (for counter runs)")
     return ap.parse_args()
 
 
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per smoother launch from the committed counter summary, or
+    None if it is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != source_hash():
+        return None
+    return float(t.group(1))
+
+
 def smoother_roofline(sim, n, launches=25):
-    """Average duration of one finest-level smoother launch (the LDS-tiled
-    kernel doing two damped red-black sweeps, as in the V-cycle's
-    pre-smoothing), measured with HIP events on the stream the library
-    launches on."""
+    """Average duration of one finest-level smoother launch (two damped
+    red-black sweeps, as in the V-cycle's smoothing), measured with HIP
+    events on the stream the library launches on."""
     import torch
     stream = sim.stream
     sim.begin_step()
@@ -56,9 +102,30 @@ def smoother_roofline(sim, n, launches=25):
     bytes_launch = 2 * SWEEP_BYTES_PFC * n * n
     achieved = bytes_launch / t_launch / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_sweeps_tile<PFC,double,2 sweeps>", "launch_us": round(t_launch * 1e6, 3),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic() if n == 512 else None,
+            "kernel": "k_sweeps_tile<PFC, double, 2 sweeps>", "launch_us": round(t_launch * 1e6, 3),
             "bytes_per_launch": bytes_launch}
+
+
+def counter_probe(n):
+    """Five smoother launches at n^2 and three launches of a reference copy
+    kernel (torch elementwise multiply, 1 GiB read + 1 GiB written), for
+    the FETCH_SIZE / WRITE_SIZE counter runs."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v = workloads.pfc_uniform_noise(n, 0.25, 0.01, 0)
+    sim = pkg.Simulation(cfg, device="cuda:0")
+    sim.set_state(rho, u, v)
+    sim.begin_step()
+    sim.smooth(0, 10)
+    x = torch.ones(2**27, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_probe": True, "n": n, "smoother_launches": 5, "copy_bytes_each_way": 2**30,
+                      "source_hash": source_hash()}))
 
 
 def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
@@ -83,16 +150,217 @@ def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
                       f"({t2 - t0:.1f} s), scaled by {cycles_per_step:.2f} V-cycles/step"}
 
 
+def rel_diff(a, b):
+    import torch
+    out = []
+    for x, y in zip(a, b):
+        out.append(float((x - y).abs().max() / max(float(y.abs().max()), 1e-300)))
+    return max(out)
+
+
+def run_mixed(a, ref_state):
+    """Config 2 in mixed precision: steps/s and max relative distance of the
+    final state from the FP64 run's."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0, precision="mixed")
+    sim = pkg.Simulation(cfg, device="cuda:0")
+    sim.set_state(rho, u, v)
+    E = [sim.energy()[0]]
+    if a.warmup:
+        sim.step(a.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.step(a.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E.append(sim.energy()[0])
+    return {"steps_per_s": round(a.steps / dt, 3), "ms_per_step": round(1e3 * dt / a.steps, 4),
+            "outer_cycles_per_step": round(st.cycles_total / max(1, st.steps_done), 3),
+            "max_rel_diff_vs_fp64": rel_diff(sim.get_state(), ref_state),
+            "energy_decreased": bool(E[1] <= E[0]), "tol": 1e-10}
+
+
+def run_batched(steps=20, count=256):
+    """Config 4: one batch per grid size on its own stream, stepped
+    concurrently; then the same instances one at a time through the unbatched
+    FP64 path (a sample of 16), and an untimed rerun of the batches one step at
+    a time reading every instance's energy after each step."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    inst = workloads.config4(count)
+    groups = {}
+    for c, r, u, v in inst:
+        groups.setdefault(c.n, []).append((c, r, u, v))
+
+    def make():
+        out = []
+        for n in sorted(groups):
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                out.append((pkg.Batch([c for c, _, _, _ in groups[n]], stream=s), s, n))
+        return out
+
+    def load(batches):
+        for B, s, n in batches:
+            with torch.cuda.stream(s):
+                for k, (c, r, u, v) in enumerate(groups[n]):
+                    B.set_state(k, r, u, v)
+        torch.cuda.synchronize()
+
+    batches = make()
+    load(batches)
+    for B, s, _ in batches:          # warm-up step (captures each batch's V-cycle graph)
+        with torch.cuda.stream(s):
+            B.step(1)
+    load(batches)
+    res = {}
+
+    def run(k, nsteps):
+        B, s, _ = batches[k]
+        with torch.cuda.stream(s):
+            res[k] = B.step(nsteps)
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=run, args=(k, steps)) for k in range(len(batches))]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    cycles = np.mean([s.cycles_total / steps for k in res for s in res[k]])
+    # unbatched FP64 path on a sample
+    sub = inst[::count // 16]
+    tu = 0.0
+    for c, r, u, v in sub:
+        sim = pkg.Simulation(dataclasses.replace(c, precision="fp64"))
+        sim.set_state(r, u, v)
+        sim.step(1)
+        sim.set_state(r, u, v)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        tu += time.perf_counter() - t1
+        sim.close()
+    unb = len(sub) * steps / tu
+    # energy check, untimed: the same instances again, one step at a time
+    load(batches)
+    viol = 0
+    for B, s, _ in batches:
+        with torch.cuda.stream(s):
+            E = [B.energy(i)[0] for i in range(B.count)]
+            for _ in range(steps):
+                B.step(1)
+                for i in range(B.count):
+                    e = B.energy(i)[0]
+                    if e > E[i] + 1e-10 * max(1.0, abs(E[i])):
+                        viol += 1
+                    E[i] = e
+    for B, _, _ in batches:
+        B.close()
+    return {"workload": f"{count} PFC instances, eps=0.4, h=pi/(2 sqrt 3), s=0.02, n~U{{64,128,256}}, "
+                        f"{steps} steps, mixed precision, tol 1e-10",
+            "solves_per_s": round(count * steps / T, 1), "seconds": round(T, 4),
+            "unbatched_fp64_solves_per_s": round(unb, 1), "unbatched_sample": len(sub),
+            "speedup_vs_unbatched_fp64": round(count * steps / T / unb, 2),
+            "mean_cycles_per_step": round(float(cycles), 3),
+            "energy_increases": viol, "energy_checks": count * steps}
+
+
+def run_serving(requests, budget_gib):
+    """Config 5: pilot per class (alone, FP64 CDFT / mixed PFC) for the mean
+    residence time, arrival rate from Little's law for 80% of the budget,
+    then the stream through the server."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    from paper_1503_07416_amd.serve import DeviceBackend, Server
+    be = DeviceBackend("cuda:0")
+    budget = int(budget_gib * 2**30)
+    sizes = (64, 128, 256, 512, 1024)
+    t_alone, slot = {}, {}
+    for model in ("pfc", "cdft"):
+        for n in sizes:
+            if model == "pfc":
+                cfg, r, u, v = workloads.pfc_uniform_noise(n, workloads.NANO_H, 0.02, 77, rho_bar=0.8,
+                                                           alpha=1 - workloads.NANO_EPS, precision="mixed")
+            else:
+                cfg, r, u, v = workloads.cdft_gauss_noise(n, 17 / 128, 0.02, 77)
+            sim = pkg.Simulation(cfg, device="cuda:0")
+            sim.set_state(r, u, v)
+            sim.step(1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sim.step(3)
+            torch.cuda.synchronize()
+            t_alone[(model, n)] = (time.perf_counter() - t) / 3
+            slot[(model, n)] = be.pool_bytes(pkg.make_params(cfg), 1)
+            sim.close()
+    e_bytes = float(np.mean(list(slot.values())))
+    e_res = 105.0 * float(np.mean(list(t_alone.values())))
+    lam = 0.8 * budget / (e_bytes * e_res)
+    reqs = workloads.serving_stream(requests, rate=lam, seed=0)
+    alone = sum(t_alone[(r.cfg.model, r.cfg.n)] * r.steps for r in reqs)
+    srv = Server(budget, backend=be, check_energy=True)
+    _, rep = srv.run(reqs, realtime=True)
+    rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+    rep.update({"workload": f"{requests} requests, PFC (mixed, as the batched workload) / CDFT (FP64, h=17/128, "
+                            "s=0.02) 50/50, n~U{64..1024}, steps~U{10..200}, Poisson arrivals, seed 0",
+                "arrival_rate_per_s": round(lam, 3), "mean_slot_bytes": int(e_bytes),
+                "mean_residence_alone_s": round(e_res, 4),
+                "sequential_alone_s": round(alone, 3),
+                "speedup_vs_sequential_alone": round(alone / rep["makespan_s"], 3)})
+    return rep
+
+
+def run_cdft(steps=50, n=1024):
+    """Config 3: CDFT 1024^2 FP64, energy and mass read after every step
+    (inside the timed region: they are part of this workload)."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v = workloads.config3(0, n=n)
+    sim = pkg.Simulation(cfg, device="cuda:0")
+    sim.set_state(rho, u, v)
+    E = [sim.energy()]
+    M = [sim.mass()]
+    cyc = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = sim.step(1)
+        cyc += st.cycles_total
+        E.append(sim.energy())
+        M.append(sim.mass())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inc = sum(1 for a, b in zip(E[:-1], E[1:]) if b[0] > a[0] + 1e-10 * max(1.0, abs(a[0])))
+    return {"workload": f"CDFT {n}^2 h=17/128 s=0.02 nu=2.362 FP64 tol 1e-10, {steps} steps",
+            "steps_per_s": round(steps / dt, 3), "vcycles_per_step": round(cyc / steps, 3),
+            "E_first": E[0][0], "E_last": E[-1][0], "F_id_last": E[-1][3], "F_ex_last": E[-1][4],
+            "KE_last": E[-1][1], "energy_increases": inc,
+            "mass_rel_drift": max(abs(m - M[0]) for m in M) / abs(M[0])}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the solver runs on a single device; --gpus must be 1"}))
         sys.exit(2)
+    if a.counter_probe:
+        counter_probe(a.n)
+        return
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
 
-    cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0, precision=a.precision)
+    cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E0 = sim.energy()[0]
@@ -105,24 +373,32 @@ def main():
     t1 = time.perf_counter()
     E1 = sim.energy()[0]
     mass = sim.mass()
+    state = sim.get_state()
     dt = t1 - t0
-    steps_per_s = a.steps / dt
     cps = st.cycles_total / max(1, st.steps_done)
     roof = smoother_roofline(sim, a.n)
     out = {
         "metric": "time steps/sec + smoother HBM GB/s at 512^2; batched solves/sec, p50/p99 latency",
-        "value": round(steps_per_s, 3), "unit": "time steps/s", "n_gpus": 1, "steps": a.steps,
+        "value": round(a.steps / dt, 3), "unit": "time steps/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(1e3 * dt / a.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"PFC {a.n}^2 h=0.25 s=0.01 eps=0.025 FAS V(2,2) tol 1e-10 {a.precision}",
-                   "n": a.n, "precision": a.precision, "vcycles_per_step": round(cps, 3),
-                   "final_residual": st.residual_last, "energy_decreased": bool(E1 <= E0),
-                   "mass": mass},
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"PFC {a.n}^2 h=0.25 s=0.01 eps=0.025 FAS V(2,2) tol 1e-10 FP64",
+                   "n": a.n, "vcycles_per_step": round(cps, 3), "final_residual": st.residual_last,
+                   "energy_decreased": bool(E1 <= E0), "mass": mass},
         "roofline": roof,
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, rho, u, v, cps, a.cpu_cycles)
+    if not a.no_extras:
+        sim.close()
+        out["mixed"] = run_mixed(a, state)
+        del state
+        torch.cuda.empty_cache()
+        out["batched"] = run_batched()
+        torch.cuda.empty_cache()
+        out["cdft"] = run_cdft()
+        torch.cuda.empty_cache()
+        out["serving"] = run_serving(a.serve_requests, a.serve_budget_gib)
     print(json.dumps(out))
 
 

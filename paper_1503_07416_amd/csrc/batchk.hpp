@@ -15,7 +15,7 @@ __global__ void k_residual_partial_b(const Lvl<double>* Ls, const Phys<double>* 
   __shared__ double lds[16];
   const int z = blockIdx.z;
   if (!active[z]) return;
-  const Lvl<double> L = Ls[z];
+  const Lvl<double> L = lvl_global(Ls[z]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   double acc = 0.0;
@@ -42,8 +42,8 @@ __global__ void k_mp_prepare_b(const Lvl<double>* Ls, const Phys<double>* Ps, co
   __shared__ double lds[16];
   const int z = blockIdx.z;
   if (!active[z]) return;
-  const Lvl<double> L = Ls[z];
-  const Lvl<float> E = Es[z];
+  const Lvl<double> L = lvl_global(Ls[z]);
+  const Lvl<float> E = lvl_global(Es[z]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   double acc = 0.0;
@@ -70,12 +70,12 @@ template <int MODEL>
 __global__ void k_mp_update_b(const Lvl<double>* Ls, const Lvl<float>* Es, const int* active) {
   const int z = blockIdx.z;
   if (!active[z]) return;
-  const Lvl<double> L = Ls[z];
+  const Lvl<double> L = lvl_global(Ls[z]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= L.n || j >= L.n) return;
   const int p = (j << L.lg) + i;
-  const Lvl<float> E = Es[z];
+  const Lvl<float> E = lvl_global(Es[z]);
 #pragma unroll
   for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][p] += (double)E.g[c][p];
 }
@@ -85,10 +85,12 @@ template <typename T>
 __global__ void k_swap_back_b(const Lvl<T>* Ls, const int* active, int nc) {
   const int z = blockIdx.z;
   if (!active[z]) return;
-  const Lvl<T> L = Ls[z];
+  const Lvl<T> L = lvl_global(Ls[z]);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.n * L.n) return;
-  for (int c = 0; c < nc; ++c) L.g[c][t] = L.gb[c][t];
+#pragma unroll
+  for (int c = 0; c < 5; ++c)
+    if (c < nc) L.g[c][t] = L.gb[c][t];
 }
 
 // norm2[z] = h_z^2 * (sum of instance z's `count` partials), fixed order;

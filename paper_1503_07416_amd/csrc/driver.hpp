@@ -59,6 +59,14 @@ template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, 
   }
 }
 
+// Whether the tail from a level of size top_n with nt levels fits in the LDS
+// the tail kernel may use (every tail level is held in LDS).  Grids of 16^2
+// and below always fit.
+template <int MODEL, typename T, bool CORR> bool tail_fits(int top_n, int nt, size_t lds_max) {
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
+  return nt <= TAIL_MAX_LEVELS && tail_lds_count<NCm, NB>(top_n, nt) * sizeof(T) <= lds_max;
+}
+
 template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
   TailArgs<T> A{};
@@ -68,11 +76,7 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu1 = K.nu1;
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
-  // as many of the coarsest tail levels in LDS as the opted-in LDS holds
-  A.nlds = 0;
-  for (int k = 1; k <= A.nt; ++k)
-    if (tail_lds_count<NCm, NB>(A.top_n, A.nt, k) * sizeof(T) <= H.tail_lds_max) A.nlds = k;
-  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.nlds) * sizeof(T);
+  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt) * sizeof(T);
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 
@@ -163,7 +167,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
 
 template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l) {
   const int nlev = (int)H.L.size(), last = nlev - 1;
-  if (H.L[l].n <= K.tail_n && nlev - l <= TAIL_MAX_LEVELS) {
+  if (H.L[l].n <= K.tail_n && tail_fits<MODEL, T, CORR>(H.L[l].n, nlev - l, H.tail_lds_max)) {
     tail_launch<MODEL, T, CORR>(H, K, l);
     return;
   }

@@ -955,7 +955,7 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
                  const Cycle& K, int l) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
   const int nlev = (int)R.size(), count = B->count;
-  if (R[l].n <= K.tail_n && nlev - l <= TAIL_MAX_LEVELS) {
+  if (R[l].n <= K.tail_n && tail_fits<MODEL, T, CORR>(R[l].n, nlev - l, lds_max)) {
     TailArgs<T> A{};
     A.Lg = Tl + l;
     A.nt = nlev - l;
@@ -963,10 +963,7 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
     A.nu1 = K.nu1;
     A.nu2 = K.nu2;
     A.coarse_sweeps = K.coarse_sweeps;
-    A.nlds = 0;
-    for (int k = 1; k <= A.nt; ++k)
-      if (tail_lds_count<NCm, NB>(A.top_n, A.nt, k) * sizeof(T) <= lds_max) A.nlds = k;
-    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.nlds) * sizeof(T);
+    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt) * sizeof(T);
     k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
     return;
   }
@@ -1166,8 +1163,13 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
     p64[i] = h->H.P;
     p32[i] = h->H32.P;
   }
-  B->lds64 = B->inst[0]->H.tail_lds_max;
-  B->lds32 = B->inst[0]->H32.tail_lds_max;
+  if (B->p.model == HFZ_PFC) {
+    B->lds64 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<PFC, double, false>));
+    B->lds32 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<PFC, float, true>));
+  } else {
+    B->lds64 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, double, false>));
+    B->lds32 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, float, true>));
+  }
   B->h_active.assign(count, 1);
   B->h_norm2.assign(count, 0.0);
   bool ok = hipMemcpyAsync(B->D64, d64.data(), d64.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,

@@ -6,6 +6,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace hfz {
 
 enum { PFC = 0, CDFT = 1 };
@@ -42,6 +44,47 @@ template <typename T> struct Lvl {
   T h;        // spacing h_l
   Coef<T> k;  // stencil coefficients of this level
 };
+
+// Address-space views.  A pointer loaded from memory (a level descriptor in a
+// device array or in LDS) is generic to the compiler, so its loads and stores
+// become FLAT instructions, which wait on both the vector-memory and the LDS
+// counters.  These views tell the compiler where the data lives so that it
+// emits global_* / ds_* instructions: global through an integer round trip
+// into an address_space(1) pointer, LDS through an assumption the address
+// space inference uses.  Only apply them to pointers that do point there.
+// (The host pass of the single-source compile sees only the plain pointer.)
+template <typename T> __device__ __forceinline__ T* as_global(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return (T*)((__attribute__((address_space(1))) T*)(uintptr_t)p);
+#else
+  return p;
+#endif
+}
+template <typename T> __device__ __forceinline__ T* as_lds(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_assume(__builtin_amdgcn_is_shared((const void*)p));
+#endif
+  return p;
+}
+
+// A level whose arrays are all in global memory (descriptor loaded from a
+// device array); null pointers stay null.
+template <typename T> __device__ __forceinline__ Lvl<T> lvl_global(const Lvl<T>& s) {
+  Lvl<T> L = s;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    L.g[c] = as_global(s.g[c]);
+    L.f[c] = as_global(s.f[c]);
+    L.g0[c] = as_global(s.g0[c]);
+    L.d[c] = as_global(s.d[c]);
+    L.gb[c] = as_global(s.gb[c]);
+  }
+  L.rk = as_global(s.rk);
+  L.om = as_global(s.om);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) L.bg[c] = as_global(s.bg[c]);
+  return L;
+}
 
 // Neighbour offsets of node (i, j).
 struct Nbr {

@@ -18,63 +18,76 @@ constexpr int TAIL_THREADS = 512;
 
 template <typename T> struct TailArgs {
   const Lvl<T>* Lg;  // device array of the tail's level descriptors; [0] = tail top
-  int nt;            // levels in the tail
-  int nlds;          // the last nlds of them are held in LDS, the others stay global
+  int nt;            // levels in the tail, all held in LDS
   int top_n;         // size of the tail top
   int nu1, nu2, coarse_sweeps;
 };
 
-// T values of LDS that the bottom `nlds` of `nt` tail levels need (top size
-// top_n): g, f, rk, om per level, plus g0 for all but the tail top.
-// NB = 3 in the correction form (the base state rho, u, v), else 0.
+// T values of LDS that `nt` tail levels need (top size top_n): g, f, rk, om
+// per level, plus g0 for all but the tail top.  NB = 3 in the correction form
+// (the base state rho, u, v), else 0.
 template <int NCm, int NB = 0>
-__host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int nlds) {
+__host__ __device__ inline size_t tail_lds_count(int top_n, int nt) {
   size_t tot = 0;
   int n = top_n;
   for (int l = 0; l < nt; ++l) {
-    const size_t cnt = (size_t)n * n;
-    if (l >= nt - nlds) tot += cnt * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
+    tot += (size_t)n * n * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
     n >>= 1;
   }
   return tot;
 }
 
-// Level descriptors of the tail: S = the arrays the phases use (LDS for the
-// bottom nlds levels, global above them), G = the global arrays.  Thread t
-// builds level t (same LDS order as tail_lds_count).
+// Level descriptors of the tail: S = the LDS arrays the phases use, G = the
+// global arrays.  Thread t builds level t (same LDS order as tail_lds_count).
 template <int NCm, int NB, typename T>
 __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S, Lvl<T>* G) {
   const int t = threadIdx.x;
   if (t >= A.nt) return;
   Lvl<T> s = A.Lg[t];
   G[t] = s;
-  const int first = A.nt - A.nlds;
-  if (t >= first) {
-    size_t off = 0;
-    for (int l = first; l < t; ++l) {
-      const size_t nl = (size_t)(A.top_n >> l);
-      off += nl * nl * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
-    }
-    T* p = base + off;
-    const int cnt = s.n * s.n;
-#pragma unroll
-    for (int c = 0; c < NCm; ++c) s.g[c] = p + c * cnt;
-    p += NCm * cnt;
-#pragma unroll
-    for (int c = 0; c < NCm; ++c) s.f[c] = p + c * cnt;
-    p += NCm * cnt;
-    if (t > 0) {
-#pragma unroll
-      for (int c = 0; c < NCm; ++c) s.g0[c] = p + c * cnt;
-      p += NCm * cnt;
-    }
-    s.rk = p;
-    s.om = p + cnt;
-    p += 2 * cnt;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) s.bg[c] = p + c * cnt;
+  size_t off = 0;
+  for (int l = 0; l < t; ++l) {
+    const size_t nl = (size_t)(A.top_n >> l);
+    off += nl * nl * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
   }
+  T* p = base + off;
+  const int cnt = s.n * s.n;
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) s.g[c] = p + c * cnt;
+  p += NCm * cnt;
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) s.f[c] = p + c * cnt;
+  p += NCm * cnt;
+  if (t > 0) {
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) s.g0[c] = p + c * cnt;
+    p += NCm * cnt;
+  }
+  s.rk = p;
+  s.om = p + cnt;
+  p += 2 * cnt;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) s.bg[c] = p + c * cnt;
   S[t] = s;
+}
+
+// The view the phases use of a tail level built by tail_lds_levels: its
+// arrays in LDS (g0 only below the top, G0 = true), the residual scratch d in
+// global memory.
+template <int NCm, int NB, bool G0, typename T> __device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
+  Lvl<T> L = s;
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) {
+    L.g[c] = as_lds(s.g[c]);
+    L.f[c] = as_lds(s.f[c]);
+    if constexpr (G0) L.g0[c] = as_lds(s.g0[c]);
+    L.d[c] = as_global(s.d[c]);
+  }
+  L.rk = as_lds(s.rk);
+  L.om = as_lds(s.om);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) L.bg[c] = as_lds(s.bg[c]);
+  return L;
 }
 
 template <int MODEL, typename T, bool CORR>
@@ -191,34 +204,44 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
   tail_lds_levels<NCm, NB, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
   __syncthreads();
-  const bool top_in_lds = A.nlds == A.nt;
-  if (top_in_lds) {
-    const int cnt = G[0].n * G[0].n;
+  {
+    const Lvl<T> s = tail_view<NCm, NB, false>(S[0]);
+    const Lvl<T> g = lvl_global(G[0]);
+    const int cnt = g.n * g.n;
+#pragma unroll
     for (int c = 0; c < NCm; ++c) {
-      tail_copy(S[0].g[c], G[0].g[c], cnt);
-      tail_copy(S[0].f[c], G[0].f[c], cnt);
+      tail_copy(s.g[c], g.g[c], cnt);
+      tail_copy(s.f[c], g.f[c], cnt);
     }
-    for (int c = 0; c < NB; ++c) tail_copy(S[0].bg[c], G[0].bg[c], cnt);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) tail_copy(s.bg[c], g.bg[c], cnt);
   }
-  for (int l = A.nt - A.nlds; l < A.nt; ++l) {
-    const int cnt = G[l].n * G[l].n;
-    tail_copy(S[l].rk, G[l].rk, cnt);
-    tail_copy(S[l].om, G[l].om, cnt);
+  for (int l = 0; l < A.nt; ++l) {
+    const Lvl<T> s = tail_view<NCm, NB, false>(S[l]);
+    const Lvl<T> g = lvl_global(G[l]);
+    const int cnt = g.n * g.n;
+    tail_copy(s.rk, g.rk, cnt);
+    tail_copy(s.om, g.om, cnt);
   }
   __syncthreads();
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
-    tail_sweeps<MODEL, T, CORR>(S[l], P, A.nu1);
-    tail_restrict<MODEL, T, CORR>(S[l], S[l + 1], P);
+    const Lvl<T> F = tail_view<NCm, NB, false>(S[l]);
+    tail_sweeps<MODEL, T, CORR>(F, P, A.nu1);
+    tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
   }
-  tail_sweeps<MODEL, T, CORR>(S[last], P, A.coarse_sweeps);
+  tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, false>(S[last]), P, A.coarse_sweeps);
   for (int l = last - 1; l >= 0; --l) {
-    tail_prolong<MODEL, T, CORR>(S[l], S[l + 1], P);
-    tail_sweeps<MODEL, T, CORR>(S[l], P, A.nu2);
+    const Lvl<T> F = tail_view<NCm, NB, false>(S[l]);
+    tail_prolong<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
+    tail_sweeps<MODEL, T, CORR>(F, P, A.nu2);
   }
-  if (top_in_lds) {
-    const int cnt = G[0].n * G[0].n;
-    for (int c = 0; c < NCm; ++c) tail_copy(G[0].g[c], S[0].g[c], cnt);
+  {
+    const Lvl<T> s = tail_view<NCm, NB, false>(S[0]);
+    const Lvl<T> g = lvl_global(G[0]);
+    const int cnt = g.n * g.n;
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) tail_copy(g.g[c], s.g[c], cnt);
   }
 }
 
@@ -235,7 +258,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_b(TailArgs<T> A, int stri
   const int z = blockIdx.x;
   if (!active[z]) return;
   TailArgs<T> B = A;
-  B.Lg = A.Lg + (size_t)z * stride;
+  B.Lg = as_global(A.Lg + (size_t)z * stride);
   tail_body<MODEL, T, CORR>(B, Ps[z]);
 }
 

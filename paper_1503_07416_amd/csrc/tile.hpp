@@ -178,14 +178,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile_b(const Lvl<T>* Ls
                                                                 double* partial, int pstride) {
   const int z = blockIdx.z;
   if (!active[z]) return;
-  const Lvl<T> L = Ls[z];
+  const Lvl<T> L = lvl_global(Ls[z]);
   Fld<T> a{}, b{};
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     a.c[c] = L.g[c];
     b.c[c] = L.gb[c];
   }
-  const Lvl<T> C = PRO ? Cs[z] : L;
+  const Lvl<T> C = PRO ? lvl_global(Cs[z]) : L;
   sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR>(L, inb ? b : a, inb ? a : b, C, Ps[z],
                                                   partial + (size_t)z * pstride);
 }
@@ -267,12 +267,12 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile_b(const Lvl<
                                                                       int inb) {
   const int z = blockIdx.z;
   if (!active[z]) return;
-  Lvl<T> F = Fs[z];
+  Lvl<T> F = lvl_global(Fs[z]);
   if (inb) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) F.g[c] = F.gb[c];
   }
-  restrict_fas_body<MODEL, T, CORR>(F, Cs[z], Ps[z]);
+  restrict_fas_body<MODEL, T, CORR>(F, lvl_global(Cs[z]), Ps[z]);
 }
 
 }  // namespace hfz
