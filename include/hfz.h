@@ -157,6 +157,13 @@ int hfz_write_field(hfz_handle* hd, int which, int level, int comp, const double
 /* Number of grid levels and the CDFT scalar (J_e * 1) (0 for PFC). */
 int hfz_info(hfz_handle* hd, int* levels, double* ce);
 
+/* Tile shape of the LDS-tiled sweep kernel on an FP64 level: tx x ty owned
+ * nodes per workgroup of `threads` threads, picked at hfz_init by timing the
+ * shapes that cover the level (environment: HFZ_TILE=<0..3> forces a shape,
+ * HFZ_TUNE=0 keeps shape 0).  The swept values do not depend on the shape.
+ * HFZ_EINVAL for a level the tiled kernel does not sweep (the coarse tail). */
+int hfz_tile_shape(hfz_handle* hd, int level, int* tx, int* ty, int* threads);
+
 int hfz_destroy(hfz_handle* hd);
 const char* hfz_strerror(int code);
 

@@ -21,6 +21,7 @@ template <typename T> struct Hier {
   std::vector<Lvl<T>> L;    // finest first
   Lvl<T>* desc = nullptr;   // device copy of L (the tail kernel reads it)
   size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use
+  std::vector<int> tile_shape;  // tile shape of the sweep kernel per level (tile.hpp)
   Phys<T> P{};
 };
 
@@ -80,16 +81,37 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 
-template <int MODEL, typename T, bool CORR, int NSW, bool PRO>
-void tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out, const Lvl<T>& C,
-                 int res) {
-  const dim3 grid(L.n / TILE_X, L.n / TILE_Y);
+// Launches the tiled sweep kernel of shape ts on level L; returns its
+// number of workgroups (= stop-test partial sums when res == 2).
+template <int MODEL, typename T, bool CORR, int NSW, bool PRO, int TS>
+int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
+                      const Lvl<T>& C, int res) {
+  constexpr TileShape S = kTileShapes[TS];
+  const dim3 grid(L.n / S.tx, L.n / S.ty);
   if (res == 1)
-    k_sweeps_tile<MODEL, T, NSW, PRO, 1, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+    k_sweeps_tile<MODEL, T, NSW, PRO, 1, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
   else if (res == 2)
-    k_sweeps_tile<MODEL, T, NSW, PRO, 2, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+    k_sweeps_tile<MODEL, T, NSW, PRO, 2, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
   else
-    k_sweeps_tile<MODEL, T, NSW, PRO, 0, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+    k_sweeps_tile<MODEL, T, NSW, PRO, 0, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+  return (int)(grid.x * grid.y);
+}
+
+// Whether tile shape ts covers an n x n level exactly.
+inline bool tile_shape_fits(int ts, int n) {
+  return ts >= 0 && ts < NUM_TILE_SHAPES && n % kTileShapes[ts].tx == 0 && n % kTileShapes[ts].ty == 0;
+}
+
+template <int MODEL, typename T, bool CORR, int NSW, bool PRO>
+int tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out, const Lvl<T>& C,
+                int res, int ts) {
+  if (!tile_shape_fits(ts, L.n)) ts = 0;
+  switch (ts) {
+    case 1: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 1>(H, K, L, in, out, C, res);
+    case 2: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 2>(H, K, L, in, out, C, res);
+    case 3: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 3>(H, K, L, in, out, C, res);
+    default: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 0>(H, K, L, in, out, C, res);
+  }
 }
 
 // `sweeps` tiled sweeps of level l from cur into the other buffer and back
@@ -98,28 +120,31 @@ void tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const 
 // (res_last: 1 the field d, 2 stop-test partial sums).  On return cur names
 // the buffer holding the iterate.
 template <int MODEL, typename T, bool CORR>
-void tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur, Fld<T>& other,
-                  int res_last = 0) {
+int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur, Fld<T>& other,
+                 int res_last = 0) {
   const Lvl<T>& L = H.L[l];
   const Lvl<T>& C = H.L[std::min<size_t>(l + 1, H.L.size() - 1)];
+  const int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
+  int blocks = 0;
   while (sweeps > 0) {
     const int nsw = sweeps >= 2 ? 2 : 1;
     const int res = (sweeps == nsw) ? res_last : 0;
     if (nsw == 2) {
       if (pro)
-        tile_launch<MODEL, T, CORR, 2, true>(H, K, L, cur, other, C, res);
+        blocks = tile_launch<MODEL, T, CORR, 2, true>(H, K, L, cur, other, C, res, ts);
       else
-        tile_launch<MODEL, T, CORR, 2, false>(H, K, L, cur, other, C, res);
+        blocks = tile_launch<MODEL, T, CORR, 2, false>(H, K, L, cur, other, C, res, ts);
     } else {
       if (pro)
-        tile_launch<MODEL, T, CORR, 1, true>(H, K, L, cur, other, C, res);
+        blocks = tile_launch<MODEL, T, CORR, 1, true>(H, K, L, cur, other, C, res, ts);
       else
-        tile_launch<MODEL, T, CORR, 1, false>(H, K, L, cur, other, C, res);
+        blocks = tile_launch<MODEL, T, CORR, 1, false>(H, K, L, cur, other, C, res, ts);
     }
     std::swap(cur, other);
     sweeps -= nsw;
     pro = false;
   }
+  return blocks;  // workgroups of the last launch
 }
 
 template <typename T> void copy_fields(Cycle& K, const Fld<T>& a, const Fld<T>& b, int nc, size_t cnt) {
@@ -154,8 +179,8 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
     // post-sweeps; on the finest level of the FP64 solve the last one also
     // leaves the partial sums of the stop-test residual
     const bool norm = (l == 0 && !CORR);
-    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
-    if (norm) K.norm_partials = (L.n / TILE_X) * (L.n / TILE_Y);
+    const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
+    if (norm) K.norm_partials = blocks;
   } else {
     if constexpr (!CORR) {
       const dim3 b = block2(F.n, F.n);

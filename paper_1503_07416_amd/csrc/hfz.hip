@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "batchk.hpp"
 #include "driver.hpp"
+#include "tune.hpp"
 
 using namespace hfz;
 
@@ -645,9 +646,23 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
     hd->use_tiles = true;
     if (hd->tail_n < 16) hd->tail_n = 32;
   }
-  if (std::getenv("HFZ_VERBOSE"))
-    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d\n", p->n, hd->nlev,
+  if (hd->use_tiles) {
+    const Cycle K = cycle_ctx(hd);
+    if (p->model == HFZ_PFC) {
+      tune_tile_shapes<PFC, double, false>(hd->H, K);
+      if (p->precision == HFZ_MIXED) tune_tile_shapes<PFC, float, true>(hd->H32, K);
+    } else {
+      tune_tile_shapes<CDFT, double, false>(hd->H, K);
+      if (p->precision == HFZ_MIXED) tune_tile_shapes<CDFT, float, true>(hd->H32, K);
+    }
+  }
+  if (std::getenv("HFZ_VERBOSE")) {
+    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p->n, hd->nlev,
                  hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
+    for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
+    for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
+    std::fprintf(stderr, "\n");
+  }
   if (p->model == HFZ_CDFT) {
     rc = cdft_setup(hd);
     if (rc != HFZ_OK) {
@@ -849,6 +864,19 @@ int hfz_info(hfz_handle* hd, int* levels, double* ce) {
   if (!hd) return HFZ_EINVAL;
   if (levels) *levels = hd->nlev;
   if (ce) *ce = hd->ce;
+  return HFZ_OK;
+}
+
+int hfz_tile_shape(hfz_handle* hd, int level, int* tx, int* ty, int* threads) {
+  if (!hd || !tx || !ty || !threads || level < 0 || level >= (int)hd->H.tile_shape.size()) return HFZ_EINVAL;
+  const int n = hd->H.L[level].n;
+  if (!hd->use_tiles || level + 1 >= hd->nlev || n < TILE_X || hd->H.L[level + 1].n < RTILE || n <= hd->tail_n)
+    return HFZ_EINVAL;
+  int ts = hd->H.tile_shape[level];
+  if (!tile_shape_fits(ts, n)) ts = 0;
+  *tx = kTileShapes[ts].tx;
+  *ty = kTileShapes[ts].ty;
+  *threads = kTileShapes[ts].nt;
   return HFZ_OK;
 }
 

@@ -24,9 +24,19 @@
 
 namespace hfz {
 
-constexpr int TILE_X = 32;
-constexpr int TILE_Y = 16;
-constexpr int TILE_THREADS = 256;
+// Tile shapes of the sweep kernel: TX x TY owned nodes per workgroup of NT
+// threads.  Shape 0 is the default (and the only one the batched kernels use);
+// the tuner (tune.hpp) picks a shape per level by timing.  The swept values
+// do not depend on the shape; only the grouping of the stop-test partial sums
+// does.
+struct TileShape {
+  int tx, ty, nt;
+};
+constexpr int NUM_TILE_SHAPES = 4;
+constexpr TileShape kTileShapes[NUM_TILE_SHAPES] = {{32, 16, 256}, {32, 16, 512}, {64, 16, 512}, {16, 16, 256}};
+constexpr int TILE_X = kTileShapes[0].tx;
+constexpr int TILE_Y = kTileShapes[0].ty;
+constexpr int TILE_THREADS = kTileShapes[0].nt;
 constexpr int RTILE = 16;  // coarse tile edge of the restriction kernel
 
 template <typename T> struct Fld {
@@ -38,11 +48,12 @@ template <typename T> struct Fld {
 // 2 the block's partial sum of |d|^2 written to partial[block] (the stop test).
 // A residual needs the swept values one node beyond the block, hence the
 // extra halo node.
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
                                                  const Lvl<T>& C, const Phys<T>& P, double* partial) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? 3 : 1;
+  constexpr int TILE_X = kTileShapes[TS].tx, TILE_Y = kTileShapes[TS].ty, TILE_THREADS = kTileShapes[TS].nt;
   constexpr int H = 2 * NSW + (RES ? 1 : 0);
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
@@ -162,10 +173,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   }
 }
 
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
-__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
-                                                              Phys<T> P, double* partial) {
-  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR>(L, gin, gout, C, P, partial);
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
+__global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
+                                                                    Phys<T> P, double* partial) {
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
 }
 
 // Batched form: instance blockIdx.z of equally sized instances, descriptors in

@@ -1,0 +1,104 @@
+// Tile-shape tuner of the tiled sweep kernel.
+//
+// The best tile shape depends on the level size: small levels have too few
+// workgroups to fill the device and want small, quick tiles; large levels want
+// wide tiles (less recomputed halo per owned node) and more threads per
+// workgroup.  For every level the V-cycle sweeps with the tiled kernel, the
+// tuner times the level's pre-smoothing launch (two sweeps and the residual
+// field) in every tile shape that covers the level, with HIP events on the
+// handle's stream, and keeps the fastest.  The kernels' speed does not depend
+// on the values they sweep, so the tuner runs on the workspace as it is; it
+// writes only the second iterate buffer and the residual scratch of the level.
+// Choices are cached per (model, arithmetic type, form, level size) for the
+// life of the process.  HFZ_TILE=<shape> forces one shape where it fits,
+// HFZ_TUNE=0 keeps shape 0.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "driver.hpp"
+
+namespace hfz {
+
+inline std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+inline std::map<std::tuple<int, int, int, int>, int>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int>, int> c;
+  return c;
+}
+
+// Average time (ms) of `reps` pre-smoothing launches of shape ts on level l,
+// after one untimed launch; negative on a HIP error.
+template <int MODEL, typename T, bool CORR>
+float time_shape(Hier<T>& H, Cycle& K, int l, int ts, int reps) {
+  const Lvl<T>& L = H.L[l];
+  const Lvl<T>& C = H.L[l + 1];
+  const Fld<T> a = fld<T>(L.g), b = fld<T>(L.gb);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+    bool ok = hipEventRecord(e0, K.stream) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+    ok = ok && hipEventRecord(e1, K.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipGetLastError() == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.0f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return ms;
+}
+
+// Fills H.tile_shape for the levels the tiled V-cycle visits (size >= 32
+// with a coarser level of >= 16, above the tail).
+template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cycle K) {
+  const int nlev = (int)H.L.size();
+  H.tile_shape.assign(nlev, 0);
+  int forced = -1;
+  if (const char* e = std::getenv("HFZ_TILE")) forced = std::atoi(e);
+  bool tune = true;
+  if (const char* e = std::getenv("HFZ_TUNE")) tune = std::atoi(e) != 0;
+  for (int l = 0; l + 1 < nlev; ++l) {
+    const int n = H.L[l].n;
+    if (n < TILE_X || H.L[l + 1].n < RTILE || H.L[l].gb[0] == nullptr) continue;
+    if (forced >= 0) {
+      H.tile_shape[l] = tile_shape_fits(forced, n) ? forced : 0;
+      continue;
+    }
+    if (!tune || n <= K.tail_n) continue;
+    const auto key = std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, n);
+    {
+      std::lock_guard<std::mutex> g(tune_mutex());
+      auto it = tune_cache().find(key);
+      if (it != tune_cache().end()) {
+        H.tile_shape[l] = it->second;
+        continue;
+      }
+    }
+    int best = 0;
+    float best_ms = -1.0f;
+    for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) {
+      if (!tile_shape_fits(ts, n)) continue;
+      const float ms = time_shape<MODEL, T, CORR>(H, K, l, ts, 5);
+      if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+        best_ms = ms;
+        best = ts;
+      }
+    }
+    H.tile_shape[l] = best;
+    std::lock_guard<std::mutex> g(tune_mutex());
+    tune_cache()[key] = best;
+  }
+}
+
+}  // namespace hfz

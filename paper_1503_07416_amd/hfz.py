@@ -25,7 +25,7 @@ SYMBOLS = [
     "hfz_default_params", "hfz_workspace_bytes", "hfz_init", "hfz_set_state",
     "hfz_get_state", "hfz_get_aux", "hfz_step", "hfz_energy", "hfz_mass",
     "hfz_begin_step", "hfz_smooth", "hfz_vcycle", "hfz_residual", "hfz_finish_step",
-    "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_destroy", "hfz_strerror",
+    "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_tile_shape", "hfz_destroy", "hfz_strerror",
     "hfz_batch_workspace_bytes", "hfz_batch_init", "hfz_batch_set_state", "hfz_batch_get_state",
     "hfz_batch_energy", "hfz_batch_release", "hfz_batch_step", "hfz_batch_destroy",
 ]
@@ -85,6 +85,7 @@ def load():
         "hfz_read_field": [vp, i, i, i, vp],
         "hfz_write_field": [vp, i, i, i, vp],
         "hfz_info": [vp, P(i), P(d)],
+        "hfz_tile_shape": [vp, i, P(i), P(i), P(i)],
         "hfz_destroy": [vp],
         "hfz_strerror": [i],
         "hfz_batch_workspace_bytes": [P(Params), i, P(ctypes.c_size_t)],
@@ -233,6 +234,13 @@ class Simulation:
         lv, ce = ctypes.c_int(), ctypes.c_double()
         check(self.lib.hfz_info(self.h, ctypes.byref(lv), ctypes.byref(ce)), "hfz_info")
         return ce.value
+
+    def tile_shape(self, level):
+        """(tx, ty, threads) of the tiled sweep kernel on FP64 level `level`, or
+        None where the coarse tail sweeps the level."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = self.lib.hfz_tile_shape(self.h, int(level), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return (a.value, b.value, c.value) if rc == 0 else None
 
     def read(self, which, level, comp):
         t = self._empty(self.n >> level)
