@@ -118,9 +118,10 @@ __device__ __forceinline__ T potential(const T* const* g, int q, const Phys<T>& 
 // Rows of N(g) at node q (App. G, Eqs. MGN_DFT_a-c / MGN_PFC_a-e).  g and rk
 // are read at q and its neighbours; om at index pf (which may live in another
 // array layout, e.g. a global array while g sits in an LDS tile).
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool PM = false>
 __device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* om, const Nbr& q,
-                                       int pf, const Coef<T>& K, const Phys<T>& P, T* out) {
+                                       int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                       const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* rho = g[0];
@@ -133,8 +134,8 @@ __device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* 
   out[0] = rho[q.p] + c4 * (rk[q.e] * uE - rk[q.w] * uW + rk[q.n] * vN - rk[q.s] * vS);
   const T qE = uE * uE + vE * vE, qW = uW * uW + vW * vW;
   const T qN = uN * uN + vN * vN, qS = uS * uS + vS * vS;
-  const T ME = potential<MODEL>(g, q.e, P), MW = potential<MODEL>(g, q.w, P);
-  const T MN = potential<MODEL>(g, q.n, P), MS = potential<MODEL>(g, q.s, P);
+  const T ME = PM ? pm[q.e] : potential<MODEL>(g, q.e, P), MW = PM ? pm[q.w] : potential<MODEL>(g, q.w, P);
+  const T MN = PM ? pm[q.n] : potential<MODEL>(g, q.n, P), MS = PM ? pm[q.s] : potential<MODEL>(g, q.s, P);
   const T lapu = (uE + uW + uN + uS - T(4) * uP) * ih2;
   const T lapv = (vE + vW + vN + vS - T(4) * vP) * ih2;
   const T b = T(0.5) * s * P.sigma * rkP * omP;
@@ -157,10 +158,10 @@ __device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* 
 // kappa^ from row 5 given rho^, mu^ from row 4 given rho^, kappa^ with the
 // cubic linearised about the current iterate.  g and rk are read at q and its
 // neighbours, f and om at index pf.
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool PM = false>
 __device__ __forceinline__ void block_update(const T* const* g, const T* const* f, const T* rk,
                                              const T* om, const Nbr& q, int pf, const Coef<T>& K,
-                                             const Phys<T>& P, T* out) {
+                                             const Phys<T>& P, T* out, const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* rho = g[0];
@@ -173,8 +174,8 @@ __device__ __forceinline__ void block_update(const T* const* g, const T* const* 
   if constexpr (MODEL == CDFT) rh = fsqrt(rh * rh + P.delta * P.delta);
   const T qE = uE * uE + vE * vE, qW = uW * uW + vW * vW;
   const T qN = uN * uN + vN * vN, qS = uS * uS + vS * vS;
-  const T ME = potential<MODEL>(g, q.e, P), MW = potential<MODEL>(g, q.w, P);
-  const T MN = potential<MODEL>(g, q.n, P), MS = potential<MODEL>(g, q.s, P);
+  const T ME = PM ? pm[q.e] : potential<MODEL>(g, q.e, P), MW = PM ? pm[q.w] : potential<MODEL>(g, q.w, P);
+  const T MN = PM ? pm[q.n] : potential<MODEL>(g, q.n, P), MS = PM ? pm[q.s] : potential<MODEL>(g, q.s, P);
   const T cg = T(0.5) * s * P.gamma * ih2;
   const T a = rkP + T(4) * cg;
   const T b = T(0.5) * s * P.sigma * rkP * omP;
@@ -236,9 +237,10 @@ __device__ __forceinline__ T dq(const T* const* e, const T* const* b, int q) {
   return eu * (T(2) * b[1][q] + eu) + ev * (T(2) * b[2][q] + ev);
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool PM = false>
 __device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, const T* rk, const T* om,
-                                        const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out) {
+                                        const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                        const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* er = e[0];
@@ -250,8 +252,10 @@ __device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, co
   const T vE = v[q.e], vW = v[q.w], vN = v[q.n], vS = v[q.s];
   out[0] = er[q.p] + c4 * (rk[q.e] * uE - rk[q.w] * uW + rk[q.n] * vN - rk[q.s] * vS);
   const T qE = dq(e, b, q.e), qW = dq(e, b, q.w), qN = dq(e, b, q.n), qS = dq(e, b, q.s);
-  const T ME = potential_d<MODEL>(e, b, q.e, P), MW = potential_d<MODEL>(e, b, q.w, P);
-  const T MN = potential_d<MODEL>(e, b, q.n, P), MS = potential_d<MODEL>(e, b, q.s, P);
+  const T ME = PM ? pm[q.e] : potential_d<MODEL>(e, b, q.e, P);
+  const T MW = PM ? pm[q.w] : potential_d<MODEL>(e, b, q.w, P);
+  const T MN = PM ? pm[q.n] : potential_d<MODEL>(e, b, q.n, P);
+  const T MS = PM ? pm[q.s] : potential_d<MODEL>(e, b, q.s, P);
   const T lapu = (uE + uW + uN + uS - T(4) * uP) * ih2;
   const T lapv = (vE + vW + vN + vS - T(4) * vP) * ih2;
   const T bb = T(0.5) * s * P.sigma * rkP * omP;
@@ -270,10 +274,11 @@ __device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, co
   }
 }
 
-template <int MODEL, typename T>
+template <int MODEL, typename T, bool PM = false>
 __device__ __forceinline__ void block_update_d(const T* const* e, const T* const* f, const T* const* b,
                                                const T* rk, const T* om, const Nbr& q, int pf,
-                                               const Coef<T>& K, const Phys<T>& P, T* out) {
+                                               const Coef<T>& K, const Phys<T>& P, T* out,
+                                               const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* er = e[0];
@@ -291,8 +296,10 @@ __device__ __forceinline__ void block_update_d(const T* const* e, const T* const
     if (!(t > T(0) && t * t > T(1e6) * P.delta * P.delta)) rh = fsqrt(t * t + P.delta * P.delta) - rb;
   }
   const T qE = dq(e, b, q.e), qW = dq(e, b, q.w), qN = dq(e, b, q.n), qS = dq(e, b, q.s);
-  const T ME = potential_d<MODEL>(e, b, q.e, P), MW = potential_d<MODEL>(e, b, q.w, P);
-  const T MN = potential_d<MODEL>(e, b, q.n, P), MS = potential_d<MODEL>(e, b, q.s, P);
+  const T ME = PM ? pm[q.e] : potential_d<MODEL>(e, b, q.e, P);
+  const T MW = PM ? pm[q.w] : potential_d<MODEL>(e, b, q.w, P);
+  const T MN = PM ? pm[q.n] : potential_d<MODEL>(e, b, q.n, P);
+  const T MS = PM ? pm[q.s] : potential_d<MODEL>(e, b, q.s, P);
   const T cg = T(0.5) * s * P.gamma * ih2;
   const T a = rkP + T(4) * cg;
   const T bb = T(0.5) * s * P.sigma * rkP * omP;
@@ -321,24 +328,34 @@ __device__ __forceinline__ void block_update_d(const T* const* e, const T* const
 }
 
 // Mode dispatch: CORR = false is the full form, CORR = true the correction
-// form about the base fields b.
+// form about the base fields b.  PM = true reads the potential M at the four
+// neighbours from pm (same index space as g) instead of evaluating it there.
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void rows_any(const T* const* g, const T* const* b, const T* rk, const T* om,
-                                         const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out) {
+__device__ __forceinline__ T potential_any(const T* const* g, const T* const* b, int q, const Phys<T>& P) {
   if constexpr (CORR)
-    rows_Nd<MODEL, T>(g, b, rk, om, q, pf, K, P, out);
+    return potential_d<MODEL, T>(g, b, q, P);
   else
-    rows_N<MODEL, T>(g, rk, om, q, pf, K, P, out);
+    return potential<MODEL, T>(g, q, P);
 }
 
-template <int MODEL, typename T, bool CORR>
+template <int MODEL, typename T, bool CORR, bool PM = false>
+__device__ __forceinline__ void rows_any(const T* const* g, const T* const* b, const T* rk, const T* om,
+                                         const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                         const T* pm = nullptr) {
+  if constexpr (CORR)
+    rows_Nd<MODEL, T, PM>(g, b, rk, om, q, pf, K, P, out, pm);
+  else
+    rows_N<MODEL, T, PM>(g, rk, om, q, pf, K, P, out, pm);
+}
+
+template <int MODEL, typename T, bool CORR, bool PM = false>
 __device__ __forceinline__ void update_any(const T* const* g, const T* const* f, const T* const* b, const T* rk,
                                            const T* om, const Nbr& q, int pf, const Coef<T>& K,
-                                           const Phys<T>& P, T* out) {
+                                           const Phys<T>& P, T* out, const T* pm = nullptr) {
   if constexpr (CORR)
-    block_update_d<MODEL, T>(g, f, b, rk, om, q, pf, K, P, out);
+    block_update_d<MODEL, T, PM>(g, f, b, rk, om, q, pf, K, P, out, pm);
   else
-    block_update<MODEL, T>(g, f, rk, om, q, pf, K, P, out);
+    block_update<MODEL, T, PM>(g, f, rk, om, q, pf, K, P, out, pm);
 }
 
 // CDFT projection of an iterate value after the coarse-grid correction: full

@@ -58,10 +58,15 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2, CRN = CRX * CRY;
+  // CDFT: the potential M (a logarithm per node) is evaluated once per node
+  // and half sweep into sm, for the nodes of the colour not being updated,
+  // instead of at each of their four neighbours.
+  constexpr bool PM = MODEL == CDFT;
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RN];
   __shared__ T sb[NB][CORR ? RN : 1];
   __shared__ T se[PRO ? NCm : 1][PRO ? CRN : 1];
+  __shared__ T sm[PM ? RN : 1];
   const int m = L.n - 1, lg = L.lg;
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
   const int x0 = (int)blockIdx.x * TILE_X - H, y0 = (int)blockIdx.y * TILE_Y - H;
@@ -120,6 +125,19 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
+    if constexpr (PM) {
+      // M at the other colour's nodes of the box one node wider than the
+      // one updated below (their values are final for this half sweep)
+      const int hm = (RX - 2 * k + 2) >> 1, cm = hm * (RY - 2 * k + 2);
+      for (int w = threadIdx.x; w < cm; w += TILE_THREADS) {
+        const int r = w / hm, t = w - r * hm;
+        const int ly = k - 1 + r;
+        const int lx = k - 1 + 2 * t + ((k - 1 + ly + colour + 1) & 1);
+        const int lp = ly * RX + lx;
+        sm[lp] = potential_any<MODEL, T, CORR>(gl, bl, lp, P);
+      }
+      __syncthreads();
+    }
     const int half = (RX - 2 * k) >> 1, cnt = half * (RY - 2 * k);
     for (int w = threadIdx.x; w < cnt; w += TILE_THREADS) {
       const int r = w / half, t = w - r * half;
@@ -133,9 +151,19 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.s = q.p - RX;
       const int pf = (((y0 + ly) & m) << lg) + ((x0 + lx) & m);
       T out[NCm];
-      update_any<MODEL, T, CORR>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out);
+      update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
+    }
+    __syncthreads();
+  }
+  if constexpr (PM && RES != 0) {
+    // M on the owned block and its one-node ring, for the residual rows
+    constexpr int BX = TILE_X + 2, BN = BX * (TILE_Y + 2);
+    for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
+      const int r = w / BX, t = w - r * BX;
+      const int lp = (H - 1 + r) * RX + H - 1 + t;
+      sm[lp] = potential_any<MODEL, T, CORR>(gl, bl, lp, P);
     }
     __syncthreads();
   }
@@ -154,7 +182,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.n = lp + RX;
       q.s = lp - RX;
       T nv[NCm];
-      rows_any<MODEL, T, CORR>(gl, bl, srk, L.om, q, gp, L.k, P, nv);
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) {
         const T d = L.f[c][gp] - nv[c];
