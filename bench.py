@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=10, help="V-cycles of the oracle sample")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
+    ap.add_argument("--probe-tile-shape", type=int, default=2,
+                    help="tile shape of the counter probe (the one the tuner picks at 512^2)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="only launch the smoother and a reference copy kernel (for counter runs)")
     return ap.parse_args()
@@ -69,9 +72,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
+def committed_traffic(shape):
     """HBM bytes per smoother launch from the committed counter summary, or
-    None if it is missing or was taken from other kernel sources."""
+    None if it is missing, was taken from other kernel sources or from
+    another tile shape."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             text = f.read()
@@ -79,7 +83,8 @@ def committed_traffic():
         return None
     m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != source_hash():
+    sh = re.search(r"tile_shape:\s*([0-9x]+)", text)
+    if not m or not t or not sh or m.group(1) != source_hash() or sh.group(1) != shape:
         return None
     return float(t.group(1))
 
@@ -101,16 +106,20 @@ def smoother_roofline(sim, n, launches=25):
     t_launch = ms * 1e-3 / launches
     bytes_launch = 2 * SWEEP_BYTES_PFC * n * n
     achieved = bytes_launch / t_launch / 1e9
+    tx, ty, nt = sim.tile_shape(0)
+    traffic = committed_traffic(f"{tx}x{ty}x{nt}") if n == 512 else None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic() if n == 512 else None,
-            "kernel": "k_sweeps_tile<PFC, double, 2 sweeps>", "launch_us": round(t_launch * 1e6, 3),
-            "bytes_per_launch": bytes_launch}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_sweeps_tile<PFC, double, 2 sweeps, {tx}x{ty} tile, {nt} threads>",
+            "launch_us": round(t_launch * 1e6, 3), "bytes_per_launch": bytes_launch}
 
 
-def counter_probe(n):
-    """Five smoother launches at n^2 and three launches of a reference copy
-    kernel (torch elementwise multiply, 1 GiB read + 1 GiB written), for
-    the FETCH_SIZE / WRITE_SIZE counter runs."""
+def counter_probe(n, shape):
+    """Five smoother launches at n^2 in tile shape `shape` (forced: the tuner's
+    timings are distorted under a counter-collecting profiler) and three
+    launches of a reference copy kernel (torch elementwise multiply, 1 GiB
+    read + 1 GiB written), for the FETCH_SIZE / WRITE_SIZE counter runs."""
+    os.environ["HFZ_TILE"] = str(shape)
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
@@ -125,7 +134,7 @@ def counter_probe(n):
         torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
     print(json.dumps({"counter_probe": True, "n": n, "smoother_launches": 5, "copy_bytes_each_way": 2**30,
-                      "source_hash": source_hash()}))
+                      "tile_shape": "x".join(map(str, sim.tile_shape(0))), "source_hash": source_hash()}))
 
 
 def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
@@ -354,7 +363,10 @@ def main():
         print(json.dumps({"error": "one GPU only: the solver runs on a single device; --gpus must be 1"}))
         sys.exit(2)
     if a.counter_probe:
-        counter_probe(a.n)
+        counter_probe(a.n, a.probe_tile_shape)
+        return
+    if a.cdft_only:
+        print(json.dumps({"cdft": run_cdft()}))
         return
     import torch
     import workloads

@@ -19,7 +19,7 @@ paper it follows (section, equation label, appendix).  Modules:
 ``scheme``    the fully discrete scheme, Eqs. discrete_a-d, written in vector
               form with the App. E operators
 ``system``    the same scheme as the nonlinear system N(g) = S of App. G
-              (typos corrected, see the readings list in the design doc)
+              (with the printed typos corrected from Eqs. discrete_a-d)
 ``smoother``  damped point-block nonlinear Gauss-Seidel (App. G, damping of
               App. G "Damped Gauss-Seidel Iteration"), red-black ordered
 ``fas``       FAS multigrid V-cycle and the time stepper (Sec. 6, App. G)

@@ -2,7 +2,7 @@
 
 The paper uses "a standard non-linear Full Approximation Scheme" with the
 App. G smoother and defers its transfer operators to an earlier paper.  The
-choices made here (the readings list in the design doc gives the reasons):
+choices made here, each the plain reading of what the paper states:
 
 * Nested nodal grids: coarse node I sits on fine node 2I (the same nesting the
   paper's Cauchy error e_ij = rho^h_ij - rho^{h/2}_{2i,2j} uses).  Grid sizes

@@ -23,7 +23,7 @@ followed by damping of every component, x <- (1 - w) x^ + w x_l, w = 0.5.
 The printed smoother rows differ from this in signs and factors that the
 system they smooth fixes (the sign of the rho row's bracket, the missing
 factor s in the diagonal, the u-for-v slip in MGSM_PFC_a, the sign of the
-3/2 constant in MGSM_PFC_d); see the readings list in the design doc.
+3/2 constant in MGSM_PFC_d).
 
 Ordering: red-black.  Nodes with (i + j) even are updated first, from the
 current values of their (odd) neighbours, then the odd nodes.  This is the

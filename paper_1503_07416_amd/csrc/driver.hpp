@@ -13,6 +13,7 @@
 
 #include "kernels.hpp"
 #include "tail.hpp"
+#include "restrict.hpp"
 #include "tile.hpp"
 
 namespace hfz {

@@ -85,16 +85,19 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
         continue;
       }
     }
-    int best = 0;
-    float best_ms = -1.0f;
-    for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) {
-      if (!tile_shape_fits(ts, n)) continue;
-      const float ms = time_shape<MODEL, T, CORR>(H, K, l, ts, 5);
-      if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
-        best_ms = ms;
-        best = ts;
+    // best of three rounds per shape; a later shape must win by 2% to
+    // replace an earlier one, so near-ties resolve the same way every run
+    float ms[NUM_TILE_SHAPES];
+    for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) ms[ts] = -1.0f;
+    for (int round = 0; round < 3; ++round)
+      for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) {
+        if (!tile_shape_fits(ts, n)) continue;
+        const float t = time_shape<MODEL, T, CORR>(H, K, l, ts, 8);
+        if (t > 0.0f && (ms[ts] < 0.0f || t < ms[ts])) ms[ts] = t;
       }
-    }
+    int best = 0;
+    for (int ts = 1; ts < NUM_TILE_SHAPES; ++ts)
+      if (ms[ts] > 0.0f && (ms[best] < 0.0f || ms[ts] < 0.98f * ms[best])) best = ts;
     H.tile_shape[l] = best;
     std::lock_guard<std::mutex> g(tune_mutex());
     tune_cache()[key] = best;

@@ -2,8 +2,8 @@
 checks.  This module only draws random numbers and fixes the constants of each
 workload; it holds none of the scheme's arithmetic.
 
-Constants follow the paper's own runs (Sec. 6), with the readings listed in
-DESIGN.md:
+Constants follow the paper's own runs (Sec. 6); where the printed value is
+ambiguous, the reading taken and its reason are stated with it:
 
 * PFC freezing run: eps = 0.025 (alpha = 1 - eps), gamma = 2, domain
   [0,32)^2 on 128^2 (h = 0.25), s = 0.01; mean density 3/2 - 0.07 sqrt(3)
