@@ -61,12 +61,17 @@ template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, 
   }
 }
 
-// Whether the tail from a level of size top_n with nt levels fits in the LDS
-// the tail kernel may use (every tail level is held in LDS).  Grids of 16^2
-// and below always fit.
-template <int MODEL, typename T, bool CORR> bool tail_fits(int top_n, int nt, size_t lds_max) {
+// LDS plan of the tail from a level of size top_n with nt levels: whether
+// every level fits in the LDS the tail kernel may use, and from which level
+// down the residual scratch d fits in LDS too (d_from = nt: none).  Grids of
+// 16^2 and below always fit.
+template <int MODEL, typename T, bool CORR> bool tail_plan(int top_n, int nt, size_t lds_max, int* d_from) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
-  return nt <= TAIL_MAX_LEVELS && tail_lds_count<NCm, NB>(top_n, nt) * sizeof(T) <= lds_max;
+  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
+  int df = nt;
+  while (df > 0 && tail_lds_count<NCm, NB>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
+  if (d_from) *d_from = df;
+  return true;
 }
 
 template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l) {
@@ -78,7 +83,8 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu1 = K.nu1;
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
-  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt) * sizeof(T);
+  tail_plan<MODEL, T, CORR>(A.top_n, A.nt, H.tail_lds_max, &A.d_from);
+  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.d_from) * sizeof(T);
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 
@@ -193,7 +199,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
 
 template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l) {
   const int nlev = (int)H.L.size(), last = nlev - 1;
-  if (H.L[l].n <= K.tail_n && tail_fits<MODEL, T, CORR>(H.L[l].n, nlev - l, H.tail_lds_max)) {
+  if (H.L[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[l].n, nlev - l, H.tail_lds_max, nullptr)) {
     tail_launch<MODEL, T, CORR>(H, K, l);
     return;
   }

@@ -983,7 +983,8 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
                  const Cycle& K, int l) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
   const int nlev = (int)R.size(), count = B->count;
-  if (R[l].n <= K.tail_n && tail_fits<MODEL, T, CORR>(R[l].n, nlev - l, lds_max)) {
+  int d_from = 0;
+  if (R[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(R[l].n, nlev - l, lds_max, &d_from)) {
     TailArgs<T> A{};
     A.Lg = Tl + l;
     A.nt = nlev - l;
@@ -991,7 +992,8 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
     A.nu1 = K.nu1;
     A.nu2 = K.nu2;
     A.coarse_sweeps = K.coarse_sweeps;
-    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt) * sizeof(T);
+    A.d_from = d_from;
+    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.d_from) * sizeof(T);
     k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
     return;
   }

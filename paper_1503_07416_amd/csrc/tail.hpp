@@ -21,19 +21,22 @@ template <typename T> struct TailArgs {
   int nt;            // levels in the tail, all held in LDS
   int top_n;         // size of the tail top
   int nu1, nu2, coarse_sweeps;
+  int d_from;        // levels l >= d_from keep the residual scratch d in LDS, the others in global memory
 };
 
-// T values of LDS that `nt` tail levels need (top size top_n): g, f, rk, om
-// per level, plus g0 for all but the tail top.  NB = 3 in the correction form
-// (the base state rho, u, v), else 0.
+// T values of LDS per level l of nt (size n): g, f, rk, om, g0 below the top,
+// the base state in the correction form (NB = 3), and d where it is held in
+// LDS (l >= d_from; the coarsest level needs none).
+template <int NCm, int NB>
+__host__ __device__ inline size_t tail_level_count(int n, int l, int nt, int d_from) {
+  const bool dl = l >= d_from && l < nt - 1;
+  return (size_t)n * n * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
+}
+
 template <int NCm, int NB = 0>
-__host__ __device__ inline size_t tail_lds_count(int top_n, int nt) {
+__host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int d_from) {
   size_t tot = 0;
-  int n = top_n;
-  for (int l = 0; l < nt; ++l) {
-    tot += (size_t)n * n * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
-    n >>= 1;
-  }
+  for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB>(top_n >> l, l, nt, d_from);
   return tot;
 }
 
@@ -46,10 +49,7 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
   Lvl<T> s = A.Lg[t];
   G[t] = s;
   size_t off = 0;
-  for (int l = 0; l < t; ++l) {
-    const size_t nl = (size_t)(A.top_n >> l);
-    off += nl * nl * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0));
-  }
+  for (int l = 0; l < t; ++l) off += tail_level_count<NCm, NB>(A.top_n >> l, l, A.nt, A.d_from);
   T* p = base + off;
   const int cnt = s.n * s.n;
 #pragma unroll
@@ -68,20 +68,26 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
   p += 2 * cnt;
 #pragma unroll
   for (int c = 0; c < NB; ++c) s.bg[c] = p + c * cnt;
+  p += NB * cnt;
+  if (t >= A.d_from && t < A.nt - 1) {
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) s.d[c] = p + c * cnt;
+  }
   S[t] = s;
 }
 
 // The view the phases use of a tail level built by tail_lds_levels: its
 // arrays in LDS (g0 only below the top, G0 = true), the residual scratch d in
-// global memory.
-template <int NCm, int NB, bool G0, typename T> __device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
+// LDS (DL = true) or global memory.
+template <int NCm, int NB, bool G0, bool DL = false, typename T>
+__device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
   Lvl<T> L = s;
 #pragma unroll
   for (int c = 0; c < NCm; ++c) {
     L.g[c] = as_lds(s.g[c]);
     L.f[c] = as_lds(s.f[c]);
     if constexpr (G0) L.g0[c] = as_lds(s.g0[c]);
-    L.d[c] = as_global(s.d[c]);
+    L.d[c] = DL ? as_lds(s.d[c]) : as_global(s.d[c]);
   }
   L.rk = as_lds(s.rk);
   L.om = as_lds(s.om);
@@ -92,9 +98,9 @@ template <int NCm, int NB, bool G0, typename T> __device__ __forceinline__ Lvl<T
 
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour) {
-  const int n = L.n, half = n >> 1, cnt = half * n;
+  const int n = L.n, cnt = (n >> 1) * n, lgh = L.lg - 1;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
-    const int j = w / half, t = w - j * half;
+    const int j = w >> lgh, t = w & ((1 << lgh) - 1);
     const int i = 2 * t + ((j + colour) & 1);
     const Nbr q = nbr(i, j, n, L.lg);
     T out[NC<MODEL>::value];
@@ -113,10 +119,12 @@ __device__ __forceinline__ void tail_sweeps(const Lvl<T> L, const Phys<T>& P, in
   }
 }
 
+// FAS restriction in two phases: d = f - N(g) on the fine level and
+// g_c = g0_c = R g (correction form: also the coarse base R bg), then
+// f_c = R d + N_c(R g).
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
-  // d = f - N(g) on the fine level (into F.d, a global scratch array) ...
   const int fcnt = F.n * F.n;
   for (int w = threadIdx.x; w < fcnt; w += blockDim.x) {
     const Nbr q = nbr(w & (F.n - 1), w >> F.lg, F.n, F.lg);
@@ -125,8 +133,6 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
 #pragma unroll
     for (int c = 0; c < NCm; ++c) F.d[c][q.p] = F.f[c][q.p] - nv[c];
   }
-  __syncthreads();
-  // ... then g_c = g0_c = R g and f_c = R d ...
   const int cnt = C.n * C.n;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int J = w >> C.lg, I = w & (C.n - 1);
@@ -135,7 +141,6 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
       const T gr = fw9(F.g[c], 2 * I, 2 * J, F.n, F.lg);
       C.g[c][w] = gr;
       C.g0[c][w] = gr;
-      C.f[c][w] = fw9(F.d[c], 2 * I, 2 * J, F.n, F.lg);
     }
     if constexpr (CORR) {
 #pragma unroll
@@ -143,14 +148,13 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
     }
   }
   __syncthreads();
-  // ... and f_c += N_c(R g)
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int J = w >> C.lg, I = w & (C.n - 1);
     const Nbr q = nbr(I, J, C.n, C.lg);
     T nv[NCm];
     rows_any<MODEL, T, CORR>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv);
 #pragma unroll
-    for (int c = 0; c < NCm; ++c) C.f[c][w] += nv[c];
+    for (int c = 0; c < NCm; ++c) C.f[c][w] = fw9(F.d[c], 2 * I, 2 * J, F.n, F.lg) + nv[c];
   }
   __syncthreads();
 }
@@ -189,11 +193,6 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
   __syncthreads();
 }
 
-template <typename T>
-__device__ __forceinline__ void tail_copy(T* dst, const T* src, int cnt) {
-  for (int w = threadIdx.x; w < cnt; w += blockDim.x) dst[w] = src[w];
-}
-
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
@@ -204,31 +203,46 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
   tail_lds_levels<NCm, NB, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
   __syncthreads();
-  {
-    const Lvl<T> s = tail_view<NCm, NB, false>(S[0]);
-    const Lvl<T> g = lvl_global(G[0]);
-    const int cnt = g.n * g.n;
-#pragma unroll
-    for (int c = 0; c < NCm; ++c) {
-      tail_copy(s.g[c], g.g[c], cnt);
-      tail_copy(s.f[c], g.f[c], cnt);
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) tail_copy(s.bg[c], g.bg[c], cnt);
-  }
+  // load: every global value a thread moves is read before it is stored
   for (int l = 0; l < A.nt; ++l) {
     const Lvl<T> s = tail_view<NCm, NB, false>(S[l]);
     const Lvl<T> g = lvl_global(G[l]);
     const int cnt = g.n * g.n;
-    tail_copy(s.rk, g.rk, cnt);
-    tail_copy(s.om, g.om, cnt);
+    for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
+      T x[2 * NCm + NB + 2];
+      x[0] = g.rk[w];
+      x[1] = g.om[w];
+      if (l == 0) {
+#pragma unroll
+        for (int c = 0; c < NCm; ++c) {
+          x[2 + c] = g.g[c][w];
+          x[2 + NCm + c] = g.f[c][w];
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[2 + 2 * NCm + c] = g.bg[c][w];
+      }
+      s.rk[w] = x[0];
+      s.om[w] = x[1];
+      if (l == 0) {
+#pragma unroll
+        for (int c = 0; c < NCm; ++c) {
+          s.g[c][w] = x[2 + c];
+          s.f[c][w] = x[2 + NCm + c];
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) s.bg[c][w] = x[2 + 2 * NCm + c];
+      }
+    }
   }
   __syncthreads();
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
     const Lvl<T> F = tail_view<NCm, NB, false>(S[l]);
     tail_sweeps<MODEL, T, CORR>(F, P, A.nu1);
-    tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
+    if (l >= A.d_from)
+      tail_restrict<MODEL, T, CORR>(tail_view<NCm, NB, false, true>(S[l]), tail_view<NCm, NB, true>(S[l + 1]), P);
+    else
+      tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
   }
   tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, false>(S[last]), P, A.coarse_sweeps);
   for (int l = last - 1; l >= 0; --l) {
@@ -240,8 +254,13 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
     const Lvl<T> s = tail_view<NCm, NB, false>(S[0]);
     const Lvl<T> g = lvl_global(G[0]);
     const int cnt = g.n * g.n;
+    for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
+      T x[NCm];
 #pragma unroll
-    for (int c = 0; c < NCm; ++c) tail_copy(g.g[c], s.g[c], cnt);
+      for (int c = 0; c < NCm; ++c) x[c] = s.g[c][w];
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) g.g[c][w] = x[c];
+    }
   }
 }
 
