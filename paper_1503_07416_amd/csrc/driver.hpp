@@ -22,7 +22,8 @@ template <typename T> struct Hier {
   std::vector<Lvl<T>> L;    // finest first
   Lvl<T>* desc = nullptr;   // device copy of L (the tail kernel reads it)
   size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use
-  std::vector<int> tile_shape;  // tile shape of the sweep kernel per level (tile.hpp)
+  std::vector<int> tile_shape;      // tile shape of the sweep kernel per level (tile.hpp)
+  std::vector<int> restrict_shape;  // restriction variant per fine level (restrict.hpp)
   Phys<T> P{};
 };
 
@@ -104,6 +105,21 @@ int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, c
   return (int)(grid.x * grid.y);
 }
 
+// The FAS restriction from fine level F (iterate in F.g, residual in F.d) to
+// C in variant rs (restrict.hpp).
+template <int MODEL, typename T, bool CORR>
+void restrict_launch(Hier<T>& H, Cycle& K, const Lvl<T>& F, const Lvl<T>& C, int rs) {
+  if (rs < 0 || rs >= NUM_RESTRICT_SHAPES || C.n % kRestrictTile[rs] != 0) rs = 0;
+  const int rt = kRestrictTile[rs];
+  const dim3 grid(C.n / rt, C.n / rt);
+  if (rs == 1)
+    k_restrict_fas_staged<MODEL, T, CORR, 8, 256><<<grid, 256, 0, K.stream>>>(F, C, H.P);
+  else if (rs == 2)
+    k_restrict_fas_staged<MODEL, T, CORR, 16, 256><<<grid, 256, 0, K.stream>>>(F, C, H.P);
+  else
+    k_restrict_fas_tile<MODEL, T, CORR><<<grid, RTILE * RTILE, 0, K.stream>>>(F, C, H.P);
+}
+
 // Whether tile shape ts covers an n x n level exactly.
 inline bool tile_shape_fits(int ts, int n) {
   return ts >= 0 && ts < NUM_TILE_SHAPES && n % kTileShapes[ts].tx == 0 && n % kTileShapes[ts].ty == 0;
@@ -180,7 +196,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
       k_residual_field<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.P);
     }
   }
-  k_restrict_fas_tile<MODEL, T, CORR><<<dim3(C.n / RTILE, C.n / RTILE), RTILE * RTILE, 0, K.stream>>>(F, C, H.P);
+  restrict_launch<MODEL, T, CORR>(H, K, F, C, l < (int)H.restrict_shape.size() ? H.restrict_shape[l] : 0);
   vcycle_rec<MODEL, T, CORR>(H, K, l + 1);
   if (K.nu2 > 0) {
     // post-sweeps; on the finest level of the FP64 solve the last one also

@@ -660,6 +660,8 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
     std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p->n, hd->nlev,
                  hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
     for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
+    std::fprintf(stderr, " restriction:");
+    for (size_t l = 0; l < hd->H.restrict_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.restrict_shape[l]);
     for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
     std::fprintf(stderr, "\n");
   }

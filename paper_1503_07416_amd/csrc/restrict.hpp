@@ -97,4 +97,106 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile_b(const Lvl<
   restrict_fas_body<MODEL, T, CORR>(F, lvl_global(Cs[z]), Ps[z]);
 }
 
+// Staged form: the fine iterate under the stencils of a coarse tile and its
+// ring, and the fine residual under the tile's own stencils, are read into LDS
+// in one coalesced phase; R g, N_c(R g) and R d are then formed from LDS.  RT is
+// the coarse tile edge, NT the workgroup size.  Same arithmetic, in the same
+// order, as restrict_fas_body.
+template <typename T> __device__ __forceinline__ T fw9l(const T* f, int p, int stride) {
+  return (T(4) * f[p] + T(2) * (f[p + 1] + f[p - 1] + f[p + stride] + f[p - stride]) +
+          (f[p + stride + 1] + f[p + stride - 1] + f[p - stride + 1] + f[p - stride - 1])) *
+         T(0.0625);
+}
+
+template <int MODEL, typename T, bool CORR, int RT, int NT>
+__device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
+  constexpr int NCm = NC<MODEL>::value;
+  constexpr int NB = CORR ? 3 : 1;
+  constexpr int CX = RT + 2, CN = CX * CX;      // coarse tile and its ring
+  constexpr int FX = 2 * RT + 5, FN = FX * FX;  // fine nodes under the ring's stencils
+  constexpr int DX = 2 * RT + 1, DN = DX * DX;  // fine nodes under the tile's stencils
+  __shared__ T fg[NCm][FN];
+  __shared__ T fb[NB][CORR ? FN : 1];
+  __shared__ T fd[NCm][DN];
+  __shared__ T sg[NCm][CN];
+  __shared__ T sb[NB][CORR ? CN : 1];
+  __shared__ T srk[CN];
+  const int mc = C.n - 1, mf = F.n - 1;
+  const int X0 = (int)blockIdx.x * RT - 1, Y0 = (int)blockIdx.y * RT - 1;  // coarse ring origin
+  const int fx0 = 2 * X0 - 1, fy0 = 2 * Y0 - 1;                              // fine origin of fg
+  for (int w = threadIdx.x; w < FN; w += NT) {
+    const int ly = w / FX, lx = w - ly * FX;
+    const int p = (((fy0 + ly) & mf) << F.lg) + ((fx0 + lx) & mf);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) fg[c][w] = F.g[c][p];
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fb[c][w] = F.bg[c][p];
+    }
+  }
+  for (int w = threadIdx.x; w < DN; w += NT) {
+    const int ly = w / DX, lx = w - ly * DX;
+    const int p = (((fy0 + 2 + ly) & mf) << F.lg) + ((fx0 + 2 + lx) & mf);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) fd[c][w] = F.d[c][p];
+  }
+  for (int w = threadIdx.x; w < CN; w += NT) {
+    const int ly = w / CX, lx = w - ly * CX;
+    srk[w] = C.rk[(((Y0 + ly) & mc) << C.lg) + ((X0 + lx) & mc)];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < CN; w += NT) {
+    const int ly = w / CX, lx = w - ly * CX;
+    const int fl = (1 + 2 * ly) * FX + 1 + 2 * lx;  // fine node under coarse (X0 + lx, Y0 + ly)
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) sg[c][w] = fw9l(fg[c], fl, FX);
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sb[c][w] = fw9l(fb[c], fl, FX);
+    }
+  }
+  __syncthreads();
+  const T* gl[NCm];
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
+  const T* bl[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
+  for (int w = threadIdx.x; w < RT * RT; w += NT) {
+    const int ty = w / RT, tx = w - ty * RT;
+    const int ly = ty + 1, lx = tx + 1;
+    const int pc = (((Y0 + ly) & mc) << C.lg) + ((X0 + lx) & mc);
+    Nbr q;
+    q.p = ly * CX + lx;
+    q.e = q.p + 1;
+    q.w = q.p - 1;
+    q.n = q.p + CX;
+    q.s = q.p - CX;
+    T nv[NCm];
+    rows_any<MODEL, T, CORR>(gl, bl, srk, C.om, q, pc, C.k, P, nv);
+    const int fl = (1 + 2 * ty) * DX + 1 + 2 * tx;
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) {
+      const T gr = sg[c][q.p];
+      C.g[c][pc] = gr;
+      C.g0[c][pc] = gr;
+      C.f[c][pc] = fw9l(fd[c], fl, DX) + nv[c];
+    }
+    if constexpr (CORR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) C.bg[c][pc] = sb[c][q.p];
+    }
+  }
+}
+
+template <int MODEL, typename T, bool CORR, int RT, int NT>
+__global__ __launch_bounds__(NT) void k_restrict_fas_staged(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, C, P);
+}
+
+// Restriction variants the tuner chooses from: 0 the direct kernel (coarse
+// tile 16), 1 the staged kernel with coarse tile 8, 2 with coarse tile 16.
+constexpr int NUM_RESTRICT_SHAPES = 3;
+constexpr int kRestrictTile[NUM_RESTRICT_SHAPES] = {16, 8, 16};
+
 }  // namespace hfz

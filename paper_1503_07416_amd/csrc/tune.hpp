@@ -1,4 +1,4 @@
-// Tile-shape tuner of the tiled sweep kernel.
+// Tuner of the tiled sweep kernel's tile shape and the restriction variant.
 //
 // The best tile shape depends on the level size: small levels have too few
 // workgroups to fill the device and want small, quick tiles; large levels want
@@ -9,9 +9,10 @@
 // handle's stream, and keeps the fastest.  The kernels' speed does not depend
 // on the values they sweep, so the tuner runs on the workspace as it is; it
 // writes only the second iterate buffer and the residual scratch of the level.
+// The restriction variants (restrict.hpp) are timed the same way per level.
 // Choices are cached per (model, arithmetic type, form, level size) for the
 // life of the process.  HFZ_TILE=<shape> forces one shape where it fits,
-// HFZ_TUNE=0 keeps shape 0.
+// HFZ_RESTRICT=<variant> one restriction variant, HFZ_TUNE=0 keeps both at 0.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -19,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
 
 #include "driver.hpp"
 
@@ -28,8 +30,8 @@ inline std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
 }
-inline std::map<std::tuple<int, int, int, int>, int>& tune_cache() {
-  static std::map<std::tuple<int, int, int, int>, int> c;
+inline std::map<std::tuple<int, int, int, int>, std::pair<int, int>>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int>, std::pair<int, int>> c;
   return c;
 }
 
@@ -59,48 +61,88 @@ float time_shape(Hier<T>& H, Cycle& K, int l, int ts, int reps) {
   return ms;
 }
 
-// Fills H.tile_shape for the levels the tiled V-cycle visits (size >= 32
-// with a coarser level of >= 16, above the tail).
+// Average time (ms) of `reps` restriction launches of variant rs from level
+// l to l + 1, after one untimed launch; negative on a HIP error.
+template <int MODEL, typename T, bool CORR>
+float time_restrict(Hier<T>& H, Cycle& K, int l, int rs, int reps) {
+  const Lvl<T>& F = H.L[l];
+  const Lvl<T>& C = H.L[l + 1];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    restrict_launch<MODEL, T, CORR>(H, K, F, C, rs);
+    bool ok = hipEventRecord(e0, K.stream) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) restrict_launch<MODEL, T, CORR>(H, K, F, C, rs);
+    ok = ok && hipEventRecord(e1, K.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipGetLastError() == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.0f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return ms;
+}
+
+// Index of the fastest of `count` candidates timed by `time(k)` (best of
+// three rounds; a later candidate must win by 2%, so near-ties resolve the
+// same way every run); 0 if none could be timed.
+template <typename F> int pick_fastest(int count, F&& time) {
+  float ms[8];
+  for (int k = 0; k < count; ++k) ms[k] = -1.0f;
+  for (int round = 0; round < 3; ++round)
+    for (int k = 0; k < count; ++k) {
+      const float t = time(k);
+      if (t > 0.0f && (ms[k] < 0.0f || t < ms[k])) ms[k] = t;
+    }
+  int best = 0;
+  for (int k = 1; k < count; ++k)
+    if (ms[k] > 0.0f && (ms[best] < 0.0f || ms[k] < 0.98f * ms[best])) best = k;
+  return best;
+}
+
+// Fills H.tile_shape and H.restrict_shape for the levels the tiled V-cycle
+// visits (size >= 32 with a coarser level of >= 16, above the tail).
+// HFZ_RESTRICT=<variant> forces a restriction variant where it fits.
 template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cycle K) {
   const int nlev = (int)H.L.size();
   H.tile_shape.assign(nlev, 0);
+  H.restrict_shape.assign(nlev, 0);
+  int forced_r = -1;
+  if (const char* e = std::getenv("HFZ_RESTRICT")) forced_r = std::atoi(e);
   int forced = -1;
   if (const char* e = std::getenv("HFZ_TILE")) forced = std::atoi(e);
   bool tune = true;
   if (const char* e = std::getenv("HFZ_TUNE")) tune = std::atoi(e) != 0;
   for (int l = 0; l + 1 < nlev; ++l) {
-    const int n = H.L[l].n;
-    if (n < TILE_X || H.L[l + 1].n < RTILE || H.L[l].gb[0] == nullptr) continue;
-    if (forced >= 0) {
-      H.tile_shape[l] = tile_shape_fits(forced, n) ? forced : 0;
-      continue;
-    }
-    if (!tune || n <= K.tail_n) continue;
+    const int n = H.L[l].n, nc = H.L[l + 1].n;
+    if (n < TILE_X || nc < RTILE || H.L[l].gb[0] == nullptr) continue;
+    if (forced >= 0) H.tile_shape[l] = tile_shape_fits(forced, n) ? forced : 0;
+    if (forced_r >= 0)
+      H.restrict_shape[l] = (forced_r < NUM_RESTRICT_SHAPES && nc % kRestrictTile[forced_r] == 0) ? forced_r : 0;
+    if (!tune || n <= K.tail_n || (forced >= 0 && forced_r >= 0)) continue;
     const auto key = std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, n);
     {
       std::lock_guard<std::mutex> g(tune_mutex());
       auto it = tune_cache().find(key);
       if (it != tune_cache().end()) {
-        H.tile_shape[l] = it->second;
+        if (forced < 0) H.tile_shape[l] = it->second.first;
+        if (forced_r < 0) H.restrict_shape[l] = it->second.second;
         continue;
       }
     }
-    // best of three rounds per shape; a later shape must win by 2% to
-    // replace an earlier one, so near-ties resolve the same way every run
-    float ms[NUM_TILE_SHAPES];
-    for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) ms[ts] = -1.0f;
-    for (int round = 0; round < 3; ++round)
-      for (int ts = 0; ts < NUM_TILE_SHAPES; ++ts) {
-        if (!tile_shape_fits(ts, n)) continue;
-        const float t = time_shape<MODEL, T, CORR>(H, K, l, ts, 8);
-        if (t > 0.0f && (ms[ts] < 0.0f || t < ms[ts])) ms[ts] = t;
-      }
-    int best = 0;
-    for (int ts = 1; ts < NUM_TILE_SHAPES; ++ts)
-      if (ms[ts] > 0.0f && (ms[best] < 0.0f || ms[ts] < 0.98f * ms[best])) best = ts;
-    H.tile_shape[l] = best;
+    const int ts = pick_fastest(NUM_TILE_SHAPES, [&](int k) {
+      return tile_shape_fits(k, n) ? time_shape<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
+    });
+    const int rs = pick_fastest(NUM_RESTRICT_SHAPES, [&](int k) {
+      return nc % kRestrictTile[k] == 0 ? time_restrict<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
+    });
+    if (forced < 0) H.tile_shape[l] = ts;
+    if (forced_r < 0) H.restrict_shape[l] = rs;
     std::lock_guard<std::mutex> g(tune_mutex());
-    tune_cache()[key] = best;
+    tune_cache()[key] = std::make_pair(ts, rs);
   }
 }
 

@@ -1,11 +1,13 @@
-"""GPU: every tile shape of the tiled sweep kernel gives the same iterates.
+"""GPU: every tile shape of the tiled sweep kernel, and every variant of the
+FAS restriction kernel, gives the same iterates.
 
 The red-black sweeps update each node from the same neighbour values whatever
 tile owns it (the halo is recomputed, not exchanged), so the shape changes
 only the grouping of work.  For each shape forced through HFZ_TILE, three
 V-cycles (FP64) or two mixed-precision steps must match shape 0 to 1e-13
 relative; the kernels are separate instantiations, so floating-point
-contraction may differ in the last bit.  The tuned shapes are reported."""
+contraction may differ in the last bit.  The same holds for the restriction
+variants forced through HFZ_RESTRICT.  The tuned shapes are reported."""
 import numpy as np
 import pytest
 
@@ -27,9 +29,9 @@ def case(model, n, precision):
     return cfg, rho, u, v
 
 
-def run_vcycles(monkeypatch, shape, model, n):
+def run_vcycles(monkeypatch, shape, model, n, env="HFZ_TILE"):
     import paper_1503_07416_amd as pkg
-    monkeypatch.setenv("HFZ_TILE", str(shape))
+    monkeypatch.setenv(env, str(shape))
     cfg, rho, u, v = case(model, n, "fp64")
     sim = pkg.Simulation(cfg)
     sim.set_state(rho, u, v)
@@ -94,3 +96,32 @@ def test_tuned_shapes_match_oracle(monkeypatch):
     assert max(errs) < 1e-11, errs
     r = fas.resnorm(g, S, sol.levels[0])
     assert abs(sim.residual() - r) < 1e-9 * r
+
+
+@pytest.mark.parametrize("model", ["pfc", "cdft"])
+def test_vcycles_same_for_every_restriction(monkeypatch, model):
+    monkeypatch.setenv("HFZ_TILE", "0")
+    ref, _ = run_vcycles(monkeypatch, 0, model, 256, env="HFZ_RESTRICT")
+    for rs in (1, 2):
+        got, _ = run_vcycles(monkeypatch, rs, model, 256, env="HFZ_RESTRICT")
+        for c, (x, y) in enumerate(zip(got, ref)):
+            assert rel_err(x, y) <= 1e-13, (rs, c, rel_err(x, y))
+
+
+@pytest.mark.parametrize("model", ["pfc", "cdft"])
+def test_mixed_steps_same_for_every_restriction(monkeypatch, model):
+    import paper_1503_07416_amd as pkg
+    monkeypatch.setenv("HFZ_TILE", "0")
+    res = {}
+    for rs in (0, 1, 2):
+        monkeypatch.setenv("HFZ_RESTRICT", str(rs))
+        cfg, rho, u, v = case(model, 128, "mixed")
+        sim = pkg.Simulation(cfg)
+        sim.set_state(rho, u, v)
+        st = sim.step(2)
+        res[rs] = ([x.cpu().numpy() for x in sim.get_state()], st.cycles_total)
+        sim.close()
+    for rs in (1, 2):
+        assert res[rs][1] == res[0][1]
+        for x, y in zip(res[rs][0], res[0][0]):
+            assert rel_err(x, y) <= 1e-13
