@@ -24,6 +24,7 @@ template <typename T> struct Hier {
   size_t tail_lds_max = 0;  // dynamic LDS the tail kernel may use
   std::vector<int> tile_shape;      // tile shape of the sweep kernel per level (tile.hpp)
   std::vector<int> restrict_shape;  // restriction variant per fine level (restrict.hpp)
+  std::vector<int> sweep_fuse;      // sweeps per tiled launch per level (2 fused, or 1)
   Phys<T> P{};
 };
 
@@ -138,7 +139,7 @@ int tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const F
 }
 
 // `sweeps` tiled sweeps of level l from cur into the other buffer and back
-// (two per launch).  The first launch applies the coarse-grid correction from
+// (two per launch, or one where the level's sweep schedule says so).  The first launch applies the coarse-grid correction from
 // level l+1 when pro is set; the last launch also computes the residual
 // (res_last: 1 the field d, 2 stop-test partial sums).  On return cur names
 // the buffer holding the iterate.
@@ -148,9 +149,10 @@ int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur,
   const Lvl<T>& L = H.L[l];
   const Lvl<T>& C = H.L[std::min<size_t>(l + 1, H.L.size() - 1)];
   const int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
+  const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
   int blocks = 0;
   while (sweeps > 0) {
-    const int nsw = sweeps >= 2 ? 2 : 1;
+    const int nsw = (sweeps >= 2 && fuse >= 2) ? 2 : 1;
     const int res = (sweeps == nsw) ? res_last : 0;
     if (nsw == 2) {
       if (pro)

@@ -662,6 +662,8 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
     for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
     std::fprintf(stderr, " restriction:");
     for (size_t l = 0; l < hd->H.restrict_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.restrict_shape[l]);
+    std::fprintf(stderr, " sweeps/launch:");
+    for (size_t l = 0; l < hd->H.sweep_fuse.size(); ++l) std::fprintf(stderr, " %d", hd->H.sweep_fuse[l]);
     for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
     std::fprintf(stderr, "\n");
   }

@@ -9,10 +9,12 @@
 // handle's stream, and keeps the fastest.  The kernels' speed does not depend
 // on the values they sweep, so the tuner runs on the workspace as it is; it
 // writes only the second iterate buffer and the residual scratch of the level.
-// The restriction variants (restrict.hpp) are timed the same way per level.
+// The restriction variants (restrict.hpp) are timed the same way per level,
+// and so is the sweep schedule: two sweeps fused per launch or one per launch.
 // Choices are cached per (model, arithmetic type, form, level size) for the
 // life of the process.  HFZ_TILE=<shape> forces one shape where it fits,
-// HFZ_RESTRICT=<variant> one restriction variant, HFZ_TUNE=0 keeps both at 0.
+// HFZ_RESTRICT=<variant> one restriction variant, HFZ_SWEEPS=1 one sweep per
+// launch (2: fused), HFZ_TUNE=0 keeps shape 0, variant 0 and fused sweeps.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -30,8 +32,8 @@ inline std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
 }
-inline std::map<std::tuple<int, int, int, int>, std::pair<int, int>>& tune_cache() {
-  static std::map<std::tuple<int, int, int, int>, std::pair<int, int>> c;
+inline std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>> c;
   return c;
 }
 
@@ -86,6 +88,36 @@ float time_restrict(Hier<T>& H, Cycle& K, int l, int rs, int reps) {
   return ms;
 }
 
+// Average time (ms) of `reps` pre-smoothing passes (two sweeps and the
+// residual field) on level l with `fuse` sweeps per launch.
+template <int MODEL, typename T, bool CORR>
+float time_schedule(Hier<T>& H, Cycle& K, int l, int fuse, int reps) {
+  const int keep = H.sweep_fuse[l];
+  H.sweep_fuse[l] = fuse;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  auto pass = [&]() {
+    Fld<T> cur = fld<T>(H.L[l].g), other = fld<T>(H.L[l].gb);
+    tiled_sweeps<MODEL, T, CORR>(H, K, l, 2, false, cur, other, 1);
+  };
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    pass();
+    bool ok = hipEventRecord(e0, K.stream) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) pass();
+    ok = ok && hipEventRecord(e1, K.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipGetLastError() == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.0f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  H.sweep_fuse[l] = keep;
+  return ms;
+}
+
 // Index of the fastest of `count` candidates timed by `time(k)` (best of
 // three rounds; a later candidate must win by 2%, so near-ties resolve the
 // same way every run); 0 if none could be timed.
@@ -110,8 +142,10 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
   const int nlev = (int)H.L.size();
   H.tile_shape.assign(nlev, 0);
   H.restrict_shape.assign(nlev, 0);
-  int forced_r = -1;
+  H.sweep_fuse.assign(nlev, 2);
+  int forced_r = -1, forced_f = -1;
   if (const char* e = std::getenv("HFZ_RESTRICT")) forced_r = std::atoi(e);
+  if (const char* e = std::getenv("HFZ_SWEEPS")) forced_f = std::atoi(e) == 1 ? 1 : 2;
   int forced = -1;
   if (const char* e = std::getenv("HFZ_TILE")) forced = std::atoi(e);
   bool tune = true;
@@ -122,27 +156,33 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     if (forced >= 0) H.tile_shape[l] = tile_shape_fits(forced, n) ? forced : 0;
     if (forced_r >= 0)
       H.restrict_shape[l] = (forced_r < NUM_RESTRICT_SHAPES && nc % kRestrictTile[forced_r] == 0) ? forced_r : 0;
-    if (!tune || n <= K.tail_n || (forced >= 0 && forced_r >= 0)) continue;
+    if (forced_f > 0) H.sweep_fuse[l] = forced_f;
+    if (!tune || n <= K.tail_n || (forced >= 0 && forced_r >= 0 && forced_f > 0)) continue;
     const auto key = std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, n);
     {
       std::lock_guard<std::mutex> g(tune_mutex());
       auto it = tune_cache().find(key);
       if (it != tune_cache().end()) {
-        if (forced < 0) H.tile_shape[l] = it->second.first;
-        if (forced_r < 0) H.restrict_shape[l] = it->second.second;
+        if (forced < 0) H.tile_shape[l] = std::get<0>(it->second);
+        if (forced_r < 0) H.restrict_shape[l] = std::get<1>(it->second);
+        if (forced_f < 0) H.sweep_fuse[l] = std::get<2>(it->second);
         continue;
       }
     }
     const int ts = pick_fastest(NUM_TILE_SHAPES, [&](int k) {
       return tile_shape_fits(k, n) ? time_shape<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
     });
+    if (forced < 0) H.tile_shape[l] = ts;
     const int rs = pick_fastest(NUM_RESTRICT_SHAPES, [&](int k) {
       return nc % kRestrictTile[k] == 0 ? time_restrict<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
     });
-    if (forced < 0) H.tile_shape[l] = ts;
     if (forced_r < 0) H.restrict_shape[l] = rs;
+    // sweep schedule in the chosen shape: candidate 0 fuses two sweeps per
+    // launch, candidate 1 launches one sweep at a time
+    const int fs = pick_fastest(2, [&](int k) { return time_schedule<MODEL, T, CORR>(H, K, l, k == 0 ? 2 : 1, 8); });
+    if (forced_f < 0) H.sweep_fuse[l] = fs == 0 ? 2 : 1;
     std::lock_guard<std::mutex> g(tune_mutex());
-    tune_cache()[key] = std::make_pair(ts, rs);
+    tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1);
   }
 }
 

@@ -125,3 +125,14 @@ def test_mixed_steps_same_for_every_restriction(monkeypatch, model):
         assert res[rs][1] == res[0][1]
         for x, y in zip(res[rs][0], res[0][0]):
             assert rel_err(x, y) <= 1e-13
+
+
+@pytest.mark.parametrize("model", ["pfc", "cdft"])
+def test_vcycles_same_for_either_sweep_schedule(monkeypatch, model):
+    """One sweep per launch (HFZ_SWEEPS=1) against two fused sweeps."""
+    monkeypatch.setenv("HFZ_TILE", "0")
+    monkeypatch.setenv("HFZ_RESTRICT", "0")
+    ref, _ = run_vcycles(monkeypatch, 2, model, 256, env="HFZ_SWEEPS")
+    got, _ = run_vcycles(monkeypatch, 1, model, 256, env="HFZ_SWEEPS")
+    for c, (x, y) in enumerate(zip(got, ref)):
+        assert rel_err(x, y) <= 1e-13, (c, rel_err(x, y))
