@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
+    ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
     ap.add_argument("--probe-tile-shape", type=int, default=2,
                     help="tile shape of the counter probe (the one the tuner picks at 512^2)")
     ap.add_argument("--counter-probe", action="store_true",
@@ -367,6 +368,16 @@ def main():
         return
     if a.cdft_only:
         print(json.dumps({"cdft": run_cdft()}))
+        return
+    if a.mixed_only:
+        import torch
+        import workloads
+        import paper_1503_07416_amd as pkg
+        cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0)
+        sim = pkg.Simulation(cfg, device="cuda:0")
+        sim.set_state(rho, u, v)
+        sim.step(a.warmup + a.steps)
+        print(json.dumps({"mixed": run_mixed(a, sim.get_state())}))
         return
     import torch
     import workloads

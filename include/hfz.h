@@ -76,14 +76,15 @@ typedef struct hfz_params {
   int max_cycles;     /* V-cycle cap per step (>= 1) */
   int coarsest_n;     /* coarsest grid size, power of two, 4 <= coarsest_n <= n */
   int coarse_sweeps;  /* sweeps on the coarsest grid per V-cycle (>= 1) */
-  int precision;      /* HFZ_FP64, or HFZ_MIXED: FP32 smoothing inside FP64 defect correction */
+  int precision;      /* HFZ_FP64, or HFZ_MIXED: FP32 smoothing inside FP64 defect correction
+                         (three FP32 V-cycles per outer FP64 iteration) */
   int sigma;          /* +1: -rho omega x u in vector form (default); -1: App. G sign */
   int continuity_fix; /* 1: recompute rho^{k+1} from the continuity row after the solve */
 } hfz_params;
 
 typedef struct hfz_stats {
   int steps_done;       /* steps completed by this call */
-  int cycles_last;      /* V-cycles (mixed: outer corrections) of the last step */
+  int cycles_last;      /* V-cycles (mixed: outer FP64 iterations) of the last step */
   long long cycles_total;
   double residual_last; /* final ||S - N(g)||_2 of the last step */
 } hfz_stats;

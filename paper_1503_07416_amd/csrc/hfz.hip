@@ -102,6 +102,7 @@ struct hfz_handle {
   size_t partial_cap = 0;
   int tail_n = 32;  // levels of this size and below run in the one-workgroup tail kernel
   bool use_graph = true;
+  int mp_inner = 3;  // FP32 V-cycles per outer defect-correction iteration
   bool use_tiles = true;  // LDS-tiled kernels on levels >= 32
   int norm_partials = 0;  // > 0: the last V-cycle's post-sweep left this many residual partials
   int graph_state = 0;  // 0: not built, 1: built, -1: unavailable
@@ -372,17 +373,19 @@ void mp_prepare_launch(hfz_handle* hd) {
   k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, (int)(g.x * g.y), 1, L.h * L.h, hd->result);
 }
 
-// One outer iteration: an FP32 V-cycle on the correction problem, g += e,
-// and the next outer residual.
+// One outer iteration: mp_inner FP32 V-cycles on the correction problem
+// (three by default: the FP32 solve is cheap next to the FP64 residual and
+// the host stop test each outer iteration costs; HFZ_MP_INNER overrides),
+// g += e, and the next outer residual.
 void mp_cycle(hfz_handle* hd) {
   Cycle K = cycle_ctx(hd);
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
   if (hd->p.model == HFZ_PFC) {
-    hfz::vcycle<PFC, float, true>(hd->H32, K);
+    for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<PFC, float, true>(hd->H32, K);
     k_mp_update<PFC><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
   } else {
-    hfz::vcycle<CDFT, float, true>(hd->H32, K);
+    for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<CDFT, float, true>(hd->H32, K);
     k_mp_update<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
   }
   mp_prepare_launch(hd);
@@ -656,6 +659,7 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
       if (p->precision == HFZ_MIXED) tune_tile_shapes<CDFT, float, true>(hd->H32, K);
     }
   }
+  if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));
   if (std::getenv("HFZ_VERBOSE")) {
     std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p->n, hd->nlev,
                  hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
@@ -1051,7 +1055,8 @@ template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
   const dim3 b = block2(n, n);
   const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, B->count);
   if (B->p.precision == HFZ_MIXED) {
-    bvcycle_rec<MODEL, float, true>(B, h0->H32.L, B->D32, B->T32, B->P32, B->lds32, K, 0);
+    for (int i = 0; i < h0->mp_inner; ++i)
+      bvcycle_rec<MODEL, float, true>(B, h0->H32.L, B->D32, B->T32, B->P32, B->lds32, K, 0);
     k_mp_update_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->D32, B->active);
     k_mp_prepare_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
     k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,

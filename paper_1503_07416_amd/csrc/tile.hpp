@@ -60,8 +60,12 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RN];
   __shared__ T sb[NB][CORR ? RN : 1];
-  __shared__ T se[PRO ? NCm : 1][PRO ? CRN : 1];
-  __shared__ T sm[PM ? RN : 1];
+  // se (the coarse correction, read only while loading) and sm (the
+  // potential, written only after the load) share one LDS array
+  constexpr int SE = PRO ? NCm * CRN : 0, SM = PM ? RN : 0;
+  __shared__ T sx[(SE > SM ? SE : SM) > 0 ? (SE > SM ? SE : SM) : 1];
+  T(*se)[CRN] = reinterpret_cast<T(*)[CRN]>(sx);
+  T* sm = sx;
   const int m = L.n - 1, lg = L.lg;
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
   const int x0 = (int)blockIdx.x * TILE_X - H, y0 = (int)blockIdx.y * TILE_Y - H;
