@@ -34,6 +34,7 @@ struct Cycle {
   int tail_n = 32;
   bool use_tiles = true;
   double* partial = nullptr;  // stop-test partial sums of the finest level
+  const int* halt = nullptr;  // device stop flag of the V-cycle loop (the kernels' Phys carry it too)
   int norm_partials = 0;      // out: > 0 when the last post-sweep left that many partials
 };
 
@@ -174,7 +175,7 @@ int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur,
 
 template <typename T> void copy_fields(Cycle& K, const Fld<T>& a, const Fld<T>& b, int nc, size_t cnt) {
   for (int c = 0; c < nc; ++c)
-    k_copy_t<T><<<(unsigned)((cnt + 255) / 256), 256, 0, K.stream>>>(a.c[c], b.c[c], cnt);
+    k_copy_t<T><<<(unsigned)((cnt + 255) / 256), 256, 0, K.stream>>>(a.c[c], b.c[c], cnt, K.halt);
 }
 
 template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l);
@@ -235,7 +236,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K
     const Lvl<T>& C = H.L[l + 1];
     const dim3 bc = block2(C.n, C.n), bf = block2(F.n, F.n);
     k_residual_field<MODEL, T><<<grid2(F.n, F.n, bf), bf, 0, K.stream>>>(F, H.P);
-    k_restrict_gd<MODEL, T><<<grid2(C.n, C.n, bc), bc, 0, K.stream>>>(F, C);
+    k_restrict_gd<MODEL, T><<<grid2(C.n, C.n, bc), bc, 0, K.stream>>>(F, C, K.halt);
     k_fas_rhs<MODEL, T><<<grid2(C.n, C.n, bc), bc, 0, K.stream>>>(C, H.P);
     vcycle_rec<MODEL, T, CORR>(H, K, l + 1);
     k_prolong<MODEL, T><<<grid2(F.n, F.n, bf), bf, 0, K.stream>>>(F, C, H.P);

@@ -99,6 +99,8 @@ struct hfz_handle {
   // reductions
   double* partial = nullptr;
   double* result = nullptr;
+  int* ctl = nullptr;  // device stop flag and cycle counter of the V-cycle loop (inside result)
+  int cycle_hint = 4;  // V-cycles (mixed: outer iterations) the previous step needed
   size_t partial_cap = 0;
   int tail_n = 32;  // levels of this size and below run in the one-workgroup tail kernel
   bool use_graph = true;
@@ -178,6 +180,7 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     hd->fb = fb;
     hd->partial = partial;
     hd->result = result;
+    hd->ctl = reinterpret_cast<int*>(result + 8);
     hd->partial_cap = pcap;
     hd->H.desc = desc;
   }
@@ -259,23 +262,33 @@ Cycle cycle_ctx(hfz_handle* hd) {
   K.tail_n = hd->tail_n;
   K.use_tiles = hd->use_tiles;
   K.partial = hd->partial;
+  K.halt = hd->ctl;
   return K;
 }
 
 // Enqueues h^2 sum (f - N(g))^2 on level 0 into result[0].
-template <int MODEL> void residual_launch_t(hfz_handle* hd) {
-  const Lvl<double>& L = hd->H.L[0];
-  const Dims d = dims2(L.n, L.n);
-  const int nb = d.grid.x * d.grid.y;
-  k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->H.P, hd->partial);
-  k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, nb, 1, L.h * L.h, hd->result);
+// The final reduction of `count` stop-test partials into result[0]; with
+// `stop`, the device stop test of the V-cycle loop as well (k_reduce_stop).
+void reduce_launch(hfz_handle* hd, int count, bool stop) {
+  const double h2 = hd->H.L[0].h * hd->H.L[0].h;
+  if (stop)
+    k_reduce_stop<<<1, 1024, 0, hd->stream>>>(hd->partial, count, h2, hd->p.tol, hd->result, hd->ctl);
+  else
+    k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, count, 1, h2, hd->result);
 }
 
-void residual_launch(hfz_handle* hd) {
+template <int MODEL> void residual_launch_t(hfz_handle* hd, bool stop) {
+  const Lvl<double>& L = hd->H.L[0];
+  const Dims d = dims2(L.n, L.n);
+  k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->H.P, hd->partial);
+  reduce_launch(hd, (int)(d.grid.x * d.grid.y), stop);
+}
+
+void residual_launch(hfz_handle* hd, bool stop = false) {
   if (hd->p.model == HFZ_PFC)
-    residual_launch_t<PFC>(hd);
+    residual_launch_t<PFC>(hd, stop);
   else
-    residual_launch_t<CDFT>(hd);
+    residual_launch_t<CDFT>(hd, stop);
 }
 
 int residual_read(hfz_handle* hd, double* norm) {
@@ -302,19 +315,19 @@ void vcycle(hfz_handle* hd) {
 
 // A V-cycle and the stop-test residual norm after it (the last post-sweep
 // may already have left the partial sums).
-void vcycle_and_norm(hfz_handle* hd) {
+void vcycle_and_norm(hfz_handle* hd, bool stop) {
   vcycle(hd);
   if (hd->norm_partials > 0)
-    k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, hd->norm_partials, 1, hd->H.L[0].h * hd->H.L[0].h,
-                                               hd->result);
+    reduce_launch(hd, hd->norm_partials, stop);
   else
-    residual_launch(hd);
+    residual_launch(hd, stop);
 }
 
-// One V-cycle followed by the residual norm, captured once into a HIP graph
-// (on a private stream: capture records, it does not execute) and replayed on
-// the caller's stream.  Returns false when graphs are unavailable; callers
-// then launch the kernels one by one.
+// One V-cycle followed by the residual norm and the device stop test,
+// captured once into a HIP graph (on a private stream: capture records, it
+// does not execute) and replayed on the caller's stream.  Returns false when
+// graphs are unavailable; callers then launch the kernels one by one and test
+// on the host.
 bool cycle_graph(hfz_handle* hd) {
   if (hd->graph_state == 1) return true;
   if (hd->graph_state < 0) return false;
@@ -326,7 +339,7 @@ bool cycle_graph(hfz_handle* hd) {
     hd->stream = cap;
     ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      vcycle_and_norm(hd);
+      vcycle_and_norm(hd, true);
       ok = hipStreamEndCapture(cap, &g) == hipSuccess;
     }
     hd->stream = user;
@@ -339,13 +352,10 @@ bool cycle_graph(hfz_handle* hd) {
   return ok;
 }
 
-// One V-cycle and the residual norm that follows it.
+// One V-cycle and the residual norm that follows it, launched kernel by
+// kernel (the host-tested loop).
 int cycle_and_residual(hfz_handle* hd, double* norm) {
-  if (hd->use_graph && cycle_graph(hd)) {
-    if (hipGraphLaunch(hd->cycle_exec, hd->stream) != hipSuccess) return HFZ_EHIP;
-  } else {
-    vcycle_and_norm(hd);
-  }
+  vcycle_and_norm(hd, false);
   return residual_read(hd, norm);
 }
 
@@ -363,32 +373,32 @@ void mp_begin(hfz_handle* hd) {
 
 // d = S - N(g) in FP64 -> inner right-hand side, base state, e = 0, and the
 // outer stop-test norm into result[0].
-void mp_prepare_launch(hfz_handle* hd) {
+void mp_prepare_launch(hfz_handle* hd, bool stop = false) {
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
   if (hd->p.model == HFZ_PFC)
     k_mp_prepare<PFC><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
   else
     k_mp_prepare<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
-  k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, (int)(g.x * g.y), 1, L.h * L.h, hd->result);
+  reduce_launch(hd, (int)(g.x * g.y), stop);
 }
 
 // One outer iteration: mp_inner FP32 V-cycles on the correction problem
 // (three by default: the FP32 solve is cheap next to the FP64 residual and
 // the host stop test each outer iteration costs; HFZ_MP_INNER overrides),
 // g += e, and the next outer residual.
-void mp_cycle(hfz_handle* hd) {
+void mp_cycle(hfz_handle* hd, bool stop) {
   Cycle K = cycle_ctx(hd);
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
   if (hd->p.model == HFZ_PFC) {
     for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<PFC, float, true>(hd->H32, K);
-    k_mp_update<PFC><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
+    k_mp_update<PFC><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
   } else {
     for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<CDFT, float, true>(hd->H32, K);
-    k_mp_update<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0]);
+    k_mp_update<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
   }
-  mp_prepare_launch(hd);
+  mp_prepare_launch(hd, stop);
 }
 
 bool mp_graph(hfz_handle* hd) {
@@ -402,7 +412,7 @@ bool mp_graph(hfz_handle* hd) {
     hd->stream = cap;
     ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      mp_cycle(hd);
+      mp_cycle(hd, true);
       ok = hipStreamEndCapture(cap, &g) == hipSuccess;
     }
     hd->stream = user;
@@ -416,12 +426,74 @@ bool mp_graph(hfz_handle* hd) {
 }
 
 int mp_cycle_and_residual(hfz_handle* hd, double* norm) {
-  if (hd->use_graph && mp_graph(hd)) {
-    if (hipGraphLaunch(hd->mp_exec, hd->stream) != hipSuccess) return HFZ_EHIP;
-  } else {
-    mp_cycle(hd);
-  }
+  mp_cycle(hd, false);
   return residual_read(hd, norm);
+}
+
+// The V-cycles of one step after the initial residual r (> tol, finite):
+// on the device-tested path the cycle graph is enqueued in batches (the first
+// as long as the previous step needed), each cycle ending in k_reduce_stop,
+// which raises the stop flag once ||S - N(g)|| <= tol or is not finite; the
+// kernels of cycles enqueued past that point return at once, so the cycles
+// that run, their count and the final norm are those of the host-tested loop,
+// at one host round trip per batch.  Without graphs every cycle is tested on
+// the host.
+int run_cycles(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
+  int cycles = 0;
+  const bool graph = hd->use_graph && (mixed ? mp_graph(hd) : cycle_graph(hd));
+  if (!graph) {
+    int rc = HFZ_OK;
+    while (!(*r <= hd->p.tol)) {
+      if (!std::isfinite(*r)) {
+        rc = HFZ_ENAN;
+        break;
+      }
+      if (cycles >= hd->p.max_cycles) {
+        rc = HFZ_ENOCONV;
+        break;
+      }
+      ++cycles;
+      rc = mixed ? mp_cycle_and_residual(hd, r) : cycle_and_residual(hd, r);
+      if (rc != HFZ_OK) break;
+    }
+    *cycles_out = cycles;
+    return rc;
+  }
+  hipGraphExec_t exec = mixed ? hd->mp_exec : hd->cycle_exec;
+  k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
+  int rc = HFZ_OK;
+  int batch = std::max(1, hd->cycle_hint);
+  for (;;) {
+    const int remaining = hd->p.max_cycles - cycles;
+    if (remaining <= 0) {
+      rc = HFZ_ENOCONV;
+      break;
+    }
+    const int nb = std::min(batch, remaining);
+    for (int i = 0; i < nb && rc == HFZ_OK; ++i)
+      if (hipGraphLaunch(exec, hd->stream) != hipSuccess) rc = HFZ_EHIP;
+    if (rc != HFZ_OK) break;
+    double h[10];
+    if (hipMemcpyAsync(h, hd->result, sizeof(h), hipMemcpyDeviceToHost, hd->stream) != hipSuccess ||
+        hipStreamSynchronize(hd->stream) != hipSuccess) {
+      rc = HFZ_EHIP;
+      break;
+    }
+    int ctl[2];
+    std::memcpy(ctl, &h[8], sizeof(ctl));
+    cycles = ctl[1];
+    *r = std::sqrt(h[0]);
+    if (ctl[0] == 1) break;
+    if (ctl[0] == 2) {
+      rc = HFZ_ENAN;
+      break;
+    }
+    batch = 2;
+  }
+  k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
+  if (rc == HFZ_OK) hd->cycle_hint = cycles;
+  *cycles_out = cycles;
+  return rc == HFZ_OK ? last_error() : rc;
 }
 
 // (J * rho) of Eq. discrete_convolution: jrho = IDFT(mult . DFT(rho)) / n^2.
@@ -629,6 +701,9 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->H32.P.delta = (float)p->delta;
   hd->H32.P.w = (float)p->w_damp;
   hd->H32.P.ce = 0.0f;
+  hd->H.P.halt = hd->ctl;
+  hd->H32.P.halt = hd->ctl;
+  k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
   // opt in to the large LDS of a gfx950 CU for the tail kernels
   if (p->model == HFZ_PFC) {
     hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<PFC, double, false>));
@@ -794,18 +869,11 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
     }
     if (rc != HFZ_OK) break;
     int cycles = 0;
-    while (!(r <= hd->p.tol)) {
-      if (!std::isfinite(r)) {
+    if (!(r <= hd->p.tol)) {
+      if (!std::isfinite(r))
         rc = HFZ_ENAN;
-        break;
-      }
-      if (cycles >= hd->p.max_cycles) {
-        rc = HFZ_ENOCONV;
-        break;
-      }
-      ++cycles;
-      rc = mixed ? mp_cycle_and_residual(hd, &r) : cycle_and_residual(hd, &r);
-      if (rc != HFZ_OK) break;
+      else
+        rc = run_cycles(hd, mixed, &r, &cycles);
     }
     st.cycles_last = cycles;
     st.residual_last = r;

@@ -80,6 +80,7 @@ __global__ void k_restrict_coef(const T* __restrict__ rf, const T* __restrict__ 
 // the coarse levels.
 template <int MODEL, typename T, int FINE>
 __global__ void k_smooth_colour(Lvl<T> L, Phys<T> P, int colour) {
+  if (halted(P.halt)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int n = L.n;
@@ -97,6 +98,7 @@ __global__ void k_smooth_colour(Lvl<T> L, Phys<T> P, int colour) {
 // the nine fine nodes of the full-weighting footprint).
 template <int MODEL, typename T>
 __global__ void k_fas_restrict(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  if (halted(P.halt)) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
   if (I >= C.n || J >= C.n) return;
@@ -132,6 +134,7 @@ __global__ void k_fas_restrict(Lvl<T> F, Lvl<T> C, Phys<T> P) {
 // evaluation per node) ...
 template <int MODEL, typename T>
 __global__ void k_residual_field(Lvl<T> F, Phys<T> P) {
+  if (halted(P.halt)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= F.n || j >= F.n) return;
@@ -145,7 +148,8 @@ __global__ void k_residual_field(Lvl<T> F, Phys<T> P) {
 
 // ... then g_c = g0_c = R g and f_c = R d on the coarse grid.
 template <int MODEL, typename T>
-__global__ void k_restrict_gd(Lvl<T> F, Lvl<T> C) {
+__global__ void k_restrict_gd(Lvl<T> F, Lvl<T> C, const int* halt) {
+  if (halted(halt)) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
   if (I >= C.n || J >= C.n) return;
@@ -163,6 +167,7 @@ __global__ void k_restrict_gd(Lvl<T> F, Lvl<T> C) {
 // K6b: f_c += N_c(R g), the FAS coarse right-hand side.
 template <int MODEL, typename T>
 __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
+  if (halted(P.halt)) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
   if (I >= C.n || J >= C.n) return;
@@ -177,6 +182,7 @@ __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
 // K7: g += P(g_c - R g), bilinear; CDFT re-projects rho.
 template <int MODEL, typename T>
 __global__ void k_prolong(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  if (halted(P.halt)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= F.n || j >= F.n) return;
@@ -230,6 +236,7 @@ __device__ __forceinline__ double block_sum(double x, double* lds) {
 // K5: per-block partial sums of sum_c (f - N(g))^2.
 template <int MODEL, typename T>
 __global__ void k_residual_partial(Lvl<T> L, Phys<T> P, double* __restrict__ partial) {
+  if (halted(P.halt)) return;
   __shared__ double lds[16];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -262,6 +269,34 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int count, in
   }
 }
 
+// The stop test of a V-cycle on the device: unless the flag ctl[0] is already
+// set, result[0] = scale * (sum of the partials, in k_reduce_final's order),
+// ctl[1] += 1 (cycles run), and ctl[0] = 1 if sqrt(result[0]) <= tol, 2 if it
+// is not finite.  One workgroup of 1024 threads.
+__global__ void k_reduce_stop(const double* __restrict__ partial, int count, double scale, double tol,
+                              double* __restrict__ result, int* ctl) {
+  __shared__ double lds[16];
+  if (ctl[0] != 0) return;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < count; t += blockDim.x) acc += partial[t];
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0) {
+    const double r2 = scale * r;
+    result[0] = r2;
+    ctl[1] += 1;
+    const double nrm = sqrt(r2);
+    if (nrm <= tol)
+      ctl[0] = 1;
+    else if (!isfinite(nrm))
+      ctl[0] = 2;
+  }
+}
+
+// Clears the stop flag and the cycle counter.
+__global__ void k_ctl_reset(int* ctl) {
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
+}
+
 // --------------------------------------------------------- post-step -----
 // K10: rho^{k+1} = S1 - s/(4h)[(rho^k u)_E - (rho^k u)_W + (rho^k v)_N - (rho^k v)_S]
 // with the converged velocity (Eq. discrete_a), written into dst.
@@ -282,7 +317,8 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
 }
 
 template <typename T>
-__global__ void k_copy_t(const T* __restrict__ a, T* __restrict__ b, size_t count) {
+__global__ void k_copy_t(const T* __restrict__ a, T* __restrict__ b, size_t count, const int* halt) {
+  if (halted(halt)) return;
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) b[t] = a[t];
 }
@@ -299,6 +335,7 @@ __global__ void k_cast(const double* __restrict__ a, float* __restrict__ b, size
 // per-block partial sums of |d|^2 are the outer stop test.
 template <int MODEL>
 __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double* __restrict__ partial) {
+  if (halted(P.halt)) return;
   __shared__ double lds[16];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -324,7 +361,8 @@ __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double
 
 // After the inner V-cycle: g += e (the FP32 correction added in FP64).
 template <int MODEL>
-__global__ void k_mp_update(Lvl<double> L, Lvl<float> E) {
+__global__ void k_mp_update(Lvl<double> L, Lvl<float> E, const int* halt) {
+  if (halted(halt)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= L.n || j >= L.n) return;

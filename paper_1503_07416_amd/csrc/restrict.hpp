@@ -79,6 +79,7 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
 
 template <int MODEL, typename T, bool CORR>
 __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  if (halted(P.halt)) return;
   restrict_fas_body<MODEL, T, CORR>(F, C, P);
 }
 
@@ -191,6 +192,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
 
 template <int MODEL, typename T, bool CORR, int RT, int NT>
 __global__ __launch_bounds__(NT) void k_restrict_fas_staged(Lvl<T> F, Lvl<T> C, Phys<T> P) {
+  if (halted(P.halt)) return;
   restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, C, P);
 }
 

@@ -19,10 +19,16 @@ __device__ __forceinline__ float flog(float x) { return logf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
 
-// Physical constants of the step, in the arithmetic type T.
+// Physical constants of the step, in the arithmetic type T, and the device
+// stop flag of the V-cycle loop (null: none).  A V-cycle kernel whose flag is
+// set returns at once: the cycles the host enqueued past convergence do
+// nothing.
 template <typename T> struct Phys {
   T s, gamma, sigma, alpha, ce, delta, w;
+  const int* halt;
 };
+
+__device__ __forceinline__ bool halted(const int* flag) { return flag != nullptr && *flag != 0; }
 
 // Stencil coefficients of one level: s/(4h), s/(2h), 1/h^2.
 template <typename T> struct Coef {

@@ -266,6 +266,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
 
 template <int MODEL, typename T, bool CORR>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P) {
+  if (halted(P.halt)) return;
   tail_body<MODEL, T, CORR>(A, P);
 }
 

@@ -203,6 +203,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
                                                                     Phys<T> P, double* partial) {
+  if (halted(P.halt)) return;
   sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
 }
 
