@@ -109,4 +109,44 @@ __global__ void k_reduce_b(const double* __restrict__ partial, int count, int ps
   }
 }
 
+// The per-instance stop test on the device: for each active instance z,
+// norm2[z] = h_z^2 * (sum of its partials, in k_reduce_b's order); with
+// `counted` the cycle that produced it is counted in cyc[z]; the instance
+// leaves the batch with stat[z] = 1 once sqrt(norm2) <= tol[z], 2 if the norm
+// is not finite, 3 if cyc[z] reached maxc[z].  One workgroup per instance.
+__global__ void k_reduce_stop_b(const double* __restrict__ partial, int count, int pstride, const Lvl<double>* Ls,
+                                int* active, double* __restrict__ norm2, int* cyc, int* stat,
+                                const double* __restrict__ tol, const int* __restrict__ maxc, int counted) {
+  __shared__ double lds[16];
+  const int z = blockIdx.x;
+  if (!active[z]) return;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < count; t += blockDim.x) acc += partial[(size_t)z * pstride + t];
+  const double r = block_sum(acc, lds);
+  if (threadIdx.x == 0) {
+    const double h = Ls[z].h;
+    const double n2 = h * h * r;
+    norm2[z] = n2;
+    if (counted) cyc[z] += 1;
+    const double nrm = sqrt(n2);
+    int s = 0;
+    if (nrm <= tol[z])
+      s = 1;
+    else if (!isfinite(nrm))
+      s = 2;
+    else if (cyc[z] >= maxc[z])
+      s = 3;
+    if (s != 0) {
+      stat[z] = s;
+      active[z] = 0;
+    }
+  }
+}
+
+// a[0..count) = 0.
+__global__ void k_zero_ints(int* a, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) a[t] = 0;
+}
+
 }  // namespace hfz

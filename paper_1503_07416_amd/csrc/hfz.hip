@@ -1014,8 +1014,13 @@ struct hfz_batch {
   Phys<float>* P32 = nullptr;
   int* active = nullptr;
   double* norm2 = nullptr;
+  int* cyc = nullptr;     // [count] V-cycles (mixed: outer iterations) of the current step
+  int* stat = nullptr;    // [count] 0 running, 1 converged, 2 not finite, 3 max_cycles reached
+  double* tol = nullptr;  // [count]
+  int* maxc = nullptr;    // [count]
   double* partial = nullptr;
   int pstride = 0;
+  int cycle_hint = 4;  // most cycles an instance needed in the previous step
   size_t lds64 = 0, lds32 = 0;
   std::vector<int> h_active;
   std::vector<double> h_norm2;
@@ -1048,6 +1053,8 @@ BatchLayout batch_layout(const hfz_params* ps, int count) {
   c.take<Phys<double>>(count);
   c.take<Phys<float>>(count);
   c.take<int>(count);
+  c.take<double>(count);
+  c.take<int>((size_t)count * 3);
   c.take<double>(count);
   c.take<double>((N2 / 256 + 64) * count);
   bl.total = bl.off_arrays + c.off;
@@ -1112,8 +1119,8 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
   if (inb) k_swap_back_b<T><<<dim3((n * n + 255) / 256, 1, count), 256, 0, K.stream>>>(Dl, B->active, NCm);
 }
 
-// Enqueues one batched V-cycle (mixed: one outer iteration) and the
-// per-instance stop-test norms into B->norm2.
+// Enqueues one batched V-cycle (mixed: one outer iteration), the
+// per-instance stop-test norms into B->norm2 and the device stop test.
 template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
   hfz_handle* h0 = B->inst[0];
   Cycle K = cycle_ctx(h0);
@@ -1127,18 +1134,18 @@ template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
       bvcycle_rec<MODEL, float, true>(B, h0->H32.L, B->D32, B->T32, B->P32, B->lds32, K, 0);
     k_mp_update_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->D32, B->active);
     k_mp_prepare_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
-    k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                              B->norm2);
+    k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                                   B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
   } else {
     bvcycle_rec<MODEL, double, false>(B, h0->H.L, B->D64, B->T64, B->P64, B->lds64, K, 0);
     const bool tiled_top = n > K.tail_n;
     if (tiled_top) {
-      k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / TILE_X) * (n / TILE_Y), B->pstride, B->D64,
-                                                B->active, B->norm2);
+      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / TILE_X) * (n / TILE_Y), B->pstride, B->D64,
+                                                     B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
     } else {
       k_residual_partial_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
-      k_reduce_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                                B->norm2);
+      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                                     B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
     }
   }
 }
@@ -1152,8 +1159,8 @@ template <int MODEL> void batch_first_norm(hfz_batch* B) {
     k_mp_prepare_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
   else
     k_residual_partial_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
-  k_reduce_b<<<B->count, 1024, 0, B->stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                               B->norm2);
+  k_reduce_stop_b<<<B->count, 1024, 0, B->stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
+                                                    B->norm2, B->cyc, B->stat, B->tol, B->maxc, 0);
 }
 
 void batch_cycle_any(hfz_batch* B, hipStream_t s) {
@@ -1181,12 +1188,6 @@ int batch_launch_cycle(hfz_batch* B) {
   }
   if (B->graph_state == 1) return hipGraphLaunch(B->exec, B->stream) == hipSuccess ? HFZ_OK : HFZ_EHIP;
   batch_cycle_any(B, B->stream);
-  return last_error();
-}
-
-int batch_read_norms(hfz_batch* B) {
-  HIPCHK(hipMemcpyAsync(B->h_norm2.data(), B->norm2, B->count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-  HIPCHK(hipStreamSynchronize(B->stream));
   return last_error();
 }
 
@@ -1250,6 +1251,11 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   B->P32 = c.take<Phys<float>>(count);
   B->active = c.take<int>(count);
   B->norm2 = c.take<double>(count);
+  int* ints = c.take<int>((size_t)count * 3);
+  B->cyc = ints;
+  B->stat = ints + count;
+  B->maxc = ints + 2 * count;
+  B->tol = c.take<double>(count);
   B->pstride = (int)((size_t)params[0].n * params[0].n / 256 + 64);
   B->partial = c.take<double>((size_t)B->pstride * count);
   const bool mixed = params[0].precision == HFZ_MIXED;
@@ -1293,6 +1299,16 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
                  hipSuccess;
   ok = ok && hipMemcpyAsync(B->P32, p32.data(), count * sizeof(Phys<float>), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
+  std::vector<double> tols(count);
+  std::vector<int> maxcs(count);
+  for (int i = 0; i < count; ++i) {
+    tols[i] = params[i].tol;
+    maxcs[i] = params[i].max_cycles;
+  }
+  ok = ok && hipMemcpyAsync(B->tol, tols.data(), count * sizeof(double), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(B->maxc, maxcs.data(), count * sizeof(int), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
   ok = ok && hipStreamSynchronize(B->stream) == hipSuccess;
   if (!ok) {
     hfz_batch_destroy(B);
@@ -1335,7 +1351,7 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
   if (nfilled == 0) return HFZ_OK;
   const bool mixed = B->p.precision == HFZ_MIXED;
   std::vector<hfz_stats> st(count);
-  std::vector<int> cycles(count), failed(count, 0);
+  std::vector<int> h_cyc(count), h_stat(count);
   int rc = HFZ_OK;
   for (int k = 0; k < nsteps && rc == HFZ_OK; ++k) {
     for (int i = 0; i < count && rc == HFZ_OK; ++i) {
@@ -1344,52 +1360,51 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
       if (rc == HFZ_OK && mixed) mp_begin(B->inst[i]);
     }
     if (rc != HFZ_OK) break;
+    // every instance runs until its own stop test ends it (on the device);
+    // the host enqueues cycles in batches and reads the states once a batch
     for (int i = 0; i < count; ++i) B->h_active[i] = filled[i];
-    std::fill(cycles.begin(), cycles.end(), 0);
     rc = batch_write_active(B);
     if (rc != HFZ_OK) break;
+    k_zero_ints<<<(2 * count + 255) / 256, 256, 0, B->stream>>>(B->cyc, 2 * count);
     if (B->p.model == HFZ_PFC)
       batch_first_norm<PFC>(B);
     else
       batch_first_norm<CDFT>(B);
-    rc = batch_read_norms(B);
-    while (rc == HFZ_OK) {
-      bool changed = false;
-      int live = 0;
-      for (int i = 0; i < count; ++i) {
-        if (!B->h_active[i]) continue;
-        const double r = std::sqrt(B->h_norm2[i]);
-        int fail = 0;
-        if (r <= B->inst[i]->p.tol) {
-        } else if (!std::isfinite(r)) {
-          fail = HFZ_ENAN;
-        } else if (cycles[i] >= B->inst[i]->p.max_cycles) {
-          fail = HFZ_ENOCONV;
-        } else {
-          ++live;
-          continue;
-        }
-        B->h_active[i] = 0;
-        changed = true;
-        failed[i] = fail;
-        st[i].cycles_last = cycles[i];
-        st[i].residual_last = r;
-      }
-      if (live == 0) break;
-      if (changed) rc = batch_write_active(B);
+    int batch = std::max(1, B->cycle_hint);
+    for (;;) {
+      for (int c = 0; c < batch && rc == HFZ_OK; ++c) rc = batch_launch_cycle(B);
       if (rc != HFZ_OK) break;
-      for (int i = 0; i < count; ++i)
-        if (B->h_active[i]) ++cycles[i];
-      rc = batch_launch_cycle(B);
-      if (rc == HFZ_OK) rc = batch_read_norms(B);
+      if (hipMemcpyAsync(h_cyc.data(), B->cyc, count * sizeof(int), hipMemcpyDeviceToHost, B->stream) != hipSuccess ||
+          hipMemcpyAsync(h_stat.data(), B->stat, count * sizeof(int), hipMemcpyDeviceToHost, B->stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(B->h_norm2.data(), B->norm2, count * sizeof(double), hipMemcpyDeviceToHost, B->stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(B->stream) != hipSuccess) {
+        rc = HFZ_EHIP;
+        break;
+      }
+      bool running = false;
+      for (int i = 0; i < count; ++i) running = running || (filled[i] && h_stat[i] == 0);
+      if (!running) break;
+      batch = 2;
     }
     if (rc != HFZ_OK) break;
+    int most = 0;
+    std::vector<int> failed(count, 0);
+    for (int i = 0; i < count; ++i) {
+      if (!filled[i]) continue;
+      st[i].cycles_last = h_cyc[i];
+      st[i].residual_last = std::sqrt(B->h_norm2[i]);
+      failed[i] = h_stat[i] == 2 ? HFZ_ENAN : h_stat[i] == 3 ? HFZ_ENOCONV : 0;
+      most = std::max(most, h_cyc[i]);
+    }
+    B->cycle_hint = most;
     for (int i = 0; i < count; ++i) {
       if (!filled[i] || failed[i]) continue;  // failed: rolled back to the previous step's state
       rc = finish_step(B->inst[i]);
       if (rc != HFZ_OK) break;
       st[i].steps_done++;
-      st[i].cycles_total += cycles[i];
+      st[i].cycles_total += h_cyc[i];
     }
     if (rc != HFZ_OK) break;
     for (int i = 0; i < count; ++i)
