@@ -149,4 +149,98 @@ __global__ void k_zero_ints(int* a, int count) {
   if (t < count) a[t] = 0;
 }
 
+// Per-instance state arrays of the batched begin / finish kernels.
+struct StateB {
+  double* u;
+  double* v;
+  double* mu;
+  double* ka;
+  double* jrho;
+};
+
+// Start of a step for every instance z with on[z]: omega^k and the source S
+// (the single-instance k_source arithmetic), the iterate g = state, and in
+// mixed precision the FP32 copies of rho^k and omega^k (E0s non-null).
+template <int MODEL>
+__global__ void k_begin_b(const Lvl<double>* L0s, const StateB* Ss, const Phys<double>* Ps, const int* on,
+                          const Lvl<float>* E0s) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> L = lvl_global(L0s[z]);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const StateB S = Ss[z];
+  double* u = as_global(S.u);
+  double* v = as_global(S.v);
+  source_node<MODEL>(L.rk, u, v, MODEL == CDFT ? as_global(S.jrho) : nullptr, L.om, L.f[0], L.f[1], L.f[2],
+                     MODEL == PFC ? L.f[3] : nullptr, MODEL == PFC ? L.f[4] : nullptr, i, j, L.n, L.lg, L.h, Ps[z]);
+  const int p = (j << L.lg) + i;
+  L.g[0][p] = L.rk[p];
+  L.g[1][p] = u[p];
+  L.g[2][p] = v[p];
+  if constexpr (MODEL == PFC) {
+    L.g[3][p] = as_global(S.mu)[p];
+    L.g[4][p] = as_global(S.ka)[p];
+  }
+  if (E0s) {
+    const Lvl<float> E = lvl_global(E0s[z]);
+    E.rk[p] = (float)L.rk[p];
+    E.om[p] = (float)L.om[p];
+  }
+}
+
+// rho^k, omega^k of every instance onto its next coarser level (and their FP32
+// copies in mixed precision, Es non-null).
+__global__ void k_restrict_coef_b(const Lvl<double>* Fs, const Lvl<double>* Cs, const int* on,
+                                  const Lvl<float>* Es) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> F = lvl_global(Fs[z]);
+  const Lvl<double> C = lvl_global(Cs[z]);
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  if (I >= C.n || J >= C.n) return;
+  const int pc = (J << C.lg) + I;
+  const double r = fw9(F.rk, 2 * I, 2 * J, F.n, F.lg);
+  const double o = fw9(F.om, 2 * I, 2 * J, F.n, F.lg);
+  C.rk[pc] = r;
+  C.om[pc] = o;
+  if (Es) {
+    const Lvl<float> E = lvl_global(Es[z]);
+    E.rk[pc] = (float)r;
+    E.om[pc] = (float)o;
+  }
+}
+
+// End of a step, first half: rho^{k+1} from the continuity row into g[0]
+// (the single-instance k_continuity arithmetic).
+__global__ void k_continuity_b(const Lvl<double>* L0s, const Phys<double>* Ps, const int* on) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> L = lvl_global(L0s[z]);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const Nbr q = nbr(i, j, L.n, L.lg);
+  L.g[0][q.p] = continuity_node(L.f[0], L.rk, L.g[1], L.g[2], q, L.h, Ps[z].s);
+}
+
+// End of a step, second half: state <- g.
+template <int MODEL> __global__ void k_state_b(const Lvl<double>* L0s, const StateB* Ss, const int* on) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> L = lvl_global(L0s[z]);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.n * L.n) return;
+  const StateB S = Ss[z];
+  L.rk[t] = L.g[0][t];
+  as_global(S.u)[t] = L.g[1][t];
+  as_global(S.v)[t] = L.g[2][t];
+  if constexpr (MODEL == PFC) {
+    as_global(S.mu)[t] = L.g[3][t];
+    as_global(S.ka)[t] = L.g[4][t];
+  }
+}
+
 }  // namespace hfz

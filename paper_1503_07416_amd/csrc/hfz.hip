@@ -1014,6 +1014,9 @@ struct hfz_batch {
   Phys<float>* P32 = nullptr;
   int* active = nullptr;
   double* norm2 = nullptr;
+  StateB* S = nullptr;   // [count] state arrays of each instance
+  int* on = nullptr;      // [count] instances the batched begin / finish kernels treat
+  std::vector<int> h_on;
   int* cyc = nullptr;     // [count] V-cycles (mixed: outer iterations) of the current step
   int* stat = nullptr;    // [count] 0 running, 1 converged, 2 not finite, 3 max_cycles reached
   double* tol = nullptr;  // [count]
@@ -1056,6 +1059,8 @@ BatchLayout batch_layout(const hfz_params* ps, int count) {
   c.take<double>(count);
   c.take<int>((size_t)count * 3);
   c.take<double>(count);
+  c.take<StateB>(count);
+  c.take<int>(count);
   c.take<double>((N2 / 256 + 64) * count);
   bl.total = bl.off_arrays + c.off;
   return bl;
@@ -1191,6 +1196,44 @@ int batch_launch_cycle(hfz_batch* B) {
   return last_error();
 }
 
+// The batched begin of a step for the instances with h_on set: source,
+// iterate, frozen coefficients on every level (and their FP32 copies).
+template <int MODEL> int batch_begin(hfz_batch* B) {
+  HIPCHK(hipMemcpyAsync(B->on, B->h_on.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  const bool mixed = B->p.precision == HFZ_MIXED;
+  const int count = B->count;
+  hfz_handle* h0 = B->inst[0];
+  for (int l = 0; l < B->nlev; ++l) {
+    const int n = h0->H.L[l].n;
+    const dim3 b = block2(n, n);
+    const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, count);
+    const Lvl<float>* E = mixed ? B->D32 + (size_t)l * count : nullptr;
+    if (l == 0)
+      k_begin_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->S, B->P64, B->on, E);
+    else
+      k_restrict_coef_b<<<g, b, 0, B->stream>>>(B->D64 + (size_t)(l - 1) * count, B->D64 + (size_t)l * count, B->on,
+                                                 E);
+  }
+  return last_error();
+}
+
+// The batched end of a step for the instances with h_on set: continuity
+// update, state <- g, and for CDFT the next convolution (per instance).
+template <int MODEL> int batch_finish(hfz_batch* B) {
+  HIPCHK(hipMemcpyAsync(B->on, B->h_on.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  const int n = B->p.n, count = B->count;
+  const dim3 b = block2(n, n);
+  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, count);
+  if (B->p.continuity_fix) k_continuity_b<<<g, b, 0, B->stream>>>(B->D64, B->P64, B->on);
+  k_state_b<MODEL><<<dim3((unsigned)(((size_t)n * n + 255) / 256), 1, count), 256, 0, B->stream>>>(B->D64, B->S,
+                                                                                                   B->on);
+  if constexpr (MODEL == CDFT) {
+    for (int i = 0; i < count; ++i)
+      if (B->h_on[i]) convolve(B->inst[i], B->inst[i]->H.L[0].rk, B->inst[i]->jrho);
+  }
+  return last_error();
+}
+
 int batch_write_active(hfz_batch* B) {
   HIPCHK(hipMemcpyAsync(B->active, B->h_active.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
   return HFZ_OK;
@@ -1256,6 +1299,9 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   B->stat = ints + count;
   B->maxc = ints + 2 * count;
   B->tol = c.take<double>(count);
+  B->S = c.take<StateB>(count);
+  B->on = c.take<int>(count);
+  B->h_on.assign(count, 0);
   B->pstride = (int)((size_t)params[0].n * params[0].n / 256 + 64);
   B->partial = c.take<double>((size_t)B->pstride * count);
   const bool mixed = params[0].precision == HFZ_MIXED;
@@ -1298,6 +1344,13 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   ok = ok && hipMemcpyAsync(B->P64, p64.data(), count * sizeof(Phys<double>), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
   ok = ok && hipMemcpyAsync(B->P32, p32.data(), count * sizeof(Phys<float>), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  std::vector<StateB> sts(count);
+  for (int i = 0; i < count; ++i) {
+    hfz_handle* h = B->inst[i];
+    sts[i] = StateB{h->u, h->v, h->mu, h->ka, h->jrho};
+  }
+  ok = ok && hipMemcpyAsync(B->S, sts.data(), count * sizeof(StateB), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
   std::vector<double> tols(count);
   std::vector<int> maxcs(count);
@@ -1349,16 +1402,12 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
   if (stats)
     for (int i = 0; i < count; ++i) stats[i] = hfz_stats{};
   if (nfilled == 0) return HFZ_OK;
-  const bool mixed = B->p.precision == HFZ_MIXED;
   std::vector<hfz_stats> st(count);
   std::vector<int> h_cyc(count), h_stat(count);
   int rc = HFZ_OK;
   for (int k = 0; k < nsteps && rc == HFZ_OK; ++k) {
-    for (int i = 0; i < count && rc == HFZ_OK; ++i) {
-      if (!filled[i]) continue;
-      rc = begin_step(B->inst[i]);
-      if (rc == HFZ_OK && mixed) mp_begin(B->inst[i]);
-    }
+    for (int i = 0; i < count; ++i) B->h_on[i] = filled[i];
+    rc = B->p.model == HFZ_PFC ? batch_begin<PFC>(B) : batch_begin<CDFT>(B);
     if (rc != HFZ_OK) break;
     // every instance runs until its own stop test ends it (on the device);
     // the host enqueues cycles in batches and reads the states once a batch
@@ -1399,14 +1448,15 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
       most = std::max(most, h_cyc[i]);
     }
     B->cycle_hint = most;
+    // failed instances are rolled back: their state stays that of the previous step
+    for (int i = 0; i < count; ++i) B->h_on[i] = filled[i] && !failed[i];
+    rc = B->p.model == HFZ_PFC ? batch_finish<PFC>(B) : batch_finish<CDFT>(B);
+    if (rc != HFZ_OK) break;
     for (int i = 0; i < count; ++i) {
-      if (!filled[i] || failed[i]) continue;  // failed: rolled back to the previous step's state
-      rc = finish_step(B->inst[i]);
-      if (rc != HFZ_OK) break;
+      if (!B->h_on[i]) continue;
       st[i].steps_done++;
       st[i].cycles_total += h_cyc[i];
     }
-    if (rc != HFZ_OK) break;
     for (int i = 0; i < count; ++i)
       if (failed[i] && rc == HFZ_OK) rc = failed[i];
   }

@@ -14,13 +14,11 @@ constexpr int RED_BLOCK = 256;  // threads per block of the reduction kernels
 // 0 for PFC (its explicit part sits in S4 = 2 Delta_h rho^k), J*rho^k +
 // 2 c_e rho^k for CDFT.
 template <int MODEL>
-__global__ void k_source(const double* __restrict__ rho, const double* __restrict__ u,
-                         const double* __restrict__ v, const double* __restrict__ jrho,
-                         double* __restrict__ om, double* S0, double* S1, double* S2, double* S3,
-                         double* S4, int n, int lg, double h, Phys<double> P) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= n || j >= n) return;
+__device__ __forceinline__ void source_node(const double* __restrict__ rho, const double* __restrict__ u,
+                                            const double* __restrict__ v, const double* __restrict__ jrho,
+                                            double* __restrict__ om, double* S0, double* S1, double* S2,
+                                            double* S3, double* S4, int i, int j, int n, int lg, double h,
+                                            const Phys<double>& P) {
   const Nbr q = nbr(i, j, n, lg);
   const double s = P.s, c4 = s / (4.0 * h), c2 = s / (2.0 * h), ih2 = 1.0 / (h * h);
   const double r = rho[q.p], uP = u[q.p], vP = v[q.p];
@@ -46,6 +44,17 @@ __global__ void k_source(const double* __restrict__ rho, const double* __restric
     S3[q.p] = 2.0 * (rho[q.e] + rho[q.w] + rho[q.n] + rho[q.s] - 4.0 * r) * ih2;
     S4[q.p] = 0.0;
   }
+}
+
+template <int MODEL>
+__global__ void k_source(const double* __restrict__ rho, const double* __restrict__ u,
+                         const double* __restrict__ v, const double* __restrict__ jrho,
+                         double* __restrict__ om, double* S0, double* S1, double* S2, double* S3,
+                         double* S4, int n, int lg, double h, Phys<double> P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= n || j >= n) return;
+  source_node<MODEL>(rho, u, v, jrho, om, S0, S1, S2, S3, S4, i, j, n, lg, h, P);
 }
 
 // ----------------------------------------------------- full weighting -----
@@ -300,6 +309,13 @@ __global__ void k_ctl_reset(int* ctl) {
 // --------------------------------------------------------- post-step -----
 // K10: rho^{k+1} = S1 - s/(4h)[(rho^k u)_E - (rho^k u)_W + (rho^k v)_N - (rho^k v)_S]
 // with the converged velocity (Eq. discrete_a), written into dst.
+__device__ __forceinline__ double continuity_node(const double* __restrict__ S0, const double* __restrict__ rk,
+                                                  const double* __restrict__ u, const double* __restrict__ v,
+                                                  const Nbr& q, double h, double s) {
+  const double c4 = s / (4.0 * h);
+  return S0[q.p] - c4 * (rk[q.e] * u[q.e] - rk[q.w] * u[q.w] + rk[q.n] * v[q.n] - rk[q.s] * v[q.s]);
+}
+
 __global__ void k_continuity(const double* __restrict__ S0, const double* __restrict__ rk,
                              const double* __restrict__ u, const double* __restrict__ v,
                              double* __restrict__ dst, int n, int lg, double h, double s) {
@@ -307,8 +323,7 @@ __global__ void k_continuity(const double* __restrict__ S0, const double* __rest
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= n || j >= n) return;
   const Nbr q = nbr(i, j, n, lg);
-  const double c4 = s / (4.0 * h);
-  dst[q.p] = S0[q.p] - c4 * (rk[q.e] * u[q.e] - rk[q.w] * u[q.w] + rk[q.n] * v[q.n] - rk[q.s] * v[q.s]);
+  dst[q.p] = continuity_node(S0, rk, u, v, q, h, s);
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t count) {
