@@ -118,6 +118,8 @@ void restrict_launch(Hier<T>& H, Cycle& K, const Lvl<T>& F, const Lvl<T>& C, int
     k_restrict_fas_staged<MODEL, T, CORR, 8, 256><<<grid, 256, 0, K.stream>>>(F, C, H.P);
   else if (rs == 2)
     k_restrict_fas_staged<MODEL, T, CORR, 16, 256><<<grid, 256, 0, K.stream>>>(F, C, H.P);
+  else if (rs == 3)
+    k_restrict_fas_staged<MODEL, T, CORR, 16, 512><<<grid, 512, 0, K.stream>>>(F, C, H.P);
   else
     k_restrict_fas_tile<MODEL, T, CORR><<<grid, RTILE * RTILE, 0, K.stream>>>(F, C, H.P);
 }

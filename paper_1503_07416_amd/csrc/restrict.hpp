@@ -197,8 +197,9 @@ __global__ __launch_bounds__(NT) void k_restrict_fas_staged(Lvl<T> F, Lvl<T> C, 
 }
 
 // Restriction variants the tuner chooses from: 0 the direct kernel (coarse
-// tile 16), 1 the staged kernel with coarse tile 8, 2 with coarse tile 16.
-constexpr int NUM_RESTRICT_SHAPES = 3;
-constexpr int kRestrictTile[NUM_RESTRICT_SHAPES] = {16, 8, 16};
+// tile 16), 1 the staged kernel with coarse tile 8, 2 with coarse tile 16,
+// 3 with coarse tile 16 and 512 threads.
+constexpr int NUM_RESTRICT_SHAPES = 4;
+constexpr int kRestrictTile[NUM_RESTRICT_SHAPES] = {16, 8, 16, 16};
 
 }  // namespace hfz

@@ -18,6 +18,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -121,7 +122,7 @@ float time_schedule(Hier<T>& H, Cycle& K, int l, int fuse, int reps) {
 // Index of the fastest of `count` candidates timed by `time(k)` (best of
 // three rounds; a later candidate must win by 2%, so near-ties resolve the
 // same way every run); 0 if none could be timed.
-template <typename F> int pick_fastest(int count, F&& time) {
+template <typename F> int pick_fastest(int count, F&& time, const char* what = nullptr, int n = 0) {
   float ms[8];
   for (int k = 0; k < count; ++k) ms[k] = -1.0f;
   for (int round = 0; round < 3; ++round)
@@ -132,6 +133,11 @@ template <typename F> int pick_fastest(int count, F&& time) {
   int best = 0;
   for (int k = 1; k < count; ++k)
     if (ms[k] > 0.0f && (ms[best] < 0.0f || ms[k] < 0.98f * ms[best])) best = k;
+  if (what && std::getenv("HFZ_VERBOSE")) {
+    std::fprintf(stderr, "hfz tune %s n=%d:", what, n);
+    for (int k = 0; k < count; ++k) std::fprintf(stderr, " %.2f", ms[k] * 1e3f);
+    std::fprintf(stderr, " us -> %d\n", best);
+  }
   return best;
 }
 
@@ -171,15 +177,16 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     }
     const int ts = pick_fastest(NUM_TILE_SHAPES, [&](int k) {
       return tile_shape_fits(k, n) ? time_shape<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
-    });
+    }, "tile shape", n);
     if (forced < 0) H.tile_shape[l] = ts;
     const int rs = pick_fastest(NUM_RESTRICT_SHAPES, [&](int k) {
       return nc % kRestrictTile[k] == 0 ? time_restrict<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
-    });
+    }, "restriction", n);
     if (forced_r < 0) H.restrict_shape[l] = rs;
     // sweep schedule in the chosen shape: candidate 0 fuses two sweeps per
     // launch, candidate 1 launches one sweep at a time
-    const int fs = pick_fastest(2, [&](int k) { return time_schedule<MODEL, T, CORR>(H, K, l, k == 0 ? 2 : 1, 8); });
+    const int fs = pick_fastest(
+        2, [&](int k) { return time_schedule<MODEL, T, CORR>(H, K, l, k == 0 ? 2 : 1, 8); }, "sweeps", n);
     if (forced_f < 0) H.sweep_fuse[l] = fs == 0 ? 2 : 1;
     std::lock_guard<std::mutex> g(tune_mutex());
     tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1);

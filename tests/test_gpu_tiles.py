@@ -102,7 +102,7 @@ def test_tuned_shapes_match_oracle(monkeypatch):
 def test_vcycles_same_for_every_restriction(monkeypatch, model):
     monkeypatch.setenv("HFZ_TILE", "0")
     ref, _ = run_vcycles(monkeypatch, 0, model, 256, env="HFZ_RESTRICT")
-    for rs in (1, 2):
+    for rs in (1, 2, 3):
         got, _ = run_vcycles(monkeypatch, rs, model, 256, env="HFZ_RESTRICT")
         for c, (x, y) in enumerate(zip(got, ref)):
             assert rel_err(x, y) <= 1e-13, (rs, c, rel_err(x, y))
@@ -113,7 +113,7 @@ def test_mixed_steps_same_for_every_restriction(monkeypatch, model):
     import paper_1503_07416_amd as pkg
     monkeypatch.setenv("HFZ_TILE", "0")
     res = {}
-    for rs in (0, 1, 2):
+    for rs in (0, 1, 2, 3):
         monkeypatch.setenv("HFZ_RESTRICT", str(rs))
         cfg, rho, u, v = case(model, 128, "mixed")
         sim = pkg.Simulation(cfg)
@@ -121,7 +121,7 @@ def test_mixed_steps_same_for_every_restriction(monkeypatch, model):
         st = sim.step(2)
         res[rs] = ([x.cpu().numpy() for x in sim.get_state()], st.cycles_total)
         sim.close()
-    for rs in (1, 2):
+    for rs in (1, 2, 3):
         assert res[rs][1] == res[0][1]
         for x, y in zip(res[rs][0], res[0][0]):
             assert rel_err(x, y) <= 1e-13
