@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
     ap.add_argument("--probe-tile-shape", type=int, default=2,
                     help="tile shape of the counter probe (the one the tuner picks at 512^2)")
     ap.add_argument("--counter-probe", action="store_true",
@@ -368,6 +369,9 @@ def main():
         return
     if a.cdft_only:
         print(json.dumps({"cdft": run_cdft()}))
+        return
+    if a.batched_only:
+        print(json.dumps({"batched": run_batched()}))
         return
     if a.mixed_only:
         import torch
