@@ -100,6 +100,9 @@ struct hfz_handle {
   double* partial = nullptr;
   double* result = nullptr;
   int* ctl = nullptr;  // device stop flag and cycle counter of the V-cycle loop (inside result)
+  StateB* state1 = nullptr;      // device copies of the state pointers, the physics and an "on" flag, so
+  Phys<double>* phys1 = nullptr;  // that the batched begin / end kernels serve this handle (count 1)
+  int* on1 = nullptr;
   int cycle_hint = 4;  // V-cycles (mixed: outer iterations) the previous step needed
   size_t partial_cap = 0;
   int tail_n = 32;  // levels of this size and below run in the one-workgroup tail kernel
@@ -158,6 +161,9 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
   double* partial = c.take<double>(pcap * 4);
   double* result = c.take<double>(64);
   Lvl<double>* desc = c.take<Lvl<double>>(L.size());
+  StateB* state1 = c.take<StateB>(1);
+  Phys<double>* phys1 = c.take<Phys<double>>(1);
+  int* on1 = c.take<int>(64);
   if (hd) {
     hd->nc = nc;
     hd->nlev = (int)L.size();
@@ -183,6 +189,9 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     hd->ctl = reinterpret_cast<int*>(result + 8);
     hd->partial_cap = pcap;
     hd->H.desc = desc;
+    hd->state1 = state1;
+    hd->phys1 = phys1;
+    hd->on1 = on1;
   }
   if (p.precision == HFZ_MIXED) {
     // FP32 correction hierarchy: e (the iterate), f, R e, d, the second sweep
@@ -269,26 +278,27 @@ Cycle cycle_ctx(hfz_handle* hd) {
 // Enqueues h^2 sum (f - N(g))^2 on level 0 into result[0].
 // The final reduction of `count` stop-test partials into result[0]; with
 // `stop`, the device stop test of the V-cycle loop as well (k_reduce_stop).
-void reduce_launch(hfz_handle* hd, int count, bool stop) {
+void reduce_launch(hfz_handle* hd, int count, bool stop, bool counted = true) {
   const double h2 = hd->H.L[0].h * hd->H.L[0].h;
   if (stop)
-    k_reduce_stop<<<1, 1024, 0, hd->stream>>>(hd->partial, count, h2, hd->p.tol, hd->result, hd->ctl);
+    k_reduce_stop<<<1, 1024, 0, hd->stream>>>(hd->partial, count, h2, hd->p.tol, hd->result, hd->ctl,
+                                              counted ? 1 : 0);
   else
     k_reduce_final<<<1, 1024, 0, hd->stream>>>(hd->partial, count, 1, h2, hd->result);
 }
 
-template <int MODEL> void residual_launch_t(hfz_handle* hd, bool stop) {
+template <int MODEL> void residual_launch_t(hfz_handle* hd, bool stop, bool counted) {
   const Lvl<double>& L = hd->H.L[0];
   const Dims d = dims2(L.n, L.n);
   k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->H.P, hd->partial);
-  reduce_launch(hd, (int)(d.grid.x * d.grid.y), stop);
+  reduce_launch(hd, (int)(d.grid.x * d.grid.y), stop, counted);
 }
 
-void residual_launch(hfz_handle* hd, bool stop = false) {
+void residual_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
   if (hd->p.model == HFZ_PFC)
-    residual_launch_t<PFC>(hd, stop);
+    residual_launch_t<PFC>(hd, stop, counted);
   else
-    residual_launch_t<CDFT>(hd, stop);
+    residual_launch_t<CDFT>(hd, stop, counted);
 }
 
 int residual_read(hfz_handle* hd, double* norm) {
@@ -361,26 +371,16 @@ int cycle_and_residual(hfz_handle* hd, double* norm) {
 
 // ---- mixed precision: FP32 correction V-cycles inside FP64 defect correction
 
-// FP32 copies of the frozen coefficients of every level (once per step).
-void mp_begin(hfz_handle* hd) {
-  for (int l = 0; l < hd->nlev; ++l) {
-    const size_t cnt = (size_t)hd->H.L[l].n * hd->H.L[l].n;
-    const unsigned nb = (unsigned)((cnt + 255) / 256);
-    k_cast<<<nb, 256, 0, hd->stream>>>(hd->H.L[l].rk, hd->H32.L[l].rk, cnt);
-    k_cast<<<nb, 256, 0, hd->stream>>>(hd->H.L[l].om, hd->H32.L[l].om, cnt);
-  }
-}
-
 // d = S - N(g) in FP64 -> inner right-hand side, base state, e = 0, and the
 // outer stop-test norm into result[0].
-void mp_prepare_launch(hfz_handle* hd, bool stop = false) {
+void mp_prepare_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
   if (hd->p.model == HFZ_PFC)
     k_mp_prepare<PFC><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
   else
     k_mp_prepare<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
-  reduce_launch(hd, (int)(g.x * g.y), stop);
+  reduce_launch(hd, (int)(g.x * g.y), stop, counted);
 }
 
 // One outer iteration: mp_inner FP32 V-cycles on the correction problem
@@ -430,20 +430,27 @@ int mp_cycle_and_residual(hfz_handle* hd, double* norm) {
   return residual_read(hd, norm);
 }
 
-// The V-cycles of one step after the initial residual r (> tol, finite):
-// on the device-tested path the cycle graph is enqueued in batches (the first
-// as long as the previous step needed), each cycle ending in k_reduce_stop,
-// which raises the stop flag once ||S - N(g)|| <= tol or is not finite; the
-// kernels of cycles enqueued past that point return at once, so the cycles
-// that run, their count and the final norm are those of the host-tested loop,
-// at one host round trip per batch.  Without graphs every cycle is tested on
-// the host.
-int run_cycles(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
+// The solve of one step: the initial residual and the V-cycles (mixed: outer
+// iterations).  On the device-tested path the initial norm and the cycle
+// graph run with k_reduce_stop, which raises the stop flag once
+// ||S - N(g)|| <= tol or is not finite; the cycles are enqueued in batches
+// (the first as long as the previous step needed, then pairs) and the kernels
+// of cycles enqueued past the stop return at once, so the cycles that run,
+// their count and the final norm are those of the host-tested loop, at one
+// host round trip per batch.  Without graphs every cycle is tested on the host.
+int solve_step(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
   int cycles = 0;
+  *cycles_out = 0;
   const bool graph = hd->use_graph && (mixed ? mp_graph(hd) : cycle_graph(hd));
   if (!graph) {
-    int rc = HFZ_OK;
-    while (!(*r <= hd->p.tol)) {
+    int rc;
+    if (mixed) {
+      mp_prepare_launch(hd);
+      rc = residual_read(hd, r);
+    } else {
+      rc = residual(hd, r);
+    }
+    while (rc == HFZ_OK && !(*r <= hd->p.tol)) {
       if (!std::isfinite(*r)) {
         rc = HFZ_ENAN;
         break;
@@ -454,21 +461,20 @@ int run_cycles(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
       }
       ++cycles;
       rc = mixed ? mp_cycle_and_residual(hd, r) : cycle_and_residual(hd, r);
-      if (rc != HFZ_OK) break;
     }
     *cycles_out = cycles;
     return rc;
   }
   hipGraphExec_t exec = mixed ? hd->mp_exec : hd->cycle_exec;
   k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
+  if (mixed)
+    mp_prepare_launch(hd, true, false);
+  else
+    residual_launch(hd, true, false);
   int rc = HFZ_OK;
   int batch = std::max(1, hd->cycle_hint);
   for (;;) {
     const int remaining = hd->p.max_cycles - cycles;
-    if (remaining <= 0) {
-      rc = HFZ_ENOCONV;
-      break;
-    }
     const int nb = std::min(batch, remaining);
     for (int i = 0; i < nb && rc == HFZ_OK; ++i)
       if (hipGraphLaunch(exec, hd->stream) != hipSuccess) rc = HFZ_EHIP;
@@ -488,10 +494,14 @@ int run_cycles(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
       rc = HFZ_ENAN;
       break;
     }
+    if (cycles >= hd->p.max_cycles) {
+      rc = HFZ_ENOCONV;
+      break;
+    }
     batch = 2;
   }
   k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
-  if (rc == HFZ_OK) hd->cycle_hint = cycles;
+  if (rc == HFZ_OK) hd->cycle_hint = std::max(1, cycles);
   *cycles_out = cycles;
   return rc == HFZ_OK ? last_error() : rc;
 }
@@ -546,49 +556,38 @@ void copy_dev(hfz_handle* hd, const double* a, double* b, size_t count) {
   k_copy<<<(unsigned)((count + 255) / 256), 256, 0, hd->stream>>>(a, b, count);
 }
 
-int begin_step(hfz_handle* hd) {
-  const int n = hd->p.n;
-  const size_t N2 = (size_t)n * n;
-  Lvl<double>& L0 = hd->H.L[0];
-  const Dims d = dims2(n, n);
-  if (hd->p.model == HFZ_PFC)
-    k_source<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, L0.om, L0.f[0], L0.f[1],
-                                                     L0.f[2], L0.f[3], L0.f[4], n, L0.lg, L0.h, hd->H.P);
-  else
-    k_source<CDFT><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, hd->jrho, L0.om, L0.f[0],
-                                                      L0.f[1], L0.f[2], nullptr, nullptr, n, L0.lg, L0.h, hd->H.P);
-  copy_dev(hd, L0.rk, L0.g[0], N2);
-  copy_dev(hd, hd->u, L0.g[1], N2);
-  copy_dev(hd, hd->v, L0.g[2], N2);
-  if (hd->p.model == HFZ_PFC) {
-    copy_dev(hd, hd->mu, L0.g[3], N2);
-    copy_dev(hd, hd->ka, L0.g[4], N2);
-  }
-  for (int l = 1; l < hd->nlev; ++l) {
-    const Dims dc = dims2(hd->H.L[l].n, hd->H.L[l].n);
-    k_restrict_coef<double><<<dc.grid, dc.block, 0, hd->stream>>>(hd->H.L[l - 1].rk, hd->H.L[l - 1].om,
-                                                                hd->H.L[l].rk, hd->H.L[l].om, hd->H.L[l].n,
-                                                                hd->H.L[l].lg);
+// Start of a step: omega^k and the source S, the iterate g = state, rho^k and
+// omega^k on every level (and their FP32 copies in mixed precision), with
+// the batched kernels over this one instance.
+template <int MODEL> int begin_step_t(hfz_handle* hd) {
+  const bool mixed = hd->p.precision == HFZ_MIXED;
+  for (int l = 0; l < hd->nlev; ++l) {
+    const int n = hd->H.L[l].n;
+    const dim3 b = block2(n, n), g = grid2(n, n, b);
+    const Lvl<float>* E = mixed ? hd->H32.desc + l : nullptr;
+    if (l == 0)
+      k_begin_b<MODEL><<<g, b, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->phys1, hd->on1, E);
+    else
+      k_restrict_coef_b<<<g, b, 0, hd->stream>>>(hd->H.desc + (l - 1), hd->H.desc + l, hd->on1, E);
   }
   return last_error();
 }
 
+int begin_step(hfz_handle* hd) {
+  return hd->p.model == HFZ_PFC ? begin_step_t<PFC>(hd) : begin_step_t<CDFT>(hd);
+}
+
+// End of a step: continuity update, state <- g, the next CDFT convolution.
 int finish_step(hfz_handle* hd) {
   const int n = hd->p.n;
-  const size_t N2 = (size_t)n * n;
-  Lvl<double>& L0 = hd->H.L[0];
-  const Dims d = dims2(n, n);
-  if (hd->p.continuity_fix)
-    k_continuity<<<d.grid, d.block, 0, hd->stream>>>(L0.f[0], L0.rk, L0.g[1], L0.g[2], L0.g[0], n, L0.lg,
-                                                     L0.h, hd->p.s);
-  copy_dev(hd, L0.g[0], L0.rk, N2);
-  copy_dev(hd, L0.g[1], hd->u, N2);
-  copy_dev(hd, L0.g[2], hd->v, N2);
+  const dim3 b = block2(n, n), g = grid2(n, n, b);
+  if (hd->p.continuity_fix) k_continuity_b<<<g, b, 0, hd->stream>>>(hd->H.desc, hd->phys1, hd->on1);
+  const dim3 gs((unsigned)(((size_t)n * n + 255) / 256));
   if (hd->p.model == HFZ_PFC) {
-    copy_dev(hd, L0.g[3], hd->mu, N2);
-    copy_dev(hd, L0.g[4], hd->ka, N2);
+    k_state_b<PFC><<<gs, 256, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->on1);
   } else {
-    convolve(hd, L0.rk, hd->jrho);
+    k_state_b<CDFT><<<gs, 256, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->on1);
+    convolve(hd, hd->H.L[0].rk, hd->jrho);
   }
   return last_error();
 }
@@ -753,6 +752,19 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
       return rc;
     }
   }
+  {
+    const StateB sb{hd->u, hd->v, hd->mu, hd->ka, hd->jrho};
+    const int one = 1;
+    const bool up = hipMemcpyAsync(hd->state1, &sb, sizeof(sb), hipMemcpyHostToDevice, hd->stream) == hipSuccess &&
+                    hipMemcpyAsync(hd->phys1, &hd->H.P, sizeof(Phys<double>), hipMemcpyHostToDevice, hd->stream) ==
+                        hipSuccess &&
+                    hipMemcpyAsync(hd->on1, &one, sizeof(int), hipMemcpyHostToDevice, hd->stream) == hipSuccess &&
+                    hipStreamSynchronize(hd->stream) == hipSuccess;
+    if (!up) {
+      delete hd;
+      return HFZ_EHIP;
+    }
+  }
   *out = hd;
   return HFZ_OK;
 }
@@ -860,21 +872,8 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats) {
     if (rc != HFZ_OK) break;
     const bool mixed = hd->p.precision == HFZ_MIXED;
     double r = 0.0;
-    if (mixed) {
-      mp_begin(hd);
-      mp_prepare_launch(hd);
-      rc = residual_read(hd, &r);
-    } else {
-      rc = residual(hd, &r);
-    }
-    if (rc != HFZ_OK) break;
     int cycles = 0;
-    if (!(r <= hd->p.tol)) {
-      if (!std::isfinite(r))
-        rc = HFZ_ENAN;
-      else
-        rc = run_cycles(hd, mixed, &r, &cycles);
-    }
+    rc = solve_step(hd, mixed, &r, &cycles);
     st.cycles_last = cycles;
     st.residual_last = r;
     if (rc != HFZ_OK) break;

@@ -280,10 +280,11 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int count, in
 
 // The stop test of a V-cycle on the device: unless the flag ctl[0] is already
 // set, result[0] = scale * (sum of the partials, in k_reduce_final's order),
-// ctl[1] += 1 (cycles run), and ctl[0] = 1 if sqrt(result[0]) <= tol, 2 if it
-// is not finite.  One workgroup of 1024 threads.
+// with `counted` ctl[1] += 1 (cycles run; not for the norm before the first
+// cycle), and ctl[0] = 1 if sqrt(result[0]) <= tol, 2 if it is not finite.
+// One workgroup of 1024 threads.
 __global__ void k_reduce_stop(const double* __restrict__ partial, int count, double scale, double tol,
-                              double* __restrict__ result, int* ctl) {
+                              double* __restrict__ result, int* ctl, int counted) {
   __shared__ double lds[16];
   if (ctl[0] != 0) return;
   double acc = 0.0;
@@ -292,7 +293,7 @@ __global__ void k_reduce_stop(const double* __restrict__ partial, int count, dou
   if (threadIdx.x == 0) {
     const double r2 = scale * r;
     result[0] = r2;
-    ctl[1] += 1;
+    if (counted) ctl[1] += 1;
     const double nrm = sqrt(r2);
     if (nrm <= tol)
       ctl[0] = 1;
