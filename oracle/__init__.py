@@ -27,6 +27,9 @@ paper it follows (section, equation label, appendix).  Modules:
               definition of the implicit step's solution
 ``linear``    closed forms of the linearised scheme (growth of small Fourier
               modes about a uniform state, viscous shear decay)
+``gradflow``  the gradient-flow variant of the convex-splitting scheme
+              (Thm. thm_grad, Eq. gradient_scheme): its rows, block smoother,
+              FAS solver and stepper
 
 Pins (see tests/test_oracle_*.py): Fourier symbols and summation by parts of
 the operators; two transcriptions of the scheme agree; FAS equals dense Newton;
@@ -34,5 +37,8 @@ discrete mass conservation and the discrete energy identity of App. F;
 convex-splitting gap >= 0; energy non-increase for s in 1e-3..1e3; closed-form
 linear growth and shear decay; uniform fixed points; symmetry equivariance;
 FFT convolution equals the direct sum; the Cauchy errors the paper prints in
-its convergence tables (tests/golden/).
+its convergence tables (tests/golden/); for the gradient-flow variant the
+scheme written directly with dF_c, dF_e, dense Newton, the closed-form
+amplification of a Fourier mode, mass, the dissipation identity and energy
+decay for any s (tests/test_oracle_gradflow.py).
 """

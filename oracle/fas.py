@@ -61,7 +61,14 @@ def resnorm(g, f, lev):
 
 
 class Solver:
-    """FAS V(nu1, nu2) over a hierarchy of frozen-coefficient levels."""
+    """FAS V(nu1, nu2) over a hierarchy of frozen-coefficient levels.
+
+    The level operator and the smoother are the class attributes ``N`` and
+    ``sweep`` (the hydrodynamic system and its App. G smoother here; the
+    gradient-flow variant substitutes its own)."""
+
+    N = staticmethod(N)
+    sweep = staticmethod(sweep)
 
     def __init__(self, levels, w=0.5, nu1=2, nu2=2, coarse_sweeps=64):
         self.levels = levels
@@ -81,28 +88,32 @@ class Solver:
         if lev.model == "cdft":
             g[0] = np.sqrt(g[0] * g[0] + lev.delta * lev.delta)
 
+    def resnorm(self, g, f, lev):
+        d = f - self.N(g, lev)
+        return np.sqrt(lev.h * lev.h * float(np.sum(d * d)))
+
     def vcycle(self, g, f, l=0):
         lev = self.levels[l]
         if l == len(self.levels) - 1:
             for _ in range(self.coarse_sweeps):
-                sweep(g, f, lev, self.w)
+                self.sweep(g, f, lev, self.w)
             return g
         for _ in range(self.nu1):
-            sweep(g, f, lev, self.w)
-        d = f - N(g, lev)
+            self.sweep(g, f, lev, self.w)
+        d = f - self.N(g, lev)
         coarse = self.levels[l + 1]
         g0 = restrict(g)
-        fc = N(g0, coarse) + restrict(d)
+        fc = self.N(g0, coarse) + restrict(d)
         gc = self.vcycle(g0.copy(), fc, l + 1)
         g += prolong(gc - g0)
         self._project(g, lev)
         for _ in range(self.nu2):
-            sweep(g, f, lev, self.w)
+            self.sweep(g, f, lev, self.w)
         return g
 
     def solve(self, g, f, tol, max_cycles, history=None):
         lev = self.levels[0]
-        r = resnorm(g, f, lev)
+        r = self.resnorm(g, f, lev)
         if history is not None:
             history.append(r)
         cycles = 0
@@ -111,7 +122,7 @@ class Solver:
                 raise NoConvergence(f"residual {r:.3e} after {cycles} V-cycles")
             self.vcycle(g, f)
             cycles += 1
-            r = resnorm(g, f, lev)
+            r = self.resnorm(g, f, lev)
             if history is not None:
                 history.append(r)
         return cycles, r

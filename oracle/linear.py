@@ -23,6 +23,11 @@ The continuum limit of the growth rate, (eig - 1)/s -> sigma with
 sigma^2 + (gamma k^2/rho_bar) sigma + rho_bar k^2 (c_c - c_e) = 0, is unstable
 exactly when c_c < c_e; for CDFT that is 1 - rho_bar Jhat(k) < 0 (Sec. 6.2).
 
+The gradient-flow scheme (Thm. thm_grad) about rho_bar has no velocity: with
+the same c_c, c_e the mode evolves as
+  r^{k+1} (1 + s lam c_c) = r^k (1 + s lam c_e),
+a factor above one exactly when c_c < c_e (the same instability criterion).
+
 A pure shear u = A sin(2 pi q y / L), v = 0 about rho_bar decays as
 Crank-Nicolson viscous diffusion: u^{k+1} = A (1 - s gamma lam_y/(2 rho_bar))
 / (1 + s gamma lam_y/(2 rho_bar)) sin(...) + O(A^2).
@@ -56,3 +61,8 @@ def one_step(r0, z0, rho_bar, s, gamma, lam, G, cc, ce_):
 def shear_factor(rho_bar, s, gamma, lam_y):
     c = 0.5 * s * gamma * lam_y / rho_bar
     return (1.0 - c) / (1.0 + c)
+
+
+def gf_factor(s, lam, cc, ce_):
+    """Amplification of a Fourier mode by one linearised gradient-flow step."""
+    return (1.0 + s * lam * ce_) / (1.0 + s * lam * cc)
