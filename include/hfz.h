@@ -19,6 +19,20 @@
  * smoother of App. G (red-black ordered), full-weighting restriction and
  * bilinear prolongation, until ||S - N(g)||_2 <= tol.
  *
+ * The same solver also advances the gradient-flow scheme of Thm. thm_grad
+ * (Eq. gradient_scheme), models HFZ_PFC_GF and HFZ_CDFT_GF:
+ *
+ *   rho^{k+1} - rho^k = s Delta_h mu^{k+1},   mu^{k+1} = dF_c[rho^{k+1}] - dF_e[rho^k]
+ *
+ * with the same discrete free energies and splittings.  The paper proves it
+ * mass conserving and unconditionally energy stable but gives no solver for
+ * it; here its unknowns per node are (rho, mu, kappa = Delta_h rho) for PFC
+ * and (rho, mu) for CDFT, the rows are N1 = rho - s Delta_h mu, the mu row of
+ * the free energy (App. G's PFC rows 4-5, or mu - ln rho - 2 c_e rho for
+ * CDFT), and the App. G smoother's recipe applies: exact block solve with
+ * the nonlinearity linearised about the current iterate, damping w, the
+ * CDFT positivity projection.  The state is rho alone (u = v = 0).
+ *
  * Conventions for every entry point
  *  - Return value: HFZ_OK (0) or a negative HFZ_E* code; no exception or
  *    abort crosses the ABI.  hfz_strerror() names a code.
@@ -55,21 +69,23 @@ enum {
   HFZ_ESTATE = -7    /* call out of order (e.g. step before set_state) */
 };
 
-enum { HFZ_PFC = 0, HFZ_CDFT = 1 };
+/* Hydrodynamic PFC / CDFT step (Eqs. discrete_a-d), or the gradient-flow
+ * scheme of Thm. thm_grad with the PFC / CDFT free energy. */
+enum { HFZ_PFC = 0, HFZ_CDFT = 1, HFZ_PFC_GF = 2, HFZ_CDFT_GF = 3 };
 enum { HFZ_FP64 = 0, HFZ_MIXED = 1 };
 
 /* Parameters of one simulation.  Paper values: gamma = 2 (Sec. 6), w_damp =
  * 0.5 (App. G, damped Gauss-Seidel), delta = 1e-10 for CDFT and unused for PFC
  * (Sec. 6, positivity projection), alpha = 1 - eps (App. B). */
 typedef struct hfz_params {
-  int model;          /* HFZ_PFC or HFZ_CDFT */
+  int model;          /* HFZ_PFC, HFZ_CDFT, HFZ_PFC_GF or HFZ_CDFT_GF */
   int n;              /* grid is n x n, n a power of two, 8 <= n <= 8192 */
   double h;           /* grid spacing (> 0) */
   double s;           /* time step (> 0) */
-  double gamma;       /* viscosity (> 0) */
-  double alpha;       /* PFC: coefficient of the quadratic term */
-  double nu;          /* CDFT: kernel scale of J (Sec. 6) */
-  double delta;       /* CDFT: rho <- sqrt(rho^2 + delta^2) after each rho update */
+  double gamma;       /* viscosity (> 0; unused by the gradient flow) */
+  double alpha;       /* PFC (both schemes): coefficient of the quadratic term */
+  double nu;          /* CDFT (both schemes): kernel scale of J (Sec. 6) */
+  double delta;       /* CDFT (both schemes): rho <- sqrt(rho^2 + delta^2) after each rho update */
   double w_damp;      /* damping, x <- (1 - w) x_GS + w x_old, 0 <= w < 1 */
   double tol;         /* residual tolerance on ||S - N(g)||_2 (h^2-weighted) */
   int nu1, nu2;       /* pre / post smoothing sweeps per level (>= 0, sum >= 1) */
@@ -78,8 +94,9 @@ typedef struct hfz_params {
   int coarse_sweeps;  /* sweeps on the coarsest grid per V-cycle (>= 1) */
   int precision;      /* HFZ_FP64, or HFZ_MIXED: FP32 smoothing inside FP64 defect correction
                          (three FP32 V-cycles per outer FP64 iteration) */
-  int sigma;          /* +1: -rho omega x u in vector form (default); -1: App. G sign */
-  int continuity_fix; /* 1: recompute rho^{k+1} from the continuity row after the solve */
+  int sigma;          /* +1: -rho omega x u in vector form (default); -1: App. G sign (hydrodynamic only) */
+  int continuity_fix; /* 1: recompute rho^{k+1} from the continuity row after the solve
+                         (gradient flow: rho^{k+1} = rho^k + s Delta_h mu^{k+1}) */
 } hfz_params;
 
 typedef struct hfz_stats {
@@ -108,15 +125,20 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
              hfz_handle** out);
 
 /* Loads (rho^0, u^0, v^0) from device buffers of n*n doubles each (copied;
- * the caller keeps ownership).  PFC: mu and kappa start consistent with
- * rho^{k+1} = rho^k.  CDFT: fails with HFZ_EDOMAIN if min rho <= 0. */
+ * the caller keeps ownership).  PFC (both schemes): mu and kappa start
+ * consistent with rho^{k+1} = rho^k; CDFT gradient flow: mu = dF[rho].
+ * CDFT (both schemes): fails with HFZ_EDOMAIN if min rho <= 0.  Gradient
+ * flow: u and v are ignored and may be NULL (the velocity is zero). */
 int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const double* v);
 
-/* Copies the current (rho^k, u^k, v^k) into caller device buffers. */
+/* Copies the current (rho^k, u^k, v^k) into caller device buffers; for the
+ * gradient flow u and v may be NULL (else they receive zeros). */
 int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v);
 
-/* Copies the PFC auxiliary unknowns (mu, kappa) of the last solve (or the
- * initial guess) into caller device buffers; HFZ_EINVAL for CDFT. */
+/* Copies the auxiliary unknowns of the last solve (or those of hfz_set_state)
+ * into caller device buffers: (mu, kappa) for PFC and the PFC gradient flow;
+ * mu for the CDFT gradient flow (kappa may be NULL, and is left untouched);
+ * HFZ_EINVAL for the hydrodynamic CDFT, which has none. */
 int hfz_get_aux(hfz_handle* hd, double* mu, double* kappa);
 
 /* Advances nsteps time steps.  On HFZ_ENOCONV / HFZ_ENAN the failing step is
@@ -126,7 +148,8 @@ int hfz_step(hfz_handle* hd, int nsteps, hfz_stats* stats);
 
 /* Discrete energy of the current state (Thm. thm_energy_stability):
  * out[0] = E = KE + F, out[1] = KE = (rho u || u)/2, out[2] = F,
- * out[3], out[4] = F_id, F_ex for CDFT (0 for PFC).  Host array of 5. */
+ * out[3], out[4] = F_id, F_ex for CDFT (0 for PFC).  Host array of 5.
+ * Gradient flow: KE = 0 and E = F, the energy of Thm. thm_grad. */
 int hfz_energy(hfz_handle* hd, double* out5);
 
 /* Discrete mass (rho || 1) = h^2 sum rho of the current state. */
@@ -137,7 +160,8 @@ int hfz_mass(hfz_handle* hd, double* mass);
 
 /* Source and frozen coefficients of the step from the current state: S and
  * omega^k (App. G), rho^k and omega^k restricted to every level, the CDFT
- * convolution J * rho^k; the iterate g starts at the state. */
+ * convolution J * rho^k; the iterate g starts at the state.  Gradient flow:
+ * S and g = (rho^k, dF[rho^k] (, Delta_h rho^k)) on level 0 only. */
 int hfz_begin_step(hfz_handle* hd);
 /* `sweeps` damped red-black sweeps on level `level` (0 = finest). */
 int hfz_smooth(hfz_handle* hd, int level, int sweeps);
@@ -145,7 +169,8 @@ int hfz_smooth(hfz_handle* hd, int level, int sweeps);
 int hfz_vcycle(hfz_handle* hd, int count);
 /* ||f - N(g)||_2 on level 0 (host double). */
 int hfz_residual(hfz_handle* hd, double* norm);
-/* Ends the step: continuity fix, state <- g, next CDFT convolution. */
+/* Ends the step: continuity fix, state <- g, next CDFT convolution
+ * (gradient flow: rho^{k+1} from row 1, mu (and kappa) kept as auxiliaries). */
 int hfz_finish_step(hfz_handle* hd);
 
 /* Field access for tests.  which: 0 = iterate g, 1 = right-hand side f,
@@ -173,7 +198,8 @@ const char* hfz_strerror(int code);
  * instances is one kernel launch (instance index in the grid), the coarse
  * tail one workgroup per instance.  All instances share model, n, precision,
  * nu1, nu2 (both >= 1), coarsest_n and coarse_sweeps; h, s, gamma and the
- * model constants may differ.  Each instance keeps its own stop test and
+ * model constants may differ (hydrodynamic models only: HFZ_EINVAL for the
+ * gradient flow).  Each instance keeps its own stop test and
  * leaves the launches when it converges, so its result is bitwise the one
  * the single-instance solver produces.  Ownership, streams and errors as for
  * the single-instance calls. */

@@ -60,7 +60,7 @@ __global__ void k_mp_prepare_b(const Lvl<double>* Ls, const Phys<double>* Ps, co
       E.g[c][q.p] = 0.0f;
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
+    for (int c = 0; c < NBase<MODEL>::value; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
   }
   const double r = block_sum(acc, lds);
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[(size_t)z * pstride + blockIdx.y * gridDim.x + blockIdx.x] = r;
@@ -241,6 +241,86 @@ template <int MODEL> __global__ void k_state_b(const Lvl<double>* L0s, const Sta
     as_global(S.mu)[t] = L.g[3][t];
     as_global(S.ka)[t] = L.g[4][t];
   }
+}
+
+// ------------------------------------------------ gradient-flow variant --
+// Start of a gradient-flow step (Thm. thm_grad) on level 0 (its rows have no
+// frozen coefficients, so no coarse level needs anything): the source
+//   S1 = rho^k;  GPFC: S2 = 2 Delta_h rho^k, S3 = 0;  GCDFT: S2 = -(J*rho^k + 2 c_e rho^k)
+// and the initial guess g = (rho^k, dF[rho^k] (, Delta_h rho^k)) with
+// dF = dF_c - dF_e of Sec. 5.3 / 5.2: GPFC (phi^3/3 + alpha phi +
+// Delta_h^2 rho) + 2 Delta_h rho, GCDFT (ln rho + 2 c_e rho) - (2 c_e rho + J*rho).
+// rho^k is level 0's rk; J*rho^k the state's jrho.
+template <int MODEL>
+__global__ void k_begin_gf(const Lvl<double>* L0s, const StateB* Ss, const Phys<double>* Ps, const int* on) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> L = lvl_global(L0s[z]);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const Phys<double> P = Ps[z];
+  const double* rho = L.rk;
+  const Nbr q = nbr(i, j, L.n, L.lg);
+  const double r = rho[q.p];
+  L.f[0][q.p] = r;
+  L.g[0][q.p] = r;
+  if constexpr (MODEL == GPFC) {
+    const double ih2 = 1.0 / (L.h * L.h);
+    const int m = L.n - 1;
+    // Delta_h rho at (a, b)
+    auto lap = [&](int a, int b) {
+      const Nbr t = nbr(a & m, b & m, L.n, L.lg);
+      return (rho[t.e] + rho[t.w] + rho[t.n] + rho[t.s] - 4.0 * rho[t.p]) * ih2;
+    };
+    const double lP = lap(i, j);
+    const double l2 = (lap(i + 1, j) + lap(i - 1, j) + lap(i, j + 1) + lap(i, j - 1) - 4.0 * lP) * ih2;
+    const double phi = r - 1.5;
+    L.f[1][q.p] = 2.0 * lP;
+    L.f[2][q.p] = 0.0;
+    L.g[1][q.p] = (phi * phi * phi / 3.0 + P.alpha * phi + l2) + 2.0 * lP;
+    L.g[2][q.p] = lP;
+  } else {
+    const double jr = as_global(Ss[z].jrho)[q.p];
+    const double tc = 2.0 * P.ce;
+    L.f[1][q.p] = -(jr + tc * r);
+    L.g[1][q.p] = (log(r) + tc * r) - (tc * r + jr);
+  }
+}
+
+// End of a gradient-flow step: with `fix`, rho^{k+1} = rho^k + s Delta_h mu
+// from the converged mu (row 1 exactly, so that the mass is conserved to
+// round-off), else the solve's rho; into g[0] and the state (level 0's rk),
+// and mu (GPFC: and kappa) into the state's auxiliaries.  Each thread reads
+// only its own rk and g[0] and the other threads' mu, so one pass is safe.
+template <int MODEL>
+__global__ void k_finish_gf(const Lvl<double>* L0s, const StateB* Ss, const Phys<double>* Ps, const int* on,
+                            int fix) {
+  const int z = blockIdx.z;
+  if (!on[z]) return;
+  const Lvl<double> L = lvl_global(L0s[z]);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.n || j >= L.n) return;
+  const Nbr q = nbr(i, j, L.n, L.lg);
+  const double* mu = L.g[1];
+  double r = L.g[0][q.p];
+  if (fix) r = L.rk[q.p] + Ps[z].s * ((nsum(mu, q) - 4.0 * mu[q.p]) / (L.h * L.h));
+  L.g[0][q.p] = r;
+  L.rk[q.p] = r;
+  const StateB S = Ss[z];
+  as_global(S.mu)[q.p] = mu[q.p];
+  if constexpr (MODEL == GPFC) as_global(S.ka)[q.p] = L.g[2][q.p];
+}
+
+// mu = dF[rho] of GCDFT, (ln rho + 2 c_e rho) - (2 c_e rho + J*rho): the
+// auxiliary consistent with the state before its first step.
+__global__ void k_gcdft_mu0(const double* __restrict__ rho, const double* __restrict__ jrho,
+                            double* __restrict__ mu, size_t count, double ce) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const double r = rho[t], tc = 2.0 * ce;
+  mu[t] = (log(r) + tc * r) - (tc * r + jrho[t]);
 }
 
 }  // namespace hfz

@@ -69,16 +69,16 @@ template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, 
 // down the residual scratch d fits in LDS too (d_from = nt: none).  Grids of
 // 16^2 and below always fit.
 template <int MODEL, typename T, bool CORR> bool tail_plan(int top_n, int nt, size_t lds_max, int* d_from) {
-  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
-  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
+  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB, NR>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
   int df = nt;
-  while (df > 0 && tail_lds_count<NCm, NB>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
+  while (df > 0 && tail_lds_count<NCm, NB, NR>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
   if (d_from) *d_from = df;
   return true;
 }
 
 template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l) {
-  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
   TailArgs<T> A{};
   A.nt = (int)H.L.size() - l;
   A.Lg = H.desc + l;
@@ -87,7 +87,7 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
   tail_plan<MODEL, T, CORR>(A.top_n, A.nt, H.tail_lds_max, &A.d_from);
-  const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.d_from) * sizeof(T);
+  const size_t sh = tail_lds_count<NCm, NB, NR>(A.top_n, A.nt, A.d_from) * sizeof(T);
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "hfz.h"
@@ -36,11 +37,31 @@ int ilog2(int x) {
   return l;
 }
 
+// Calls f with the model as a compile-time constant (std::integral_constant).
+template <class F> auto by_model(int model, F&& f) {
+  switch (model) {
+    case HFZ_PFC:
+      return f(std::integral_constant<int, PFC>());
+    case HFZ_CDFT:
+      return f(std::integral_constant<int, CDFT>());
+    case HFZ_PFC_GF:
+      return f(std::integral_constant<int, GPFC>());
+    default:
+      return f(std::integral_constant<int, GCDFT>());
+  }
+}
+
+bool model_cdft(int model) { return model == HFZ_CDFT || model == HFZ_CDFT_GF; }
+bool model_gf(int model) { return model == HFZ_PFC_GF || model == HFZ_CDFT_GF; }
+int model_nc(int model) {
+  return model == HFZ_PFC ? 5 : (model == HFZ_CDFT ? 3 : (model == HFZ_PFC_GF ? 3 : 2));
+}
+
 int validate(const hfz_params* p) {
   if (!p) return HFZ_EINVAL;
-  if (p->model != HFZ_PFC && p->model != HFZ_CDFT) return HFZ_EINVAL;
+  if (p->model < HFZ_PFC || p->model > HFZ_CDFT_GF) return HFZ_EINVAL;
   if (!is_pow2(p->n) || p->n < 8 || p->n > 8192) return HFZ_EINVAL;
-  if (p->model == HFZ_CDFT && p->n > 2048) return HFZ_EINVAL;  // LDS row FFT: 2 x 2048 complex doubles
+  if (model_cdft(p->model) && p->n > 2048) return HFZ_EINVAL;  // LDS row FFT: 2 x 2048 complex doubles
   if (!(p->h > 0) || !(p->s > 0) || !(p->gamma > 0)) return HFZ_EINVAL;
   if (!(p->w_damp >= 0.0) || !(p->w_damp < 1.0)) return HFZ_EINVAL;
   if (!(p->tol > 0)) return HFZ_EINVAL;
@@ -49,8 +70,8 @@ int validate(const hfz_params* p) {
   if (!is_pow2(p->coarsest_n) || p->coarsest_n < 4 || p->coarsest_n > p->n) return HFZ_EINVAL;
   if (p->sigma != 1 && p->sigma != -1) return HFZ_EINVAL;
   if (p->precision != HFZ_FP64 && p->precision != HFZ_MIXED) return HFZ_EINVAL;
-  if (p->model == HFZ_CDFT && (!(p->nu > 0) || !(p->delta >= 0))) return HFZ_EINVAL;
-  if (p->model == HFZ_PFC && !std::isfinite(p->alpha)) return HFZ_EINVAL;
+  if (model_cdft(p->model) && (!(p->nu > 0) || !(p->delta >= 0))) return HFZ_EINVAL;
+  if (!model_cdft(p->model) && !std::isfinite(p->alpha)) return HFZ_EINVAL;
   return HFZ_OK;
 }
 
@@ -121,7 +142,7 @@ namespace {
 // Lays out every buffer of the handle; with ws == nullptr only sizes.
 size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
   Carver c{static_cast<char*>(ws)};
-  const int nc = (p.model == HFZ_PFC) ? 5 : 3;
+  const int nc = model_nc(p.model);
   const int n = p.n;
   const size_t N2 = (size_t)n * n;
   std::vector<Lvl<double>> L;
@@ -145,13 +166,11 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
   double* u = c.take<double>(N2);
   double* v = c.take<double>(N2);
   double *mu = nullptr, *ka = nullptr;
-  if (p.model == HFZ_PFC) {
-    mu = c.take<double>(N2);
-    ka = c.take<double>(N2);
-  }
+  if (p.model != HFZ_CDFT) mu = c.take<double>(N2);  // the auxiliaries (PFC: mu, kappa; CDFT gradient flow: mu)
+  if (p.model == HFZ_PFC || p.model == HFZ_PFC_GF) ka = c.take<double>(N2);
   double *jrho = nullptr, *mult = nullptr;
   double2 *fa = nullptr, *fb = nullptr;
-  if (p.model == HFZ_CDFT) {
+  if (model_cdft(p.model)) {
     jrho = c.take<double>(N2);
     mult = c.take<double>(N2);
     fa = c.take<double2>(N2);
@@ -295,10 +314,7 @@ template <int MODEL> void residual_launch_t(hfz_handle* hd, bool stop, bool coun
 }
 
 void residual_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
-  if (hd->p.model == HFZ_PFC)
-    residual_launch_t<PFC>(hd, stop, counted);
-  else
-    residual_launch_t<CDFT>(hd, stop, counted);
+  by_model(hd->p.model, [&](auto m) { residual_launch_t<decltype(m)::value>(hd, stop, counted); });
 }
 
 int residual_read(hfz_handle* hd, double* norm) {
@@ -316,10 +332,7 @@ int residual(hfz_handle* hd, double* norm) {
 
 void vcycle(hfz_handle* hd) {
   Cycle K = cycle_ctx(hd);
-  if (hd->p.model == HFZ_PFC)
-    hfz::vcycle<PFC, double, false>(hd->H, K);
-  else
-    hfz::vcycle<CDFT, double, false>(hd->H, K);
+  by_model(hd->p.model, [&](auto m) { hfz::vcycle<decltype(m)::value, double, false>(hd->H, K); });
   hd->norm_partials = K.norm_partials;
 }
 
@@ -376,10 +389,9 @@ int cycle_and_residual(hfz_handle* hd, double* norm) {
 void mp_prepare_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
-  if (hd->p.model == HFZ_PFC)
-    k_mp_prepare<PFC><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
-  else
-    k_mp_prepare<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
+  by_model(hd->p.model, [&](auto m) {
+    k_mp_prepare<decltype(m)::value><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
+  });
   reduce_launch(hd, (int)(g.x * g.y), stop, counted);
 }
 
@@ -391,13 +403,11 @@ void mp_cycle(hfz_handle* hd, bool stop) {
   Cycle K = cycle_ctx(hd);
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
-  if (hd->p.model == HFZ_PFC) {
-    for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<PFC, float, true>(hd->H32, K);
-    k_mp_update<PFC><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
-  } else {
-    for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<CDFT, float, true>(hd->H32, K);
-    k_mp_update<CDFT><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
-  }
+  by_model(hd->p.model, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<M, float, true>(hd->H32, K);
+    k_mp_update<M><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
+  });
   mp_prepare_launch(hd, stop);
 }
 
@@ -558,8 +568,15 @@ void copy_dev(hfz_handle* hd, const double* a, double* b, size_t count) {
 
 // Start of a step: omega^k and the source S, the iterate g = state, rho^k and
 // omega^k on every level (and their FP32 copies in mixed precision), with
-// the batched kernels over this one instance.
+// the batched kernels over this one instance.  Gradient flow: S and the
+// initial guess on level 0 (no frozen coefficients).
 template <int MODEL> int begin_step_t(hfz_handle* hd) {
+  if constexpr (gradflow(MODEL)) {
+    const int n = hd->p.n;
+    const dim3 b = block2(n, n), g = grid2(n, n, b);
+    k_begin_gf<MODEL><<<g, b, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->phys1, hd->on1);
+    return last_error();
+  }
   const bool mixed = hd->p.precision == HFZ_MIXED;
   for (int l = 0; l < hd->nlev; ++l) {
     const int n = hd->H.L[l].n;
@@ -574,13 +591,23 @@ template <int MODEL> int begin_step_t(hfz_handle* hd) {
 }
 
 int begin_step(hfz_handle* hd) {
-  return hd->p.model == HFZ_PFC ? begin_step_t<PFC>(hd) : begin_step_t<CDFT>(hd);
+  return by_model(hd->p.model, [&](auto m) { return begin_step_t<decltype(m)::value>(hd); });
 }
 
 // End of a step: continuity update, state <- g, the next CDFT convolution.
 int finish_step(hfz_handle* hd) {
   const int n = hd->p.n;
   const dim3 b = block2(n, n), g = grid2(n, n, b);
+  if (model_gf(hd->p.model)) {
+    const int fix = hd->p.continuity_fix ? 1 : 0;
+    if (hd->p.model == HFZ_PFC_GF) {
+      k_finish_gf<GPFC><<<g, b, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->phys1, hd->on1, fix);
+    } else {
+      k_finish_gf<GCDFT><<<g, b, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->phys1, hd->on1, fix);
+      convolve(hd, hd->H.L[0].rk, hd->jrho);
+    }
+    return last_error();
+  }
   if (hd->p.continuity_fix) k_continuity_b<<<g, b, 0, hd->stream>>>(hd->H.desc, hd->phys1, hd->on1);
   const dim3 gs((unsigned)(((size_t)n * n + 255) / 256));
   if (hd->p.model == HFZ_PFC) {
@@ -597,7 +624,7 @@ int energy_impl(hfz_handle* hd, double* out4) {
   const Lvl<double>& L0 = hd->H.L[0];
   const Dims d = dims2(n, n);
   const int nb = d.grid.x * d.grid.y;
-  if (hd->p.model == HFZ_PFC)
+  if (!model_cdft(hd->p.model))
     k_energy_partial<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, n, L0.lg, L0.h,
                                                              hd->p.alpha, hd->partial);
   else
@@ -633,7 +660,7 @@ double* field_ptr(hfz_handle* hd, int which, int level, int comp) {
 extern "C" {
 
 int hfz_default_params(int model, hfz_params* p) {
-  if (!p || (model != HFZ_PFC && model != HFZ_CDFT)) return HFZ_EINVAL;
+  if (!p || model < HFZ_PFC || model > HFZ_CDFT_GF) return HFZ_EINVAL;
   std::memset(p, 0, sizeof(*p));
   p->model = model;
   p->n = 32;
@@ -642,7 +669,7 @@ int hfz_default_params(int model, hfz_params* p) {
   p->gamma = 2.0;
   p->alpha = 0.975;
   p->nu = 2.362;
-  p->delta = (model == HFZ_CDFT) ? 1e-10 : 0.0;
+  p->delta = model_cdft(model) ? 1e-10 : 0.0;
   p->w_damp = 0.5;
   p->tol = 1e-10;
   p->nu1 = 2;
@@ -704,13 +731,11 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->H32.P.halt = hd->ctl;
   k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
   // opt in to the large LDS of a gfx950 CU for the tail kernels
-  if (p->model == HFZ_PFC) {
-    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<PFC, double, false>));
-    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<PFC, float, true>));
-  } else {
-    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<CDFT, double, false>));
-    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<CDFT, float, true>));
-  }
+  by_model(p->model, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, double, false>));
+    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, float, true>));
+  });
   if (const char* e = std::getenv("HFZ_TAIL_N")) {
     const int t = std::atoi(e);
     if (t == 0 || is_pow2(t)) hd->tail_n = t;
@@ -725,13 +750,11 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   }
   if (hd->use_tiles) {
     const Cycle K = cycle_ctx(hd);
-    if (p->model == HFZ_PFC) {
-      tune_tile_shapes<PFC, double, false>(hd->H, K);
-      if (p->precision == HFZ_MIXED) tune_tile_shapes<PFC, float, true>(hd->H32, K);
-    } else {
-      tune_tile_shapes<CDFT, double, false>(hd->H, K);
-      if (p->precision == HFZ_MIXED) tune_tile_shapes<CDFT, float, true>(hd->H32, K);
-    }
+    by_model(p->model, [&](auto m) {
+      constexpr int M = decltype(m)::value;
+      tune_tile_shapes<M, double, false>(hd->H, K);
+      if (p->precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K);
+    });
   }
   if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));
   if (std::getenv("HFZ_VERBOSE")) {
@@ -745,7 +768,7 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
     for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
     std::fprintf(stderr, "\n");
   }
-  if (p->model == HFZ_CDFT) {
+  if (model_cdft(p->model)) {
     rc = cdft_setup(hd);
     if (rc != HFZ_OK) {
       delete hd;
@@ -770,11 +793,13 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
 }
 
 int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const double* v) {
-  if (!hd || !rho || !u || !v) return HFZ_EINVAL;
+  if (!hd || !rho) return HFZ_EINVAL;
+  const bool gf = model_gf(hd->p.model);
+  if (!gf && (!u || !v)) return HFZ_EINVAL;
   const int n = hd->p.n;
   const size_t N2 = (size_t)n * n;
   Lvl<double>& L0 = hd->H.L[0];
-  if (hd->p.model == HFZ_CDFT) {
+  if (model_cdft(hd->p.model)) {
     k_min_partial<<<256, 256, 0, hd->stream>>>(rho, N2, hd->partial);
     double mins[256];
     HIPCHK(hipMemcpyAsync(mins, hd->partial, sizeof(mins), hipMemcpyDeviceToHost, hd->stream));
@@ -784,14 +809,21 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
     if (!(mn > 0.0)) return HFZ_EDOMAIN;
   }
   copy_dev(hd, rho, L0.rk, N2);
-  copy_dev(hd, u, hd->u, N2);
-  copy_dev(hd, v, hd->v, N2);
+  if (gf) {
+    // the gradient flow has no velocity: u = v = 0 (KE = 0 in the energy)
+    HIPCHK(hipMemsetAsync(hd->u, 0, N2 * sizeof(double), hd->stream));
+    HIPCHK(hipMemsetAsync(hd->v, 0, N2 * sizeof(double), hd->stream));
+  } else {
+    copy_dev(hd, u, hd->u, N2);
+    copy_dev(hd, v, hd->v, N2);
+  }
   const Dims d = dims2(n, n);
-  if (hd->p.model == HFZ_PFC) {
+  if (!model_cdft(hd->p.model)) {
     k_pfc_kappa<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, n, L0.lg, L0.h);
     k_pfc_mu<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, hd->mu, n, L0.lg, L0.h, hd->p.alpha);
   } else {
     convolve(hd, L0.rk, hd->jrho);
+    if (gf) k_gcdft_mu0<<<(unsigned)((N2 + 255) / 256), 256, 0, hd->stream>>>(L0.rk, hd->jrho, hd->mu, N2, hd->ce);
   }
   HIPCHK(hipStreamSynchronize(hd->stream));
   hd->has_state = true;
@@ -799,22 +831,25 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
 }
 
 int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v) {
-  if (!hd || !rho || !u || !v) return HFZ_EINVAL;
+  if (!hd || !rho) return HFZ_EINVAL;
+  if (!model_gf(hd->p.model) && (!u || !v)) return HFZ_EINVAL;
   if (!hd->has_state) return HFZ_ESTATE;
   const size_t N2 = (size_t)hd->p.n * hd->p.n;
   copy_dev(hd, hd->H.L[0].rk, rho, N2);
-  copy_dev(hd, hd->u, u, N2);
-  copy_dev(hd, hd->v, v, N2);
+  if (u) copy_dev(hd, hd->u, u, N2);
+  if (v) copy_dev(hd, hd->v, v, N2);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
 }
 
 int hfz_get_aux(hfz_handle* hd, double* mu, double* kappa) {
-  if (!hd || !mu || !kappa || hd->p.model != HFZ_PFC) return HFZ_EINVAL;
+  if (!hd || !mu || hd->p.model == HFZ_CDFT) return HFZ_EINVAL;
+  const bool has_kappa = hd->ka != nullptr;
+  if (has_kappa && !kappa) return HFZ_EINVAL;
   if (!hd->has_state) return HFZ_ESTATE;
   const size_t N2 = (size_t)hd->p.n * hd->p.n;
   copy_dev(hd, hd->mu, mu, N2);
-  copy_dev(hd, hd->ka, kappa, N2);
+  if (has_kappa) copy_dev(hd, hd->ka, kappa, N2);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
 }
@@ -833,15 +868,12 @@ int hfz_smooth(hfz_handle* hd, int level, int sweeps) {
     const Lvl<double>& L = hd->H.L[level];
     const Fld<double> home = fld<double>(L.g);
     Fld<double> cur = home, other = fld<double>(L.gb);
-    if (hd->p.model == HFZ_PFC)
-      tiled_sweeps<PFC, double, false>(hd->H, K, level, sweeps, false, cur, other);
-    else
-      tiled_sweeps<CDFT, double, false>(hd->H, K, level, sweeps, false, cur, other);
+    by_model(hd->p.model, [&](auto m) {
+      tiled_sweeps<decltype(m)::value, double, false>(hd->H, K, level, sweeps, false, cur, other);
+    });
     if (cur.c[0] != home.c[0]) copy_fields<double>(K, cur, home, hd->nc, (size_t)L.n * L.n);
-  } else if (hd->p.model == HFZ_PFC) {
-    smooth_level<PFC, double>(hd->H, K, level, sweeps);
   } else {
-    smooth_level<CDFT, double>(hd->H, K, level, sweeps);
+    by_model(hd->p.model, [&](auto m) { smooth_level<decltype(m)::value, double>(hd->H, K, level, sweeps); });
   }
   return last_error();
 }
@@ -899,8 +931,8 @@ int hfz_energy(hfz_handle* hd, double* out5) {
   out5[0] = q[0] + F;
   out5[1] = q[0];
   out5[2] = F;
-  out5[3] = hd->p.model == HFZ_CDFT ? q[1] : 0.0;
-  out5[4] = hd->p.model == HFZ_CDFT ? q[2] : 0.0;
+  out5[3] = model_cdft(hd->p.model) ? q[1] : 0.0;
+  out5[4] = model_cdft(hd->p.model) ? q[2] : 0.0;
   if (!std::isfinite(out5[0])) return HFZ_ENAN;
   return HFZ_OK;
 }
@@ -1068,7 +1100,7 @@ BatchLayout batch_layout(const hfz_params* ps, int count) {
 template <int MODEL, typename T, bool CORR>
 void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_max,
                  const Cycle& K, int l) {
-  constexpr int NCm = NC<MODEL>::value, NB = CORR ? 3 : 0;
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
   const int nlev = (int)R.size(), count = B->count;
   int d_from = 0;
   if (R[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(R[l].n, nlev - l, lds_max, &d_from)) {
@@ -1080,7 +1112,7 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
     A.nu2 = K.nu2;
     A.coarse_sweeps = K.coarse_sweeps;
     A.d_from = d_from;
-    const size_t sh = tail_lds_count<NCm, NB>(A.top_n, A.nt, A.d_from) * sizeof(T);
+    const size_t sh = tail_lds_count<NCm, NB, NR>(A.top_n, A.nt, A.d_from) * sizeof(T);
     k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
     return;
   }
@@ -1247,6 +1279,7 @@ int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes
   for (int i = 0; i < count; ++i) {
     const int rc = validate(&params[i]);
     if (rc != HFZ_OK) return rc;
+    if (model_gf(params[i].model)) return HFZ_EINVAL;  // the batched solve covers the hydrodynamic models
     if (!batch_compatible(params[0], params[i])) return HFZ_EINVAL;
   }
   if (params[0].nu1 < 1 || params[0].nu2 < 1) return HFZ_EINVAL;

@@ -188,7 +188,7 @@ __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
   for (int c = 0; c < NCm; ++c) C.f[c][q.p] += nv[c];
 }
 
-// K7: g += P(g_c - R g), bilinear; CDFT re-projects rho.
+// K7: g += P(g_c - R g), bilinear; CDFT (both variants) re-projects rho.
 template <int MODEL, typename T>
 __global__ void k_prolong(Lvl<T> F, Lvl<T> C, Phys<T> P) {
   if (halted(P.halt)) return;
@@ -217,7 +217,7 @@ __global__ void k_prolong(Lvl<T> F, Lvl<T> C, Phys<T> P) {
                      (C.g[c][p11] - C.g0[c][p11]));
     }
     T x = F.g[c][pf] + e;
-    if constexpr (MODEL == CDFT) {
+    if constexpr (cdft_like(MODEL)) {
       if (c == 0) x = fsqrt(x * x + P.delta * P.delta);
     }
     F.g[c][pf] = x;
@@ -347,7 +347,8 @@ __global__ void k_cast(const double* __restrict__ a, float* __restrict__ b, size
 // ------------------------------------------- mixed precision, outer loop --
 // Before each inner FP32 V-cycle: d = S - N(g) in FP64 on the finest level
 // becomes the inner right-hand side (FP32), the current FP64 iterate's
-// (rho, u, v) the inner base state, the inner correction starts at 0; the
+// (rho, u, v) (gradient flow: rho) the inner base state, the inner
+// correction starts at 0; the
 // per-block partial sums of |d|^2 are the outer stop test.
 template <int MODEL>
 __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double* __restrict__ partial) {
@@ -369,7 +370,7 @@ __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double
       E.g[c][q.p] = 0.0f;
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
+    for (int c = 0; c < NBase<MODEL>::value; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
   }
   const double r = block_sum(acc, lds);
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
@@ -404,7 +405,7 @@ __global__ void k_energy_partial(const double* __restrict__ rho, const double* _
     const double r = rho[q.p];
     ke = 0.5 * r * (u[q.p] * u[q.p] + v[q.p] * v[q.p]);
     ms = r;
-    if constexpr (MODEL == PFC) {
+    if constexpr (!cdft_like(MODEL)) {
       const double phi = r - 1.5;
       const double L = (rho[q.e] + rho[q.w] + rho[q.n] + rho[q.s] - 4.0 * r) / (h * h);
       f1 = phi * phi * phi * phi / 12.0 + 0.5 * alpha * phi * phi + 0.5 * L * L + r * L;

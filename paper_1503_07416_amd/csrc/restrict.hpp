@@ -27,22 +27,23 @@ __device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
-  constexpr int NB = CORR ? 3 : 1;
+  constexpr int NB = CORR ? NBase<MODEL>::value : 1;
+  constexpr bool RK = NCoef<MODEL>::value > 0;
   constexpr int RX = RTILE + 2, RN = RX * RX;
   __shared__ T sg[NCm][RN];
-  __shared__ T srk[RN];
+  __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
   const int mc = C.n - 1;
   const int X0 = (int)blockIdx.x * RTILE - 1, Y0 = (int)blockIdx.y * RTILE - 1;
   for (int w = threadIdx.x; w < RN; w += RTILE * RTILE) {
     const int ly = w / RX, lx = w - ly * RX;
     const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
-    srk[w] = C.rk[(J << C.lg) + I];
+    if constexpr (RK) srk[w] = C.rk[(J << C.lg) + I];
 #pragma unroll
     for (int c = 0; c < NCm; ++c) sg[c][w] = fw9g(F.g[c], 2 * I, 2 * J, F.n, F.lg);
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sb[c][w] = fw9g(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
+      for (int c = 0; c < NB; ++c) sb[c][w] = fw9g(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
     }
   }
   __syncthreads();
@@ -51,7 +52,7 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
   const T* bl[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
+  for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
   const int ty = threadIdx.x / RTILE, tx = threadIdx.x - ty * RTILE;
   const int ly = ty + 1, lx = tx + 1;
   const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
@@ -73,7 +74,7 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   }
   if constexpr (CORR) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) C.bg[c][pc] = sb[c][q.p];
+    for (int c = 0; c < NB; ++c) C.bg[c][pc] = sb[c][q.p];
   }
 }
 
@@ -112,7 +113,8 @@ template <typename T> __device__ __forceinline__ T fw9l(const T* f, int p, int s
 template <int MODEL, typename T, bool CORR, int RT, int NT>
 __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
-  constexpr int NB = CORR ? 3 : 1;
+  constexpr int NB = CORR ? NBase<MODEL>::value : 1;
+  constexpr bool RK = NCoef<MODEL>::value > 0;
   constexpr int CX = RT + 2, CN = CX * CX;      // coarse tile and its ring
   constexpr int FX = 2 * RT + 5, FN = FX * FX;  // fine nodes under the ring's stencils
   constexpr int DX = 2 * RT + 1, DN = DX * DX;  // fine nodes under the tile's stencils
@@ -121,7 +123,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
   __shared__ T fd[NCm][DN];
   __shared__ T sg[NCm][CN];
   __shared__ T sb[NB][CORR ? CN : 1];
-  __shared__ T srk[CN];
+  __shared__ T srk[RK ? CN : 1];
   const int mc = C.n - 1, mf = F.n - 1;
   const int X0 = (int)blockIdx.x * RT - 1, Y0 = (int)blockIdx.y * RT - 1;  // coarse ring origin
   const int fx0 = 2 * X0 - 1, fy0 = 2 * Y0 - 1;                              // fine origin of fg
@@ -132,7 +134,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
     for (int c = 0; c < NCm; ++c) fg[c][w] = F.g[c][p];
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) fb[c][w] = F.bg[c][p];
+      for (int c = 0; c < NB; ++c) fb[c][w] = F.bg[c][p];
     }
   }
   for (int w = threadIdx.x; w < DN; w += NT) {
@@ -141,9 +143,11 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
 #pragma unroll
     for (int c = 0; c < NCm; ++c) fd[c][w] = F.d[c][p];
   }
-  for (int w = threadIdx.x; w < CN; w += NT) {
-    const int ly = w / CX, lx = w - ly * CX;
-    srk[w] = C.rk[(((Y0 + ly) & mc) << C.lg) + ((X0 + lx) & mc)];
+  if constexpr (RK) {
+    for (int w = threadIdx.x; w < CN; w += NT) {
+      const int ly = w / CX, lx = w - ly * CX;
+      srk[w] = C.rk[(((Y0 + ly) & mc) << C.lg) + ((X0 + lx) & mc)];
+    }
   }
   __syncthreads();
   for (int w = threadIdx.x; w < CN; w += NT) {
@@ -153,7 +157,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
     for (int c = 0; c < NCm; ++c) sg[c][w] = fw9l(fg[c], fl, FX);
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sb[c][w] = fw9l(fb[c], fl, FX);
+      for (int c = 0; c < NB; ++c) sb[c][w] = fw9l(fb[c], fl, FX);
     }
   }
   __syncthreads();
@@ -162,7 +166,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
   const T* bl[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
+  for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
   for (int w = threadIdx.x; w < RT * RT; w += NT) {
     const int ty = w / RT, tx = w - ty * RT;
     const int ly = ty + 1, lx = tx + 1;
@@ -185,7 +189,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
     }
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) C.bg[c][pc] = sb[c][q.p];
+      for (int c = 0; c < NB; ++c) C.bg[c][pc] = sb[c][q.p];
     }
   }
 }

@@ -10,9 +10,24 @@
 
 namespace hfz {
 
-enum { PFC = 0, CDFT = 1 };
+// PFC and CDFT: the hydrodynamic step (App. G).  GPFC and GCDFT: the
+// gradient-flow variant of the same convex splitting (Thm. thm_grad).
+enum { PFC = 0, CDFT = 1, GPFC = 2, GCDFT = 3 };
 
-template <int MODEL> struct NC { static constexpr int value = (MODEL == PFC) ? 5 : 3; };
+__host__ __device__ constexpr bool gradflow(int m) { return m == GPFC || m == GCDFT; }
+__host__ __device__ constexpr bool cdft_like(int m) { return m == CDFT || m == GCDFT; }
+
+// Unknowns per node: PFC (rho, u, v, mu, kappa), CDFT (rho, u, v), GPFC
+// (rho, mu, kappa), GCDFT (rho, mu).
+template <int MODEL> struct NC {
+  static constexpr int value = MODEL == PFC ? 5 : (MODEL == CDFT ? 3 : (MODEL == GPFC ? 3 : 2));
+};
+// Base fields the correction form is taken about: (rho, u, v), or rho alone
+// in the gradient flow (its only nonlinearities are in rho).
+template <int MODEL> struct NBase { static constexpr int value = gradflow(MODEL) ? 1 : 3; };
+// Frozen-coefficient arrays the rows read (rho^k, omega^k); the gradient-flow
+// rows have constant coefficients.
+template <int MODEL> struct NCoef { static constexpr int value = gradflow(MODEL) ? 0 : 2; };
 
 __device__ __forceinline__ double flog(double x) { return log(x); }
 __device__ __forceinline__ float flog(float x) { return logf(x); }
@@ -121,13 +136,90 @@ __device__ __forceinline__ T potential(const T* const* g, int q, const Phys<T>& 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gradient-flow variant (Thm. thm_grad, Eq. gradient_scheme): rho^{k+1} -
+// rho^k = s Delta_h (dF_c[rho^{k+1}] - dF_e[rho^k]) with the discrete
+// gradients of Sec. 5.2 / 5.3, written as N(g) = S with mu (and for PFC
+// kappa = Delta_h rho) as unknowns:
+//   N1 = rho - s Delta_h mu                              S1 = rho^k
+//   GPFC:  N2 = mu - phi^3/3 - alpha phi - Delta_h kappa, S2 = 2 Delta_h rho^k
+//          N3 = kappa - Delta_h rho,                      S3 = 0
+//   GCDFT: N2 = mu - ln rho - 2 c_e rho,   S2 = -(J*rho^k + 2 c_e rho^k)
+// The smoother solves the node's block exactly with the neighbours held and
+// the nonlinearity linearised about the current iterate (the App. G
+// treatment of the cubic), then damps like App. G; GCDFT projects rho^.
+// With c = 1/h^2 and sums over the four neighbours the block is
+//   rho + 4 s c mu = S1 + s c sum(mu)                                =: b1
+//   GPFC:  mu - A rho + 4 c kappa = S2 - 3A/2 - (2/3) phi_l^3 + c sum(kappa) =: b2,
+//          A = alpha + phi_l^2;   kappa + 4 c rho = S3 + c sum(rho)  =: b3
+//   GCDFT: mu - B rho = S2 + ln rho_l - 1 =: b2,  B = 1/rho_l + 2 c_e
+// so rho^ = (b1 - 4sc(b2 - 4c b3)) / (1 + 4sc(A + 16c^2)), kappa^ = b3 - 4c rho^,
+// mu^ = b2 + A rho^ - 4c kappa^ (GPFC); rho^ = (b1 - 4sc b2)/(1 + 4sc B),
+// projected, mu^ = b2 + B rho^ (GCDFT).
+
+template <typename T> __device__ __forceinline__ T nsum(const T* f, const Nbr& q) {
+  return f[q.e] + f[q.w] + f[q.n] + f[q.s];
+}
+
+template <int MODEL, typename T>
+__device__ __forceinline__ void rows_gf(const T* const* g, const Nbr& q, const Coef<T>& K, const Phys<T>& P,
+                                        T* out) {
+  const T ih2 = K.ih2;
+  const T* rho = g[0];
+  const T* mu = g[1];
+  const T rP = rho[q.p], mP = mu[q.p];
+  out[0] = rP - P.s * ((nsum(mu, q) - T(4) * mP) * ih2);
+  if constexpr (MODEL == GPFC) {
+    const T* ka = g[2];
+    const T phi = rP - T(1.5);
+    const T lapk = (nsum(ka, q) - T(4) * ka[q.p]) * ih2;
+    const T lapr = (nsum(rho, q) - T(4) * rP) * ih2;
+    out[1] = mP - phi * phi * phi * T(1.0 / 3.0) - P.alpha * phi - lapk;
+    out[2] = ka[q.p] - lapr;
+  } else {
+    out[1] = mP - flog(rP) - T(2) * P.ce * rP;
+  }
+}
+
+template <int MODEL, typename T>
+__device__ __forceinline__ void block_update_gf(const T* const* g, const T* const* f, const Nbr& q, int pf,
+                                                const Coef<T>& K, const Phys<T>& P, T* out) {
+  const T c = K.ih2, sc = P.s * c;
+  const T* rho = g[0];
+  const T* mu = g[1];
+  const T rl = rho[q.p];
+  const T b1 = f[0][pf] + sc * nsum(mu, q);
+  const T w = P.w, w1 = T(1) - P.w;
+  if constexpr (MODEL == GPFC) {
+    const T* ka = g[2];
+    const T pl = rl - T(1.5);
+    const T A = P.alpha + pl * pl;
+    const T b2 = f[1][pf] - T(1.5) * A - (T(2) / T(3)) * pl * pl * pl + c * nsum(ka, q);
+    const T b3 = f[2][pf] + c * nsum(rho, q);
+    const T rh = (b1 - T(4) * sc * (b2 - T(4) * c * b3)) / (T(1) + T(4) * sc * (A + T(16) * c * c));
+    const T kh = b3 - T(4) * c * rh;
+    const T mh = b2 + A * rh - T(4) * c * kh;
+    out[0] = w1 * rh + w * rl;
+    out[1] = w1 * mh + w * mu[q.p];
+    out[2] = w1 * kh + w * ka[q.p];
+  } else {
+    const T B = T(1) / rl + T(2) * P.ce;
+    const T b2 = f[1][pf] + flog(rl) - T(1);
+    T rh = (b1 - T(4) * sc * b2) / (T(1) + T(4) * sc * B);
+    rh = fsqrt(rh * rh + P.delta * P.delta);
+    const T mh = b2 + B * rh;
+    out[0] = w1 * rh + w * rl;
+    out[1] = w1 * mh + w * mu[q.p];
+  }
+}
+
 // Rows of N(g) at node q (App. G, Eqs. MGN_DFT_a-c / MGN_PFC_a-e).  g and rk
 // are read at q and its neighbours; om at index pf (which may live in another
 // array layout, e.g. a global array while g sits in an LDS tile).
 template <int MODEL, typename T, bool PM = false>
-__device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* om, const Nbr& q,
-                                       int pf, const Coef<T>& K, const Phys<T>& P, T* out,
-                                       const T* pm = nullptr) {
+__device__ __forceinline__ void rows_hydro(const T* const* g, const T* rk, const T* om, const Nbr& q,
+                                           int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                           const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* rho = g[0];
@@ -165,9 +257,9 @@ __device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* 
 // cubic linearised about the current iterate.  g and rk are read at q and its
 // neighbours, f and om at index pf.
 template <int MODEL, typename T, bool PM = false>
-__device__ __forceinline__ void block_update(const T* const* g, const T* const* f, const T* rk,
-                                             const T* om, const Nbr& q, int pf, const Coef<T>& K,
-                                             const Phys<T>& P, T* out, const T* pm = nullptr) {
+__device__ __forceinline__ void block_update_hydro(const T* const* g, const T* const* f, const T* rk,
+                                                   const T* om, const Nbr& q, int pf, const Coef<T>& K,
+                                                   const Phys<T>& P, T* out, const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* rho = g[0];
@@ -244,9 +336,9 @@ __device__ __forceinline__ T dq(const T* const* e, const T* const* b, int q) {
 }
 
 template <int MODEL, typename T, bool PM = false>
-__device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, const T* rk, const T* om,
-                                        const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
-                                        const T* pm = nullptr) {
+__device__ __forceinline__ void rows_Nd_hydro(const T* const* e, const T* const* b, const T* rk, const T* om,
+                                              const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                              const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* er = e[0];
@@ -281,10 +373,10 @@ __device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, co
 }
 
 template <int MODEL, typename T, bool PM = false>
-__device__ __forceinline__ void block_update_d(const T* const* e, const T* const* f, const T* const* b,
-                                               const T* rk, const T* om, const Nbr& q, int pf,
-                                               const Coef<T>& K, const Phys<T>& P, T* out,
-                                               const T* pm = nullptr) {
+__device__ __forceinline__ void block_update_d_hydro(const T* const* e, const T* const* f, const T* const* b,
+                                                     const T* rk, const T* om, const Nbr& q, int pf,
+                                                     const Coef<T>& K, const Phys<T>& P, T* out,
+                                                     const T* pm = nullptr) {
   const T s = P.s;
   const T c4 = K.c4, c2 = K.c2, ih2 = K.ih2;
   const T* er = e[0];
@@ -331,6 +423,113 @@ __device__ __forceinline__ void block_update_d(const T* const* e, const T* const
     out[3] = w1 * mh + w * mu[q.p];
     out[4] = w1 * kh + w * ka[q.p];
   }
+}
+
+// Correction form of the gradient flow about the base density rho_b (b[0]):
+// N_d(e) = N(b + e) - N(b) with the cubic difference
+// c(e) = e (phi_b^2 + phi_b e + e^2/3) (GPFC) and ln((rho_b + e)/rho_b) =
+// log1p(e/rho_b) (GCDFT); the rows are otherwise linear in e.  The block
+// solve linearises c(e) ~ c(e_l) + (phi_b + e_l)^2 (e - e_l) and
+// log1p(e/rho_b) ~ log1p(e_l/rho_b) + (e - e_l)/(rho_b + e_l), and projects
+// rho_b + e^ like the full form.
+template <int MODEL, typename T>
+__device__ __forceinline__ void rows_gfd(const T* const* e, const T* const* b, const Nbr& q, const Coef<T>& K,
+                                         const Phys<T>& P, T* out) {
+  const T ih2 = K.ih2;
+  const T* er = e[0];
+  const T* em = e[1];
+  const T x = er[q.p];
+  out[0] = x - P.s * ((nsum(em, q) - T(4) * em[q.p]) * ih2);
+  if constexpr (MODEL == GPFC) {
+    const T* ek = e[2];
+    const T pb = b[0][q.p] - T(1.5);
+    const T cub = x * (pb * pb + pb * x + x * x * T(1.0 / 3.0));
+    const T lapk = (nsum(ek, q) - T(4) * ek[q.p]) * ih2;
+    const T lapr = (nsum(er, q) - T(4) * x) * ih2;
+    out[1] = em[q.p] - cub - P.alpha * x - lapk;
+    out[2] = ek[q.p] - lapr;
+  } else {
+    out[1] = em[q.p] - flog1p(x / b[0][q.p]) - T(2) * P.ce * x;
+  }
+}
+
+template <int MODEL, typename T>
+__device__ __forceinline__ void block_update_gfd(const T* const* e, const T* const* f, const T* const* b,
+                                                 const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P,
+                                                 T* out) {
+  const T c = K.ih2, sc = P.s * c;
+  const T* er = e[0];
+  const T* em = e[1];
+  const T el = er[q.p];
+  const T b1 = f[0][pf] + sc * nsum(em, q);
+  const T w = P.w, w1 = T(1) - P.w;
+  if constexpr (MODEL == GPFC) {
+    const T* ek = e[2];
+    const T pb = b[0][q.p] - T(1.5);
+    const T pl = pb + el;
+    const T A = P.alpha + pl * pl;
+    const T cl = el * (pb * pb + pb * el + el * el * T(1.0 / 3.0));
+    const T b2 = f[1][pf] + cl - pl * pl * el + c * nsum(ek, q);
+    const T b3 = f[2][pf] + c * nsum(er, q);
+    const T rh = (b1 - T(4) * sc * (b2 - T(4) * c * b3)) / (T(1) + T(4) * sc * (A + T(16) * c * c));
+    const T kh = b3 - T(4) * c * rh;
+    const T mh = b2 + A * rh - T(4) * c * kh;
+    out[0] = w1 * rh + w * el;
+    out[1] = w1 * mh + w * em[q.p];
+    out[2] = w1 * kh + w * ek[q.p];
+  } else {
+    const T rb = b[0][q.p];
+    const T t = rb + el;
+    const T B = T(1) / t + T(2) * P.ce;
+    const T b2 = f[1][pf] + flog1p(el / rb) - el / t;
+    T rh = (b1 - T(4) * sc * b2) / (T(1) + T(4) * sc * B);
+    const T tt = rb + rh;
+    if (!(tt > T(0) && tt * tt > T(1e6) * P.delta * P.delta)) rh = fsqrt(tt * tt + P.delta * P.delta) - rb;
+    const T mh = b2 + B * rh;
+    out[0] = w1 * rh + w * el;
+    out[1] = w1 * mh + w * em[q.p];
+  }
+}
+
+// Model dispatch of the rows and the block update: the hydrodynamic system
+// or the gradient flow.
+template <int MODEL, typename T, bool PM = false>
+__device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* om, const Nbr& q, int pf,
+                                       const Coef<T>& K, const Phys<T>& P, T* out, const T* pm = nullptr) {
+  if constexpr (gradflow(MODEL))
+    rows_gf<MODEL, T>(g, q, K, P, out);
+  else
+    rows_hydro<MODEL, T, PM>(g, rk, om, q, pf, K, P, out, pm);
+}
+
+template <int MODEL, typename T, bool PM = false>
+__device__ __forceinline__ void block_update(const T* const* g, const T* const* f, const T* rk, const T* om,
+                                             const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                             const T* pm = nullptr) {
+  if constexpr (gradflow(MODEL))
+    block_update_gf<MODEL, T>(g, f, q, pf, K, P, out);
+  else
+    block_update_hydro<MODEL, T, PM>(g, f, rk, om, q, pf, K, P, out, pm);
+}
+
+template <int MODEL, typename T, bool PM = false>
+__device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, const T* rk, const T* om,
+                                        const Nbr& q, int pf, const Coef<T>& K, const Phys<T>& P, T* out,
+                                        const T* pm = nullptr) {
+  if constexpr (gradflow(MODEL))
+    rows_gfd<MODEL, T>(e, b, q, K, P, out);
+  else
+    rows_Nd_hydro<MODEL, T, PM>(e, b, rk, om, q, pf, K, P, out, pm);
+}
+
+template <int MODEL, typename T, bool PM = false>
+__device__ __forceinline__ void block_update_d(const T* const* e, const T* const* f, const T* const* b,
+                                               const T* rk, const T* om, const Nbr& q, int pf, const Coef<T>& K,
+                                               const Phys<T>& P, T* out, const T* pm = nullptr) {
+  if constexpr (gradflow(MODEL))
+    block_update_gfd<MODEL, T>(e, f, b, q, pf, K, P, out);
+  else
+    block_update_d_hydro<MODEL, T, PM>(e, f, b, rk, om, q, pf, K, P, out, pm);
 }
 
 // Mode dispatch: CORR = false is the full form, CORR = true the correction

@@ -24,32 +24,33 @@ template <typename T> struct TailArgs {
   int d_from;        // levels l >= d_from keep the residual scratch d in LDS, the others in global memory
 };
 
-// T values of LDS per level l of nt (size n): g, f, rk, om, g0 below the top,
-// the base state in the correction form (NB = 3), and d where it is held in
-// LDS (l >= d_from; the coarsest level needs none).
-template <int NCm, int NB>
+// T values of LDS per level l of nt (size n): g, f, the NR frozen
+// coefficients (rk, om; none in the gradient flow), g0 below the top, the NB
+// base fields of the correction form, and d where it is held in LDS
+// (l >= d_from; the coarsest level needs none).
+template <int NCm, int NB, int NR>
 __host__ __device__ inline size_t tail_level_count(int n, int l, int nt, int d_from) {
   const bool dl = l >= d_from && l < nt - 1;
-  return (size_t)n * n * (2 * NCm + 2 + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
+  return (size_t)n * n * (2 * NCm + NR + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
 }
 
-template <int NCm, int NB = 0>
+template <int NCm, int NB, int NR>
 __host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int d_from) {
   size_t tot = 0;
-  for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB>(top_n >> l, l, nt, d_from);
+  for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB, NR>(top_n >> l, l, nt, d_from);
   return tot;
 }
 
 // Level descriptors of the tail: S = the LDS arrays the phases use, G = the
 // global arrays.  Thread t builds level t (same LDS order as tail_lds_count).
-template <int NCm, int NB, typename T>
+template <int NCm, int NB, int NR, typename T>
 __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S, Lvl<T>* G) {
   const int t = threadIdx.x;
   if (t >= A.nt) return;
   Lvl<T> s = A.Lg[t];
   G[t] = s;
   size_t off = 0;
-  for (int l = 0; l < t; ++l) off += tail_level_count<NCm, NB>(A.top_n >> l, l, A.nt, A.d_from);
+  for (int l = 0; l < t; ++l) off += tail_level_count<NCm, NB, NR>(A.top_n >> l, l, A.nt, A.d_from);
   T* p = base + off;
   const int cnt = s.n * s.n;
 #pragma unroll
@@ -63,9 +64,14 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
     for (int c = 0; c < NCm; ++c) s.g0[c] = p + c * cnt;
     p += NCm * cnt;
   }
-  s.rk = p;
-  s.om = p + cnt;
-  p += 2 * cnt;
+  if constexpr (NR == 2) {
+    s.rk = p;
+    s.om = p + cnt;
+    p += 2 * cnt;
+  } else {
+    s.rk = nullptr;
+    s.om = nullptr;
+  }
 #pragma unroll
   for (int c = 0; c < NB; ++c) s.bg[c] = p + c * cnt;
   p += NB * cnt;
@@ -79,7 +85,7 @@ __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S,
 // The view the phases use of a tail level built by tail_lds_levels: its
 // arrays in LDS (g0 only below the top, G0 = true), the residual scratch d in
 // LDS (DL = true) or global memory.
-template <int NCm, int NB, bool G0, bool DL = false, typename T>
+template <int NCm, int NB, int NR, bool G0, bool DL = false, typename T>
 __device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
   Lvl<T> L = s;
 #pragma unroll
@@ -89,8 +95,10 @@ __device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
     if constexpr (G0) L.g0[c] = as_lds(s.g0[c]);
     L.d[c] = DL ? as_lds(s.d[c]) : as_global(s.d[c]);
   }
-  L.rk = as_lds(s.rk);
-  L.om = as_lds(s.om);
+  if constexpr (NR == 2) {
+    L.rk = as_lds(s.rk);
+    L.om = as_lds(s.om);
+  }
 #pragma unroll
   for (int c = 0; c < NB; ++c) L.bg[c] = as_lds(s.bg[c]);
   return L;
@@ -144,7 +152,7 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
     }
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) C.bg[c][w] = fw9(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
+      for (int c = 0; c < NBase<MODEL>::value; ++c) C.bg[c][w] = fw9(F.bg[c], 2 * I, 2 * J, F.n, F.lg);
     }
   }
   __syncthreads();
@@ -184,7 +192,7 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
                        (C.g[c][p11] - C.g0[c][p11]));
       }
       T x = F.g[c][w] + e;
-      if constexpr (MODEL == CDFT) {
+      if constexpr (cdft_like(MODEL)) {
         if (c == 0) x = project_any<T, CORR>(x, CORR ? F.bg[0][w] : T(0), P.delta);
       }
       F.g[c][w] = x;
@@ -196,22 +204,26 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P) {
   constexpr int NCm = NC<MODEL>::value;
-  constexpr int NB = CORR ? 3 : 0;
+  constexpr int NB = CORR ? NBase<MODEL>::value : 0;
+  constexpr int NR = NCoef<MODEL>::value;
   extern __shared__ __align__(16) unsigned char tail_smem[];
   // level descriptors in LDS: S = LDS copies, G = the global arrays
   __shared__ Lvl<T> S[TAIL_MAX_LEVELS];
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
-  tail_lds_levels<NCm, NB, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
+  tail_lds_levels<NCm, NB, NR, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
   __syncthreads();
   // load: every global value a thread moves is read before it is stored
   for (int l = 0; l < A.nt; ++l) {
-    const Lvl<T> s = tail_view<NCm, NB, false>(S[l]);
+    const Lvl<T> s = tail_view<NCm, NB, NR, false>(S[l]);
     const Lvl<T> g = lvl_global(G[l]);
     const int cnt = g.n * g.n;
+    if (NR == 0 && l > 0) break;  // only the top level has anything to load
     for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
       T x[2 * NCm + NB + 2];
-      x[0] = g.rk[w];
-      x[1] = g.om[w];
+      if constexpr (NR == 2) {
+        x[0] = g.rk[w];
+        x[1] = g.om[w];
+      }
       if (l == 0) {
 #pragma unroll
         for (int c = 0; c < NCm; ++c) {
@@ -221,8 +233,10 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
 #pragma unroll
         for (int c = 0; c < NB; ++c) x[2 + 2 * NCm + c] = g.bg[c][w];
       }
-      s.rk[w] = x[0];
-      s.om[w] = x[1];
+      if constexpr (NR == 2) {
+        s.rk[w] = x[0];
+        s.om[w] = x[1];
+      }
       if (l == 0) {
 #pragma unroll
         for (int c = 0; c < NCm; ++c) {
@@ -237,21 +251,21 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   __syncthreads();
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
-    const Lvl<T> F = tail_view<NCm, NB, false>(S[l]);
+    const Lvl<T> F = tail_view<NCm, NB, NR, false>(S[l]);
     tail_sweeps<MODEL, T, CORR>(F, P, A.nu1);
     if (l >= A.d_from)
-      tail_restrict<MODEL, T, CORR>(tail_view<NCm, NB, false, true>(S[l]), tail_view<NCm, NB, true>(S[l + 1]), P);
+      tail_restrict<MODEL, T, CORR>(tail_view<NCm, NB, NR, false, true>(S[l]), tail_view<NCm, NB, NR, true>(S[l + 1]), P);
     else
-      tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
+      tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, NR, true>(S[l + 1]), P);
   }
-  tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, false>(S[last]), P, A.coarse_sweeps);
+  tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, NR, false>(S[last]), P, A.coarse_sweeps);
   for (int l = last - 1; l >= 0; --l) {
-    const Lvl<T> F = tail_view<NCm, NB, false>(S[l]);
-    tail_prolong<MODEL, T, CORR>(F, tail_view<NCm, NB, true>(S[l + 1]), P);
+    const Lvl<T> F = tail_view<NCm, NB, NR, false>(S[l]);
+    tail_prolong<MODEL, T, CORR>(F, tail_view<NCm, NB, NR, true>(S[l + 1]), P);
     tail_sweeps<MODEL, T, CORR>(F, P, A.nu2);
   }
   {
-    const Lvl<T> s = tail_view<NCm, NB, false>(S[0]);
+    const Lvl<T> s = tail_view<NCm, NB, NR, false>(S[0]);
     const Lvl<T> g = lvl_global(G[0]);
     const int cnt = g.n * g.n;
     for (int w = threadIdx.x; w < cnt; w += blockDim.x) {

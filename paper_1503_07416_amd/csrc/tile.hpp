@@ -2,7 +2,7 @@
 //
 // k_sweeps_tile: NSW damped red-black sweeps in one launch.  A workgroup owns a
 // TILE_X x TILE_Y block of nodes and loads it with a halo of 2 NSW nodes (the
-// iterate g and the frozen rho^k into LDS).  Each half sweep updates the
+// iterate g and, for the hydrodynamic rows, the frozen rho^k into LDS).  Each half sweep updates the
 // nodes of one colour in a box that shrinks by one node per half sweep, so
 // after 2 NSW half sweeps the owned block holds exactly the values the
 // whole-grid sweeps produce; the halo work is recomputed, not exchanged.  The
@@ -47,7 +47,8 @@ template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS =
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
                                                  const Lvl<T>& C, const Phys<T>& P, double* partial) {
   constexpr int NCm = NC<MODEL>::value;
-  constexpr int NB = CORR ? 3 : 1;
+  constexpr int NB = CORR ? NBase<MODEL>::value : 1;
+  constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
   constexpr int TILE_X = kTileShapes[TS].tx, TILE_Y = kTileShapes[TS].ty, TILE_THREADS = kTileShapes[TS].nt;
   constexpr int H = 2 * NSW + (RES ? 1 : 0);
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
@@ -58,7 +59,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   // instead of at each of their four neighbours.
   constexpr bool PM = MODEL == CDFT;
   __shared__ T sg[NCm][RN];
-  __shared__ T srk[RN];
+  __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
   // se (the coarse correction, read only while loading) and sm (the
   // potential, written only after the load) share one LDS array
@@ -84,10 +85,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     const int ly = w / RX, lx = w - ly * RX;
     const int gi = (x0 + lx) & m, gj = (y0 + ly) & m;
     const int gp = (gj << lg) + gi;
-    srk[w] = L.rk[gp];
+    if constexpr (RK) srk[w] = L.rk[gp];
     if constexpr (CORR) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sb[c][w] = L.bg[c][gp];
+      for (int c = 0; c < NB; ++c) sb[c][w] = L.bg[c][gp];
     }
 #pragma unroll
     for (int c = 0; c < NCm; ++c) {
@@ -108,7 +109,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
         else
           e = T(0.25) * (e00 + se[c][cp + 1] + se[c][cp + CRX] + se[c][cp + CRX + 1]);
         x += e;
-        if constexpr (MODEL == CDFT) {
+        if constexpr (cdft_like(MODEL)) {
           if (c == 0) x = project_any<T, CORR>(x, CORR ? L.bg[0][gp] : T(0), P.delta);
         }
       }
@@ -121,7 +122,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
   const T* bl[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) bl[c] = sb[CORR ? c : 0];
+  for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
     if constexpr (PM) {

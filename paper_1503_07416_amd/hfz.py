@@ -13,7 +13,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhfz.so")
 
-PFC, CDFT = 0, 1
+PFC, CDFT, PFC_GF, CDFT_GF = 0, 1, 2, 3
+MODELS = {"pfc": PFC, "cdft": CDFT, "pfc_gf": PFC_GF, "cdft_gf": CDFT_GF}
 FP64, MIXED = 0, 1
 OK, EINVAL, ENOMEM, EDOMAIN, ENOCONV, ENAN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 
@@ -115,7 +116,7 @@ def make_params(cfg):
     get = (lambda k, dflt=None: cfg.get(k, dflt)) if isinstance(cfg, dict) else \
           (lambda k, dflt=None: getattr(cfg, k, dflt))
     lib = load()
-    model = PFC if get("model") == "pfc" else CDFT
+    model = MODELS[get("model")]
     p = Params()
     check(lib.hfz_default_params(model, ctypes.byref(p)), "hfz_default_params")
     p.n = int(get("n"))
@@ -147,7 +148,7 @@ def workspace_bytes(p):
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(None if t is None else t.data_ptr())
 
 
 class Simulation:
@@ -175,8 +176,17 @@ class Simulation:
         n = self.n if n is None else n
         return torch.empty((n, n), dtype=torch.float64, device=self.device)
 
-    def set_state(self, rho, u, v):
-        r, uu, vv = self._dev(rho), self._dev(u), self._dev(v)
+    @property
+    def gradflow(self):
+        return self.p.model in (PFC_GF, CDFT_GF)
+
+    def set_state(self, rho, u=None, v=None):
+        """(rho, u, v); the gradient-flow models take rho alone (u, v ignored)."""
+        r = self._dev(rho)
+        if self.gradflow:
+            uu = vv = None
+        else:
+            uu, vv = self._dev(u), self._dev(v)
         torch.cuda.current_stream(self.device).synchronize()
         check(self.lib.hfz_set_state(self.h, _ptr(r), _ptr(uu), _ptr(vv)), "hfz_set_state")
 
@@ -186,7 +196,9 @@ class Simulation:
         return r, u, v
 
     def get_aux(self):
-        mu, ka = self._empty(), self._empty()
+        """(mu, kappa) of the last solve; kappa is None for the CDFT gradient flow."""
+        mu = self._empty()
+        ka = None if self.p.model == CDFT_GF else self._empty()
         check(self.lib.hfz_get_aux(self.h, _ptr(mu), _ptr(ka)), "hfz_get_aux")
         return mu, ka
 

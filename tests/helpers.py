@@ -2,10 +2,15 @@
 metrics, and the GPU availability switch."""
 import numpy as np
 
+from oracle import gradflow
 from oracle.fas import Stepper
 
 
 def oracle_stepper(cfg):
+    """The oracle's stepper of a workload config (the hydrodynamic scheme or
+    its gradient-flow variant)."""
+    if getattr(cfg, "gradflow", False):
+        return gradflow.Stepper(cfg.base_model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
     return Stepper(cfg.model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
 
 

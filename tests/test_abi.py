@@ -38,7 +38,7 @@ def ws(**kw):
     lib = hfz.load()
     p = hfz.Params()
     model = kw.pop("model", 0)
-    assert lib.hfz_default_params(model if model in (0, 1) else 0, ctypes.byref(p)) == 0
+    assert lib.hfz_default_params(model if model in (0, 1, 2, 3) else 0, ctypes.byref(p)) == 0
     p.model = model
     for k, v in kw.items():
         setattr(p, k, v)
@@ -73,3 +73,25 @@ def test_simulation_fails_loudly_without_device():
         pytest.skip("a GPU is present")
     with pytest.raises(Exception):
         pkg.Simulation(dict(model="pfc", n=32, h=0.25, s=0.01))
+
+
+def test_gradient_flow_models_validate():
+    """Models 2 and 3 (the gradient flow) size a smaller workspace than their
+    hydrodynamic counterparts (fewer unknowns per node), keep the CDFT size
+    limit of the row FFT, and are refused by the batched solve."""
+    lib = hfz.load()
+    for model, base in [(2, 0), (3, 1)]:
+        p = hfz.Params()
+        assert lib.hfz_default_params(model, ctypes.byref(p)) == 0
+        assert p.model == model
+        assert (p.delta > 0) == (model == 3)
+        rc, nb = ws(model=model, n=512)
+        rcb, nbb = ws(model=base, n=512)
+        assert rc == 0 and rcb == 0 and nb < nbb
+        nbytes = ctypes.c_size_t(0)
+        p.n = 64
+        assert lib.hfz_batch_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(nbytes)) == -1
+    assert ws(model=3, n=4096)[0] == -1
+    assert ws(model=4, n=64)[0] == -1
+    p = hfz.Params()
+    assert lib.hfz_default_params(4, ctypes.byref(p)) == -1

@@ -1,0 +1,202 @@
+"""GPU parity of the gradient-flow variant (Thm. thm_grad, Eq. gradient_scheme)
+through the C ABI against the CPU FP64 oracle (oracle/gradflow.py), stage by
+stage and step by step, for the PFC and CDFT free energies; at the benchmark
+sizes, properties the oracle can evaluate in one pass."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import grid
+from oracle import gradflow as gf
+from tests.helpers import oracle_stepper, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-10     # FP64 step parity, relative (per field)
+TOL_MIXED = 1e-6     # mixed-precision step against the FP64 oracle
+
+
+def np_(t):
+    return t.cpu().numpy()
+
+
+def case(model, n, seed=0, precision="fp64", **kw):
+    return workloads.gradflow(model, n, seed, precision=precision, **kw)
+
+
+def sim_for(cfg, rho):
+    import paper_1503_07416_amd as pkg
+    s = pkg.Simulation(cfg)
+    s.set_state(rho)
+    return s
+
+
+MODELS = ["pfc_gf", "cdft_gf"]
+SIZES = [("pfc_gf", 8), ("pfc_gf", 32), ("pfc_gf", 128), ("cdft_gf", 16), ("cdft_gf", 64), ("cdft_gf", 128)]
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_source_and_initial_guess(model):
+    cfg, rho, _, _ = case(model, 64)
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    if model == "cdft_gf":
+        assert abs(sim.ce() - ora.ce) < 1e-13 * ora.ce
+        assert rel_err(np_(sim.read(4, 0, 0)), ora.Jrho) < 1e-12
+    # hfz_set_state's auxiliaries are dF[rho] (and Delta_h rho)
+    mu, ka = sim.get_aux()
+    g0 = ora.initial_guess()
+    assert rel_err(np_(mu), g0[1]) < 1e-12
+    if ka is not None:
+        assert rel_err(np_(ka), g0[2]) < 1e-12
+    sim.begin_step()
+    S = ora.build_source()
+    for c in range(S.shape[0]):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+        else:
+            assert np.abs(np_(sim.read(1, 0, c))).max() == 0.0
+        assert rel_err(np_(sim.read(0, 0, c)), g0[c]) < 1e-12, c
+    assert sim.levels() == len(ora.solver().levels)
+
+
+@pytest.mark.parametrize("model,n", SIZES)
+def test_sweeps_and_residual(model, n):
+    """One and two damped sweeps on the finest level (per-colour kernel below
+    32^2, the LDS-tiled kernel from 32^2 up) and the residual norm."""
+    cfg, rho, _, _ = case(model, n, seed=1)
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    sim.begin_step()
+    S = ora.build_source()
+    lev = ora.solver().levels[0]
+    g = ora.initial_guess()
+    r0 = ora.solver().resnorm(g, S, lev)
+    assert abs(sim.residual() - r0) < 1e-11 * r0
+    sim.smooth(0, 1)
+    gf.sweep(g, S, lev, cfg.w)
+    for c in range(g.shape[0]):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    sim.smooth(0, 2)
+    gf.sweep(g, S, lev, cfg.w)
+    gf.sweep(g, S, lev, cfg.w)
+    for c in range(g.shape[0]):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    r2 = ora.solver().resnorm(g, S, lev)
+    assert abs(sim.residual() - r2) < 1e-10 * r2
+
+
+@pytest.mark.parametrize("model,n", SIZES)
+def test_vcycles(model, n):
+    cfg, rho, _, _ = case(model, n, seed=2)
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    sim.begin_step()
+    S = ora.build_source()
+    sol = ora.solver()
+    g = ora.initial_guess()
+    for k in range(3):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(g.shape[0])]
+        assert max(errs) < 1e-11, (k, errs)
+    r = sol.resnorm(g, S, sol.levels[0])
+    assert abs(sim.residual() - r) < 1e-9 * r
+
+
+@pytest.mark.parametrize("model,n", [("pfc_gf", 32), ("pfc_gf", 64), ("cdft_gf", 32), ("cdft_gf", 128)])
+def test_steps(model, n):
+    """Steps with the device stop test (HIP graphs): same V-cycle counts, rho
+    and mu within 1e-10 of the oracle, F and mass agree, mass conserved."""
+    cfg, rho, _, _ = case(model, n, seed=3)
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    m0 = sim.mass()
+    for k in range(4):
+        st = sim.step(1)
+        c, r = ora.step()
+        assert abs(st.cycles_last - c) <= 1, (k, st.cycles_last, c)
+        assert st.residual_last <= cfg.tol
+        r_gpu, u_gpu, v_gpu = [np_(x) for x in sim.get_state()]
+        assert rel_err(r_gpu, ora.rho) < TOL_STEP, k
+        assert np.abs(u_gpu).max() == 0.0 and np.abs(v_gpu).max() == 0.0
+        mu, _ = sim.get_aux()
+        assert rel_err(np_(mu), ora.mu) < TOL_STEP, k
+        E = sim.energy()
+        assert E[1] == 0.0
+        assert abs(E[2] - ora.free_energy()) < 1e-10 * abs(ora.free_energy())
+    assert abs(sim.mass() - m0) < 1e-13 * abs(m0)
+    assert abs(sim.mass() - ora.mass()) < 1e-12 * ora.mass()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_mixed_precision_steps(model):
+    """FP32 smoothing inside FP64 defect correction reaches the same FP64
+    tolerance: the state agrees with the FP64 oracle to 1e-6."""
+    cfg, rho, _, _ = case(model, 128, seed=4, precision="mixed")
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    for k in range(3):
+        st = sim.step(1)
+        ora.step()
+        assert st.residual_last <= cfg.tol
+        assert rel_err(np_(sim.get_state()[0]), ora.rho) < TOL_MIXED, k
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_uniform_state_is_a_fixed_point(model):
+    cfg, rho, _, _ = case(model, 64)
+    rho = np.full_like(rho, rho.mean())
+    sim = sim_for(cfg, rho)
+    st = sim.step(2)
+    assert st.cycles_total == 0
+    assert np.abs(np_(sim.get_state()[0]) - rho).max() < 1e-14
+
+
+@pytest.mark.parametrize("model,n", [("pfc_gf", 512), ("cdft_gf", 1024)])
+def test_full_size_step(model, n):
+    """Benchmark sizes: the GPU's iterate solves the oracle's system to tol,
+    the end of the step is the oracle's rho^k + s Delta_h mu, and the
+    benchmarked step (graphs, device stop test) gives the same state and
+    cycle count as the stage-by-stage solve; F decreases, mass to round-off."""
+    cfg, rho, _, _ = case(model, n)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    S = ora.build_source()
+    lev = ora.solver().levels[0]
+    print(f"{model}: n={n}", flush=True)
+    sim = sim_for(cfg, rho)
+    sim.begin_step()
+    for c in range(S.shape[0]):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+    r = sim.residual()
+    cycles = 0
+    while r > cfg.tol and cycles < cfg.max_cycles:
+        sim.vcycle(1)
+        cycles += 1
+        r = sim.residual()
+    assert r <= cfg.tol
+    g = np.stack([np_(sim.read(0, 0, c)) for c in range(lev.ncomp)])
+    r_ora = np.sqrt(lev.h ** 2 * float(np.sum((S - gf.N(g, lev)) ** 2)))
+    assert r_ora <= cfg.tol and abs(r_ora - r) <= 1e-3 * r + 1e-13, (r_ora, r)
+    sim.finish_step()
+    staged = np_(sim.get_state()[0])
+    assert rel_err(staged, rho + cfg.s * grid.lap(g[1], cfg.h)) < 1e-12
+    sim.close()
+
+    sim = sim_for(cfg, rho)
+    F0, m0 = sim.energy()[2], sim.mass()
+    st = sim.step(1)
+    F1, m1 = sim.energy()[2], sim.mass()
+    print(f"{model}: cycles {st.cycles_last}, residual {st.residual_last:.3e}, F {F0:.9e} -> {F1:.9e}", flush=True)
+    assert st.cycles_last == cycles
+    assert rel_err(np_(sim.get_state()[0]), staged) <= 1e-12
+    assert F1 <= F0 + 1e-12 * abs(F0)
+    assert abs(m1 - m0) <= 1e-13 * abs(m0)
+    sim.close()

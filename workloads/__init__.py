@@ -15,6 +15,8 @@ ambiguous, the reading taken and its reason are stated with it:
   against the text).
 * Sheared-nanocrystal run: eps = 0.4, coexistence densities 0.72958 and 0.90073,
   h = pi / (2 sqrt 3), s = 0.02.
+* Gradient-flow variant (Thm. thm_grad; the paper runs no experiment with it):
+  the PFC and CDFT freezing runs' constants, grids and initial densities.
 """
 import math
 from dataclasses import dataclass, field, asdict
@@ -35,7 +37,7 @@ NANO_H = math.pi / (2.0 * math.sqrt(3.0))
 class Config:
     """Parameters of one instance (the C ABI's parameter block carries the same
     values)."""
-    model: str                 # "pfc" or "cdft"
+    model: str                 # "pfc", "cdft", or the gradient flow "pfc_gf", "cdft_gf"
     n: int
     h: float
     s: float
@@ -54,14 +56,25 @@ class Config:
     continuity_fix: bool = True
     precision: str = "fp64"    # "fp64" or "mixed"
 
+    @property
+    def gradflow(self):
+        return self.model.endswith("_gf")
+
+    @property
+    def base_model(self):
+        """"pfc" or "cdft": the free energy, whichever scheme."""
+        return self.model[:-3] if self.gradflow else self.model
+
     def oracle_kwargs(self):
         d = asdict(self)
         d.pop("precision")
         d.pop("n"); d.pop("h"); d.pop("s"); d.pop("model")
-        if self.model == "pfc":
+        if self.base_model == "pfc":
             d.pop("nu"); d.pop("delta")
         else:
             d.pop("alpha")
+        if self.gradflow:
+            d.pop("gamma"); d.pop("sigma")
         return d
 
 
@@ -79,6 +92,20 @@ def cdft_gauss_noise(n, h, s, seed, rho_bar=CDFT_RHO_BAR, amp=0.02, **kw):
     rho = rho_bar + amp * rng.standard_normal((n, n))
     z = np.zeros((n, n))
     return Config("cdft", n, h, s, **kw), rho, z.copy(), z.copy()
+
+
+def gradflow(model, n, seed=0, precision="fp64", **kw):
+    """Gradient-flow workload: "pfc_gf" draws rho as the PFC freezing run
+    (rho_bar + 0.05 U(-1, 1), h = 0.25, s = 0.01), "cdft_gf" as the CDFT run
+    (rho_bar + 0.02 N(0, 1), h = 17/128, s = 0.02); u = v = 0."""
+    if model == "pfc_gf":
+        cfg, rho, u, v = pfc_uniform_noise(n, 0.25, 0.01, seed, precision=precision, **kw)
+    elif model == "cdft_gf":
+        cfg, rho, u, v = cdft_gauss_noise(n, 17.0 / 128.0, 0.02, seed, precision=precision, **kw)
+    else:
+        raise ValueError(model)
+    cfg.model = model
+    return cfg, rho, u, v
 
 
 def random_velocity(n, seed, amp):
