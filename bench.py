@@ -21,7 +21,12 @@ Also reported on the same JSON line:
                 10-200 steps) through the continuous-batching server under a
                 device-memory budget: p50/p99 per-step latency, throughput;
   cdft          CDFT 1024^2 (h = 17/128, s = 0.02), 50 steps with the energy
-                and mass read after every step.
+                and mass read after every step;
+  gradflow      the gradient-flow variant of the scheme (Thm. thm_grad) with the
+                PFC free energy at 512^2 and the CDFT free energy at 1024^2 (the
+                freezing runs' constants and initial densities), FP64 and mixed:
+                steps/s, V-cycles per step, F and mass checks, and the roofline of
+                its finest-level smoother.
 """
 import argparse
 import dataclasses
@@ -40,6 +45,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one damped red-black sweep per fine node: read g (5),
 # f (5), rho^k, omega^k, write g (5), FP64
 SWEEP_BYTES_PFC = 17 * 8
+# the gradient flow: read g, f and write g with 3 (PFC) or 2 (CDFT) unknowns
+SWEEP_BYTES_GF = {"pfc_gf": 9 * 8, "cdft_gf": 6 * 8}
 KERNEL_SOURCES = ["paper_1503_07416_amd/csrc/tile.hpp", "paper_1503_07416_amd/csrc/stencil.hpp",
                   "paper_1503_07416_amd/csrc/kernels.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_pfc512_fp64_hbm_counters.md")
@@ -59,6 +66,7 @@ def parse():
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
+    ap.add_argument("--gradflow-only", action="store_true", help="only the gradient-flow workloads (for profiles)")
     ap.add_argument("--convergence", action="store_true",
                     help="the paper's convergence study instead of the benchmark (minutes of GPU time)")
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
@@ -95,7 +103,7 @@ def committed_traffic(shape):
     return float(t.group(1))
 
 
-def smoother_roofline(sim, n, launches=25):
+def smoother_roofline(sim, n, launches=25, sweep_bytes=SWEEP_BYTES_PFC, model="PFC"):
     """Average duration of one finest-level smoother launch (two damped
     red-black sweeps, as in the V-cycle's smoothing), measured with HIP
     events on the stream the library launches on."""
@@ -110,13 +118,13 @@ def smoother_roofline(sim, n, launches=25):
     stop.synchronize()
     ms = start.elapsed_time(stop)
     t_launch = ms * 1e-3 / launches
-    bytes_launch = 2 * SWEEP_BYTES_PFC * n * n
+    bytes_launch = 2 * sweep_bytes * n * n
     achieved = bytes_launch / t_launch / 1e9
     tx, ty, nt = sim.tile_shape(0)
-    traffic = committed_traffic(f"{tx}x{ty}x{nt}") if n == 512 else None
+    traffic = committed_traffic(f"{tx}x{ty}x{nt}") if (n == 512 and model == "PFC") else None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"k_sweeps_tile<PFC, double, 2 sweeps, {tx}x{ty} tile, {nt} threads>",
+            "kernel": f"k_sweeps_tile<{model}, double, 2 sweeps, {tx}x{ty} tile, {nt} threads>",
             "launch_us": round(t_launch * 1e6, 3), "bytes_per_launch": bytes_launch}
 
 
@@ -363,6 +371,53 @@ def run_cdft(steps=50, n=1024):
             "mass_rel_drift": max(abs(m - M[0]) for m in M) / abs(M[0])}
 
 
+def run_gradflow(steps=50, check_steps=10):
+    """The gradient-flow variant: PFC free energy at 512^2 and CDFT at 1024^2,
+    FP64 and mixed precision.  `steps` timed steps, then `check_steps` more
+    with F and the mass read after each (not timed)."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    out = {}
+    for model, n, kname in [("pfc_gf", 512, "GPFC"), ("cdft_gf", 1024, "GCDFT")]:
+        res = {}
+        for prec in ("fp64", "mixed"):
+            cfg, rho, _, _ = workloads.gradflow(model, n, 0, precision=prec)
+            sim = pkg.Simulation(cfg, device="cuda:0")
+            sim.set_state(rho)
+            sim.step(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            F = [sim.energy()[2]]
+            M = [sim.mass()]
+            for _ in range(check_steps):
+                sim.step(1)
+                F.append(sim.energy()[2])
+                M.append(sim.mass())
+            r = {"steps_per_s": round(steps / dt, 3), "ms_per_step": round(1e3 * dt / steps, 4),
+                 "vcycles_per_step": round(st.cycles_total / steps, 3), "final_residual": st.residual_last,
+                 "F_last": F[-1],
+                 "energy_increases": sum(1 for a, b in zip(F[:-1], F[1:]) if b > a + 1e-12 * abs(a)),
+                 "mass_rel_drift": max(abs(m - M[0]) for m in M) / abs(M[0])}
+            if prec == "fp64":
+                r["roofline"] = smoother_roofline(sim, n, sweep_bytes=SWEEP_BYTES_GF[model], model=kname)
+                ref = sim.get_state()[0]
+            else:
+                r["max_rel_diff_vs_fp64"] = rel_diff([sim.get_state()[0]], [ref])
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            res[prec] = r
+        h, s_ = (0.25, 0.01) if model == "pfc_gf" else (17.0 / 128.0, 0.02)
+        res["workload"] = (f"{model} {n}^2 h={h:g} s={s_:g} FAS V(2,2) tol 1e-10, {steps} timed steps "
+                           f"(+{check_steps} checked)")
+        out[model] = res
+    return out
+
+
 def run_convergence(sizes, tf):
     """The paper's convergence study (Sec. 6.1): smooth initial density on
     [0,32)^2, u = 0, refinement path s = 0.025 h^2 to t_f; CDFT with nu = 1 and
@@ -439,6 +494,9 @@ def main():
     if a.batched_only:
         print(json.dumps({"batched": run_batched()}))
         return
+    if a.gradflow_only:
+        print(json.dumps({"gradflow": run_gradflow()}))
+        return
     if a.mixed_only:
         import torch
         import workloads
@@ -492,6 +550,8 @@ def main():
         out["cdft"] = run_cdft()
         torch.cuda.empty_cache()
         out["serving"] = run_serving(a.serve_requests, a.serve_budget_gib)
+        torch.cuda.empty_cache()
+        out["gradflow"] = run_gradflow()
     print(json.dumps(out))
 
 
