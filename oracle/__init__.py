@@ -30,6 +30,8 @@ paper it follows (section, equation label, appendix).  Modules:
 ``gradflow``  the gradient-flow variant of the convex-splitting scheme
               (Thm. thm_grad, Eq. gradient_scheme): its rows, block smoother,
               FAS solver and stepper
+``walls``     the PFC step in a channel (Sec. 6, sheared-nanocrystal run): no-slip
+              moving walls and no-flux density in y, periodic in x
 
 Pins (see tests/test_oracle_*.py): Fourier symbols and summation by parts of
 the operators; two transcriptions of the scheme agree; FAS equals dense Newton;
@@ -40,5 +42,7 @@ FFT convolution equals the direct sum; the Cauchy errors the paper prints in
 its convergence tables (tests/golden/); for the gradient-flow variant the
 scheme written directly with dF_c, dF_e, dense Newton, the closed-form
 amplification of a Fourier mode, mass, the dissipation identity and energy
-decay for any s (tests/test_oracle_gradflow.py).
+decay for any s (tests/test_oracle_gradflow.py); for the channel dense Newton,
+the Couette steady state and start-up, mirror symmetry, energy decay with
+resting walls and the transfers on linear fields (tests/test_oracle_walls.py).
 """

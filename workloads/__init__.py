@@ -108,6 +108,28 @@ def gradflow(model, n, seed=0, precision="fp64", **kw):
     return cfg, rho, u, v
 
 
+def nucleate(n, h, eps=NANO_EPS, rho_s=NANO_RHO_S, rho_l=NANO_RHO_L, diag_atoms=13.0):
+    """The sheared-nanocrystal initial density (Sec. 6): the one-mode solid
+    rho_s + A (cos(sqrt3/2 x + pi) cos(y/2) - cos(y)/2) inside a regular
+    hexagon of long diagonal diag_atoms * a (a = 4 pi / sqrt 3, the solid's
+    period in x), centred at (L/2, L/2) with that diagonal along x, and the
+    uniform liquid rho_l outside; A is the one-mode amplitude the paper gives
+    for eps and rho_s.  Shape (n + 1, n): the node rows y = j h, j = 0..n, of
+    the channel (walls at j = 0 and j = n)."""
+    L = n * h
+    x = np.arange(n) * h
+    y = np.arange(n + 1) * h
+    X, Y = np.meshgrid(x, y)
+    dp = rho_s - 1.5
+    A = 4.0 / (5.0 * math.sqrt(3.0)) * dp - 4.0 * math.sqrt(3.0) / 15.0 * math.sqrt(15.0 * eps - 12.0 * dp * dp)
+    solid = rho_s + A * (np.cos(math.sqrt(3.0) / 2.0 * X + math.pi) * np.cos(0.5 * Y) - 0.5 * np.cos(Y))
+    a = 4.0 * math.pi / math.sqrt(3.0)
+    R = 0.5 * diag_atoms * a
+    dx, dy = np.abs(X - L / 2), np.abs(Y - L / 2)
+    inside = (dy <= math.sqrt(3.0) / 2.0 * R) & (math.sqrt(3.0) * dx + dy <= math.sqrt(3.0) * R)
+    return np.where(inside, solid, rho_l)
+
+
 def random_velocity(n, seed, amp):
     rng = np.random.default_rng(seed)
     return amp * rng.uniform(-1.0, 1.0, (n, n)), amp * rng.uniform(-1.0, 1.0, (n, n))
