@@ -33,11 +33,21 @@
  * the nonlinearity linearised about the current iterate, damping w, the
  * CDFT positivity projection.  The state is rho alone (u = v = 0).
  *
+ * The PFC step also runs in a channel (hfz_params.walls = 1; Sec. 6, the
+ * sheared-nanocrystal run): periodic in x, walls in y at the node rows j = 0
+ * and j = n, which hold the boundary values: no-slip moving walls u =
+ * u_wall_bottom / u_wall_top, v = 0, and no flux for the density, rho on a
+ * wall row equal to the adjacent interior row (likewise mu and kappa, and
+ * rho^k).  The unknowns are on the interior rows 1..n-1; fields then have
+ * (n + 1) * n values, rows 0..n.  The smoother refreshes the wall rows after
+ * every half sweep; the multigrid levels are nested vertex grids whose wall
+ * rows follow the same rules; norm, energy and mass sum the interior rows.
+ *
  * Conventions for every entry point
  *  - Return value: HFZ_OK (0) or a negative HFZ_E* code; no exception or
  *    abort crosses the ABI.  hfz_strerror() names a code.
- *  - Fields are FP64, n*n values, row-major [j][i] with x (index i) fastest,
- *    node (i, j) at (i h, j h).
+ *  - Fields are FP64, n*n values (a channel: (n + 1) * n, rows j = 0..n),
+ *    row-major [j][i] with x (index i) fastest, node (i, j) at (i h, j h).
  *  - Device pointers are plain HIP device addresses on the device current
  *    when hfz_init ran.  The caller owns all device memory: the workspace
  *    (hfz_workspace_bytes) and the state buffers.  The library never
@@ -97,6 +107,9 @@ typedef struct hfz_params {
   int sigma;          /* +1: -rho omega x u in vector form (default); -1: App. G sign (hydrodynamic only) */
   int continuity_fix; /* 1: recompute rho^{k+1} from the continuity row after the solve
                          (gradient flow: rho^{k+1} = rho^k + s Delta_h mu^{k+1}) */
+  int walls;          /* 0: periodic; 1: a channel, walls at y = 0 and y = n h (HFZ_PFC, FP64,
+                         nu1 >= 1 and nu2 >= 1 only; HFZ_EINVAL otherwise) */
+  double u_wall_bottom, u_wall_top; /* channel: u on the walls (v = 0 there) */
 } hfz_params;
 
 typedef struct hfz_stats {

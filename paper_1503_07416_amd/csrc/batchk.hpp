@@ -169,17 +169,26 @@ __global__ void k_begin_b(const Lvl<double>* L0s, const StateB* Ss, const Phys<d
   const Lvl<double> L = lvl_global(L0s[z]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= L.n || j >= L.n) return;
+  if (i >= L.n || j >= L.ny) return;
   const StateB S = Ss[z];
   double* u = as_global(S.u);
   double* v = as_global(S.v);
-  source_node<MODEL>(L.rk, u, v, MODEL == CDFT ? as_global(S.jrho) : nullptr, L.om, L.f[0], L.f[1], L.f[2],
-                     MODEL == PFC ? L.f[3] : nullptr, MODEL == PFC ? L.f[4] : nullptr, i, j, L.n, L.lg, L.h, Ps[z]);
   const int p = (j << L.lg) + i;
+  constexpr bool PF = algebra(MODEL) == PFC;
+  if (walls(MODEL) && (j == 0 || j == L.n)) {
+    // channel wall rows: no equation (S = 0, omega^k = 0); the iterate keeps
+    // the state's boundary values
+#pragma unroll
+    for (int c = 0; c < NC<MODEL>::value; ++c) L.f[c][p] = 0.0;
+    L.om[p] = 0.0;
+  } else {
+    source_node<MODEL>(L.rk, u, v, algebra(MODEL) == CDFT ? as_global(S.jrho) : nullptr, L.om, L.f[0], L.f[1],
+                       L.f[2], PF ? L.f[3] : nullptr, PF ? L.f[4] : nullptr, i, j, L.n, L.lg, L.h, Ps[z]);
+  }
   L.g[0][p] = L.rk[p];
   L.g[1][p] = u[p];
   L.g[2][p] = v[p];
-  if constexpr (MODEL == PFC) {
+  if constexpr (PF) {
     L.g[3][p] = as_global(S.mu)[p];
     L.g[4][p] = as_global(S.ka)[p];
   }
@@ -191,7 +200,10 @@ __global__ void k_begin_b(const Lvl<double>* L0s, const StateB* Ss, const Phys<d
 }
 
 // rho^k, omega^k of every instance onto its next coarser level (and their FP32
-// copies in mixed precision, Es non-null).
+// copies in mixed precision, Es non-null).  WL: a channel, whose coarse wall
+// rows take rho^k of the adjacent interior row (no flux) and omega^k = 0;
+// the interior rows' footprints lie on fine interior rows.
+template <bool WL = false>
 __global__ void k_restrict_coef_b(const Lvl<double>* Fs, const Lvl<double>* Cs, const int* on,
                                   const Lvl<float>* Es) {
   const int z = blockIdx.z;
@@ -200,10 +212,12 @@ __global__ void k_restrict_coef_b(const Lvl<double>* Fs, const Lvl<double>* Cs, 
   const Lvl<double> C = lvl_global(Cs[z]);
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  if (I >= C.n || J >= C.n) return;
+  if (I >= C.n || J >= C.ny) return;
   const int pc = (J << C.lg) + I;
-  const double r = fw9(F.rk, 2 * I, 2 * J, F.n, F.lg);
-  const double o = fw9(F.om, 2 * I, 2 * J, F.n, F.lg);
+  const bool wall = WL && (J == 0 || J == C.n);
+  const int Jr = !wall ? J : (J == 0 ? 1 : C.n - 1);
+  const double r = fw9(F.rk, 2 * I, 2 * Jr, F.n, F.lg);
+  const double o = wall ? 0.0 : fw9(F.om, 2 * I, 2 * J, F.n, F.lg);
   C.rk[pc] = r;
   C.om[pc] = o;
   if (Es) {
@@ -214,16 +228,20 @@ __global__ void k_restrict_coef_b(const Lvl<double>* Fs, const Lvl<double>* Cs, 
 }
 
 // End of a step, first half: rho^{k+1} from the continuity row into g[0]
-// (the single-instance k_continuity arithmetic).
+// (the single-instance k_continuity arithmetic).  WL: a channel; a wall row
+// takes the value of its adjacent interior row (each thread reads only rk,
+// f and the velocity, so the copy needs no second pass).
+template <bool WL = false>
 __global__ void k_continuity_b(const Lvl<double>* L0s, const Phys<double>* Ps, const int* on) {
   const int z = blockIdx.z;
   if (!on[z]) return;
   const Lvl<double> L = lvl_global(L0s[z]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= L.n || j >= L.n) return;
-  const Nbr q = nbr(i, j, L.n, L.lg);
-  L.g[0][q.p] = continuity_node(L.f[0], L.rk, L.g[1], L.g[2], q, L.h, Ps[z].s);
+  if (i >= L.n || j >= L.ny) return;
+  const int jr = !WL ? j : (j == 0 ? 1 : (j == L.n ? L.n - 1 : j));
+  const Nbr q = WL ? nbr_of<WPFC>(i, jr, L.n, L.lg) : nbr(i, j, L.n, L.lg);
+  L.g[0][(j << L.lg) + i] = continuity_node(L.f[0], L.rk, L.g[1], L.g[2], q, L.h, Ps[z].s);
 }
 
 // End of a step, second half: state <- g.
@@ -232,12 +250,12 @@ template <int MODEL> __global__ void k_state_b(const Lvl<double>* L0s, const Sta
   if (!on[z]) return;
   const Lvl<double> L = lvl_global(L0s[z]);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L.n * L.n) return;
+  if (t >= L.n * L.ny) return;
   const StateB S = Ss[z];
   L.rk[t] = L.g[0][t];
   as_global(S.u)[t] = L.g[1][t];
   as_global(S.v)[t] = L.g[2][t];
-  if constexpr (MODEL == PFC) {
+  if constexpr (algebra(MODEL) == PFC) {
     as_global(S.mu)[t] = L.g[3][t];
     as_global(S.ka)[t] = L.g[4][t];
   }

@@ -53,13 +53,17 @@ template <typename T> Fld<T> fld(T* const* p) {
 // Damped red-black sweeps with the per-colour kernels (full form).
 template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, int sweeps) {
   const Lvl<T>& L = H.L[l];
-  const dim3 b = block2(L.n / 2, L.n), g = grid2(L.n / 2, L.n, b);
+  const dim3 b = block2(L.n / 2, L.ny), g = grid2(L.n / 2, L.ny, b);
   for (int k = 0; k < sweeps; ++k) {
     for (int colour = 0; colour < 2; ++colour) {
       if (l == 0)
         k_smooth_colour<MODEL, T, 1><<<g, b, 0, K.stream>>>(L, H.P, colour);
       else
         k_smooth_colour<MODEL, T, 0><<<g, b, 0, K.stream>>>(L, H.P, colour);
+      if constexpr (walls(MODEL)) {
+        const dim3 bw = block2(L.n, 1);
+        k_wall_rows<T><<<grid2(L.n, 1, bw), bw, 0, K.stream>>>(L, K.halt);
+      }
     }
   }
 }
@@ -70,9 +74,10 @@ template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, 
 // 16^2 and below always fit.
 template <int MODEL, typename T, bool CORR> bool tail_plan(int top_n, int nt, size_t lds_max, int* d_from) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
-  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB, NR>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
+  constexpr int WR = walls(MODEL) ? 1 : 0;
+  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB, NR, WR>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
   int df = nt;
-  while (df > 0 && tail_lds_count<NCm, NB, NR>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
+  while (df > 0 && tail_lds_count<NCm, NB, NR, WR>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
   if (d_from) *d_from = df;
   return true;
 }
@@ -87,7 +92,7 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
   tail_plan<MODEL, T, CORR>(A.top_n, A.nt, H.tail_lds_max, &A.d_from);
-  const size_t sh = tail_lds_count<NCm, NB, NR>(A.top_n, A.nt, A.d_from) * sizeof(T);
+  const size_t sh = tail_lds_count<NCm, NB, NR, walls(MODEL) ? 1 : 0>(A.top_n, A.nt, A.d_from) * sizeof(T);
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 
@@ -112,6 +117,7 @@ int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, c
 template <int MODEL, typename T, bool CORR>
 void restrict_launch(Hier<T>& H, Cycle& K, const Lvl<T>& F, const Lvl<T>& C, int rs) {
   if (rs < 0 || rs >= NUM_RESTRICT_SHAPES || C.n % kRestrictTile[rs] != 0) rs = 0;
+  if constexpr (walls(MODEL)) rs = 0;  // the channel's wall rows are handled by the direct kernel
   const int rt = kRestrictTile[rs];
   const dim3 grid(C.n / rt, C.n / rt);
   if (rs == 1)
@@ -196,7 +202,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
   Lvl<T> F = L;  // descriptor of the buffer holding the iterate
   for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
   if (K.nu1 == 0) {
-    if constexpr (!CORR) {
+    if constexpr (!CORR && !walls(MODEL)) {
       const dim3 b = block2(F.n, F.n);
       k_residual_field<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.P);
     }
@@ -210,12 +216,12 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
     const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
     if (norm) K.norm_partials = blocks;
   } else {
-    if constexpr (!CORR) {
+    if constexpr (!CORR && !walls(MODEL)) {
       const dim3 b = block2(F.n, F.n);
       k_prolong<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, C, H.P);
     }
   }
-  if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.n);
+  if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.ny);
 }
 
 template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l) {
@@ -228,7 +234,9 @@ template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K
     vcycle_tiled<MODEL, T, CORR>(H, K, l);
     return;
   }
-  if constexpr (!CORR) {
+  // (a channel always runs the tiled kernels and the tail: its hierarchy is
+  // built so, and the plain per-level path below is periodic)
+  if constexpr (!CORR && !walls(MODEL)) {
     if (l == last) {
       smooth_level<MODEL, T>(H, K, l, K.coarse_sweeps);
       return;

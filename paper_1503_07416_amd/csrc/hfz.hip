@@ -37,15 +37,21 @@ int ilog2(int x) {
   return l;
 }
 
-// Calls f with the model as a compile-time constant (std::integral_constant).
-template <class F> auto by_model(int model, F&& f) {
-  switch (model) {
-    case HFZ_PFC:
+// The kernels' model: the ABI model, or WPFC for the PFC step in a channel.
+int kernel_model(const hfz_params& p) { return p.walls ? WPFC : p.model; }
+
+// Calls f with the kernels' model (kernel_model) as a compile-time constant
+// (std::integral_constant).
+template <class F> auto by_model(int km, F&& f) {
+  switch (km) {
+    case PFC:
       return f(std::integral_constant<int, PFC>());
-    case HFZ_CDFT:
+    case CDFT:
       return f(std::integral_constant<int, CDFT>());
-    case HFZ_PFC_GF:
+    case GPFC:
       return f(std::integral_constant<int, GPFC>());
+    case WPFC:
+      return f(std::integral_constant<int, WPFC>());
     default:
       return f(std::integral_constant<int, GCDFT>());
   }
@@ -72,6 +78,10 @@ int validate(const hfz_params* p) {
   if (p->precision != HFZ_FP64 && p->precision != HFZ_MIXED) return HFZ_EINVAL;
   if (model_cdft(p->model) && (!(p->nu > 0) || !(p->delta >= 0))) return HFZ_EINVAL;
   if (!model_cdft(p->model) && !std::isfinite(p->alpha)) return HFZ_EINVAL;
+  if (p->walls != 0 && p->walls != 1) return HFZ_EINVAL;
+  if (p->walls && (p->model != HFZ_PFC || p->precision != HFZ_FP64 || p->nu1 < 1 || p->nu2 < 1 ||
+                   !std::isfinite(p->u_wall_bottom) || !std::isfinite(p->u_wall_top)))
+    return HFZ_EINVAL;
   return HFZ_OK;
 }
 
@@ -101,6 +111,7 @@ Dims dims2(int nx, int ny) {
 
 struct hfz_handle {
   hfz_params p{};
+  int km = 0;  // the kernels' model (kernel_model)
   hipStream_t stream = nullptr;
   int nlev = 0;
   int nc = 0;
@@ -144,13 +155,15 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
   Carver c{static_cast<char*>(ws)};
   const int nc = model_nc(p.model);
   const int n = p.n;
-  const size_t N2 = (size_t)n * n;
+  const int wr = p.walls ? 1 : 0;  // a channel's levels hold the wall rows too
+  const size_t N2 = (size_t)n * (n + wr);
   std::vector<Lvl<double>> L;
   for (int m = n; m >= p.coarsest_n; m >>= 1) {
     Lvl<double> l{};
     l.n = m;
+    l.ny = m + wr;
     l.lg = ilog2(m);
-    const size_t cnt = (size_t)m * m;
+    const size_t cnt = (size_t)m * (m + wr);
     for (int k = 0; k < nc; ++k) l.g[k] = c.take<double>(cnt);
     for (int k = 0; k < nc; ++k) l.f[k] = c.take<double>(cnt);
     if (m != n)
@@ -219,8 +232,9 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
     for (int m = n; m >= p.coarsest_n; m >>= 1) {
       Lvl<float> l{};
       l.n = m;
+      l.ny = m + wr;
       l.lg = ilog2(m);
-      const size_t cnt = (size_t)m * m;
+      const size_t cnt = (size_t)m * (m + wr);
       for (int k = 0; k < nc; ++k) l.g[k] = c.take<float>(cnt);
       for (int k = 0; k < nc; ++k) l.f[k] = c.take<float>(cnt);
       for (int k = 0; k < nc; ++k) l.g0[k] = c.take<float>(cnt);
@@ -308,13 +322,13 @@ void reduce_launch(hfz_handle* hd, int count, bool stop, bool counted = true) {
 
 template <int MODEL> void residual_launch_t(hfz_handle* hd, bool stop, bool counted) {
   const Lvl<double>& L = hd->H.L[0];
-  const Dims d = dims2(L.n, L.n);
+  const Dims d = dims2(L.n, L.ny);
   k_residual_partial<MODEL, double><<<d.grid, d.block, 0, hd->stream>>>(L, hd->H.P, hd->partial);
   reduce_launch(hd, (int)(d.grid.x * d.grid.y), stop, counted);
 }
 
 void residual_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
-  by_model(hd->p.model, [&](auto m) { residual_launch_t<decltype(m)::value>(hd, stop, counted); });
+  by_model(hd->km, [&](auto m) { residual_launch_t<decltype(m)::value>(hd, stop, counted); });
 }
 
 int residual_read(hfz_handle* hd, double* norm) {
@@ -332,7 +346,7 @@ int residual(hfz_handle* hd, double* norm) {
 
 void vcycle(hfz_handle* hd) {
   Cycle K = cycle_ctx(hd);
-  by_model(hd->p.model, [&](auto m) { hfz::vcycle<decltype(m)::value, double, false>(hd->H, K); });
+  by_model(hd->km, [&](auto m) { hfz::vcycle<decltype(m)::value, double, false>(hd->H, K); });
   hd->norm_partials = K.norm_partials;
 }
 
@@ -389,7 +403,7 @@ int cycle_and_residual(hfz_handle* hd, double* norm) {
 void mp_prepare_launch(hfz_handle* hd, bool stop = false, bool counted = true) {
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
-  by_model(hd->p.model, [&](auto m) {
+  by_model(hd->km, [&](auto m) {
     k_mp_prepare<decltype(m)::value><<<g, b, 0, hd->stream>>>(L, hd->H.P, hd->H32.L[0], hd->partial);
   });
   reduce_launch(hd, (int)(g.x * g.y), stop, counted);
@@ -403,7 +417,7 @@ void mp_cycle(hfz_handle* hd, bool stop) {
   Cycle K = cycle_ctx(hd);
   const Lvl<double>& L = hd->H.L[0];
   const dim3 b = block2(L.n, L.n), g = grid2(L.n, L.n, b);
-  by_model(hd->p.model, [&](auto m) {
+  by_model(hd->km, [&](auto m) {
     constexpr int M = decltype(m)::value;
     for (int i = 0; i < hd->mp_inner; ++i) hfz::vcycle<M, float, true>(hd->H32, K);
     k_mp_update<M><<<g, b, 0, hd->stream>>>(L, hd->H32.L[0], hd->ctl);
@@ -579,19 +593,19 @@ template <int MODEL> int begin_step_t(hfz_handle* hd) {
   }
   const bool mixed = hd->p.precision == HFZ_MIXED;
   for (int l = 0; l < hd->nlev; ++l) {
-    const int n = hd->H.L[l].n;
-    const dim3 b = block2(n, n), g = grid2(n, n, b);
+    const int n = hd->H.L[l].n, ny = hd->H.L[l].ny;
+    const dim3 b = block2(n, ny), g = grid2(n, ny, b);
     const Lvl<float>* E = mixed ? hd->H32.desc + l : nullptr;
     if (l == 0)
       k_begin_b<MODEL><<<g, b, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->phys1, hd->on1, E);
     else
-      k_restrict_coef_b<<<g, b, 0, hd->stream>>>(hd->H.desc + (l - 1), hd->H.desc + l, hd->on1, E);
+      k_restrict_coef_b<walls(MODEL)><<<g, b, 0, hd->stream>>>(hd->H.desc + (l - 1), hd->H.desc + l, hd->on1, E);
   }
   return last_error();
 }
 
 int begin_step(hfz_handle* hd) {
-  return by_model(hd->p.model, [&](auto m) { return begin_step_t<decltype(m)::value>(hd); });
+  return by_model(hd->km, [&](auto m) { return begin_step_t<decltype(m)::value>(hd); });
 }
 
 // End of a step: continuity update, state <- g, the next CDFT convolution.
@@ -608,6 +622,13 @@ int finish_step(hfz_handle* hd) {
     }
     return last_error();
   }
+  if (hd->km == WPFC) {
+    const dim3 bw = block2(n, n + 1), gw = grid2(n, n + 1, bw);
+    if (hd->p.continuity_fix) k_continuity_b<true><<<gw, bw, 0, hd->stream>>>(hd->H.desc, hd->phys1, hd->on1);
+    const dim3 gs((unsigned)(((size_t)n * (n + 1) + 255) / 256));
+    k_state_b<WPFC><<<gs, 256, 0, hd->stream>>>(hd->H.desc, hd->state1, hd->on1);
+    return last_error();
+  }
   if (hd->p.continuity_fix) k_continuity_b<<<g, b, 0, hd->stream>>>(hd->H.desc, hd->phys1, hd->on1);
   const dim3 gs((unsigned)(((size_t)n * n + 255) / 256));
   if (hd->p.model == HFZ_PFC) {
@@ -622,9 +643,12 @@ int finish_step(hfz_handle* hd) {
 int energy_impl(hfz_handle* hd, double* out4) {
   const int n = hd->p.n;
   const Lvl<double>& L0 = hd->H.L[0];
-  const Dims d = dims2(n, n);
+  const Dims d = dims2(n, L0.ny);
   const int nb = d.grid.x * d.grid.y;
-  if (!model_cdft(hd->p.model))
+  if (hd->km == WPFC)
+    k_energy_partial<WPFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, n, L0.lg, L0.h,
+                                                              hd->p.alpha, hd->partial);
+  else if (!model_cdft(hd->p.model))
     k_energy_partial<PFC><<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->u, hd->v, nullptr, n, L0.lg, L0.h,
                                                              hd->p.alpha, hd->partial);
   else
@@ -702,6 +726,7 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hfz_handle* hd = new (std::nothrow) hfz_handle();
   if (!hd) return HFZ_ENOMEM;
   hd->p = *p;
+  hd->km = kernel_model(*p);
   hd->stream = static_cast<hipStream_t>(hip_stream);
   layout(*p, dev_ws, hd);
   bool ok = hipMemcpyAsync(hd->H.desc, hd->H.L.data(), hd->H.L.size() * sizeof(Lvl<double>),
@@ -720,6 +745,8 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->H.P.delta = p->delta;
   hd->H.P.w = p->w_damp;
   hd->H.P.ce = 0.0;
+  hd->H.P.ub = p->u_wall_bottom;
+  hd->H.P.ut = p->u_wall_top;
   hd->H32.P.s = (float)p->s;
   hd->H32.P.gamma = (float)p->gamma;
   hd->H32.P.sigma = (float)p->sigma;
@@ -727,11 +754,13 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   hd->H32.P.delta = (float)p->delta;
   hd->H32.P.w = (float)p->w_damp;
   hd->H32.P.ce = 0.0f;
+  hd->H32.P.ub = (float)p->u_wall_bottom;
+  hd->H32.P.ut = (float)p->u_wall_top;
   hd->H.P.halt = hd->ctl;
   hd->H32.P.halt = hd->ctl;
   k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
   // opt in to the large LDS of a gfx950 CU for the tail kernels
-  by_model(p->model, [&](auto m) {
+  by_model(hd->km, [&](auto m) {
     constexpr int M = decltype(m)::value;
     hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, double, false>));
     hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, float, true>));
@@ -742,15 +771,16 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   }
   if (const char* e = std::getenv("HFZ_GRAPH")) hd->use_graph = std::atoi(e) != 0;
   if (const char* e = std::getenv("HFZ_TILES")) hd->use_tiles = std::atoi(e) != 0;
-  if (p->precision == HFZ_MIXED) {
-    // the correction-form inner solve runs only on the tiled and tail kernels:
-    // every level above the tail must be tileable (>= 32 with a >= 16 coarse)
+  if (p->precision == HFZ_MIXED || p->walls) {
+    // the correction-form inner solve, and a channel, run only on the tiled
+    // and tail kernels: every level above the tail must be tileable (>= 32
+    // with a >= 16 coarse)
     hd->use_tiles = true;
     if (hd->tail_n < 16) hd->tail_n = 32;
   }
   if (hd->use_tiles) {
     const Cycle K = cycle_ctx(hd);
-    by_model(p->model, [&](auto m) {
+    by_model(hd->km, [&](auto m) {
       constexpr int M = decltype(m)::value;
       tune_tile_shapes<M, double, false>(hd->H, K);
       if (p->precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K);
@@ -797,7 +827,7 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
   const bool gf = model_gf(hd->p.model);
   if (!gf && (!u || !v)) return HFZ_EINVAL;
   const int n = hd->p.n;
-  const size_t N2 = (size_t)n * n;
+  const size_t N2 = (size_t)n * hd->H.L[0].ny;
   Lvl<double>& L0 = hd->H.L[0];
   if (model_cdft(hd->p.model)) {
     k_min_partial<<<256, 256, 0, hd->stream>>>(rho, N2, hd->partial);
@@ -818,7 +848,13 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
     copy_dev(hd, v, hd->v, N2);
   }
   const Dims d = dims2(n, n);
-  if (!model_cdft(hd->p.model)) {
+  if (hd->km == WPFC) {
+    const Dims dw = dims2(n, n + 1);
+    k_wall_state<<<(n + 63) / 64, 64, 0, hd->stream>>>(L0.rk, hd->u, hd->v, n, L0.lg, hd->p.u_wall_bottom,
+                                                       hd->p.u_wall_top);
+    k_pfc_kappa<true><<<dw.grid, dw.block, 0, hd->stream>>>(L0.rk, hd->ka, n, L0.lg, L0.h);
+    k_pfc_mu<true><<<dw.grid, dw.block, 0, hd->stream>>>(L0.rk, hd->ka, hd->mu, n, L0.lg, L0.h, hd->p.alpha);
+  } else if (!model_cdft(hd->p.model)) {
     k_pfc_kappa<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, n, L0.lg, L0.h);
     k_pfc_mu<<<d.grid, d.block, 0, hd->stream>>>(L0.rk, hd->ka, hd->mu, n, L0.lg, L0.h, hd->p.alpha);
   } else {
@@ -834,7 +870,7 @@ int hfz_get_state(hfz_handle* hd, double* rho, double* u, double* v) {
   if (!hd || !rho) return HFZ_EINVAL;
   if (!model_gf(hd->p.model) && (!u || !v)) return HFZ_EINVAL;
   if (!hd->has_state) return HFZ_ESTATE;
-  const size_t N2 = (size_t)hd->p.n * hd->p.n;
+  const size_t N2 = (size_t)hd->p.n * hd->H.L[0].ny;
   copy_dev(hd, hd->H.L[0].rk, rho, N2);
   if (u) copy_dev(hd, hd->u, u, N2);
   if (v) copy_dev(hd, hd->v, v, N2);
@@ -847,7 +883,7 @@ int hfz_get_aux(hfz_handle* hd, double* mu, double* kappa) {
   const bool has_kappa = hd->ka != nullptr;
   if (has_kappa && !kappa) return HFZ_EINVAL;
   if (!hd->has_state) return HFZ_ESTATE;
-  const size_t N2 = (size_t)hd->p.n * hd->p.n;
+  const size_t N2 = (size_t)hd->p.n * hd->H.L[0].ny;
   copy_dev(hd, hd->mu, mu, N2);
   if (has_kappa) copy_dev(hd, hd->ka, kappa, N2);
   HIPCHK(hipStreamSynchronize(hd->stream));
@@ -868,12 +904,12 @@ int hfz_smooth(hfz_handle* hd, int level, int sweeps) {
     const Lvl<double>& L = hd->H.L[level];
     const Fld<double> home = fld<double>(L.g);
     Fld<double> cur = home, other = fld<double>(L.gb);
-    by_model(hd->p.model, [&](auto m) {
+    by_model(hd->km, [&](auto m) {
       tiled_sweeps<decltype(m)::value, double, false>(hd->H, K, level, sweeps, false, cur, other);
     });
-    if (cur.c[0] != home.c[0]) copy_fields<double>(K, cur, home, hd->nc, (size_t)L.n * L.n);
+    if (cur.c[0] != home.c[0]) copy_fields<double>(K, cur, home, hd->nc, (size_t)L.n * L.ny);
   } else {
-    by_model(hd->p.model, [&](auto m) { smooth_level<decltype(m)::value, double>(hd->H, K, level, sweeps); });
+    by_model(hd->km, [&](auto m) { smooth_level<decltype(m)::value, double>(hd->H, K, level, sweeps); });
   }
   return last_error();
 }
@@ -951,7 +987,7 @@ int hfz_read_field(hfz_handle* hd, int which, int level, int comp, double* dst) 
   if (!hd || !dst) return HFZ_EINVAL;
   double* src = field_ptr(hd, which, level, comp);
   if (!src) return HFZ_EINVAL;
-  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].n;
+  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].ny;
   copy_dev(hd, src, dst, cnt);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
@@ -961,7 +997,7 @@ int hfz_write_field(hfz_handle* hd, int which, int level, int comp, const double
   if (!hd || !src) return HFZ_EINVAL;
   double* dst = field_ptr(hd, which, level, comp);
   if (!dst) return HFZ_EINVAL;
-  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].n;
+  const size_t cnt = (size_t)hd->H.L[level].n * hd->H.L[level].ny;
   copy_dev(hd, src, dst, cnt);
   HIPCHK(hipStreamSynchronize(hd->stream));
   return last_error();
@@ -1279,7 +1315,8 @@ int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes
   for (int i = 0; i < count; ++i) {
     const int rc = validate(&params[i]);
     if (rc != HFZ_OK) return rc;
-    if (model_gf(params[i].model)) return HFZ_EINVAL;  // the batched solve covers the hydrodynamic models
+    // the batched solve covers the periodic hydrodynamic models
+    if (model_gf(params[i].model) || params[i].walls) return HFZ_EINVAL;
     if (!batch_compatible(params[0], params[i])) return HFZ_EINVAL;
   }
   if (params[0].nu1 < 1 || params[0].nu2 < 1) return HFZ_EINVAL;

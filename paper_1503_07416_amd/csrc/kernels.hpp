@@ -19,7 +19,7 @@ __device__ __forceinline__ void source_node(const double* __restrict__ rho, cons
                                             double* __restrict__ om, double* S0, double* S1, double* S2,
                                             double* S3, double* S4, int i, int j, int n, int lg, double h,
                                             const Phys<double>& P) {
-  const Nbr q = nbr(i, j, n, lg);
+  const Nbr q = nbr_of<MODEL>(i, j, n, lg);
   const double s = P.s, c4 = s / (4.0 * h), c2 = s / (2.0 * h), ih2 = 1.0 / (h * h);
   const double r = rho[q.p], uP = u[q.p], vP = v[q.p];
   const double w2 = 1.0 / (2.0 * h);
@@ -31,7 +31,7 @@ __device__ __forceinline__ void source_node(const double* __restrict__ rho, cons
   const double b = 0.5 * s * P.sigma * r * o;
   double s2 = r * uP + b * vP + 0.5 * s * P.gamma * lapu;
   double s3 = r * vP - b * uP + 0.5 * s * P.gamma * lapv;
-  if constexpr (MODEL == CDFT) {
+  if constexpr (algebra(MODEL) == CDFT) {
     const double tc = 2.0 * P.ce;
     const double EE = jrho[q.e] + tc * rho[q.e], EW = jrho[q.w] + tc * rho[q.w];
     const double EN = jrho[q.n] + tc * rho[q.n], ES = jrho[q.s] + tc * rho[q.s];
@@ -40,7 +40,7 @@ __device__ __forceinline__ void source_node(const double* __restrict__ rho, cons
   }
   S1[q.p] = s2;
   S2[q.p] = s3;
-  if constexpr (MODEL == PFC) {
+  if constexpr (algebra(MODEL) == PFC) {
     S3[q.p] = 2.0 * (rho[q.e] + rho[q.w] + rho[q.n] + rho[q.s] - 4.0 * r) * ih2;
     S4[q.p] = 0.0;
   }
@@ -93,9 +93,10 @@ __global__ void k_smooth_colour(Lvl<T> L, Phys<T> P, int colour) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int n = L.n;
-  if (t >= (n >> 1) || j >= n) return;
+  if (t >= (n >> 1) || j >= L.ny) return;
+  if (walls(MODEL) && (j == 0 || j == n)) return;  // the wall rows are boundary values
   const int i = 2 * t + ((j + colour) & 1);
-  const Nbr q = nbr(i, j, n, L.lg);
+  const Nbr q = nbr_of<MODEL>(i, j, n, L.lg);
   T out[NC<MODEL>::value];
   block_update<MODEL, T>(L.g, L.f, L.rk, L.om, q, q.p, L.k, P, out);
 #pragma unroll
@@ -250,9 +251,9 @@ __global__ void k_residual_partial(Lvl<T> L, Phys<T> P, double* __restrict__ par
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   double acc = 0.0;
-  if (i < L.n && j < L.n) {
+  if (i < L.n && j < L.ny && !(walls(MODEL) && (j == 0 || j == L.n))) {
     constexpr int NCm = NC<MODEL>::value;
-    const Nbr q = nbr(i, j, L.n, L.lg);
+    const Nbr q = nbr_of<MODEL>(i, j, L.n, L.lg);
     T nv[NCm];
     rows_N<MODEL, T>(L.g, L.rk, L.om, q, q.p, L.k, P, nv);
 #pragma unroll
@@ -299,6 +300,22 @@ __global__ void k_reduce_stop(const double* __restrict__ partial, int count, dou
       ctl[0] = 1;
     else if (!isfinite(nrm))
       ctl[0] = 2;
+  }
+}
+
+// Channel wall rows of an iterate: rho, mu, kappa copy the adjacent interior
+// row (u, v on the walls are fixed and stay as they are).  One thread per
+// column.
+template <typename T> __global__ void k_wall_rows(Lvl<T> L, const int* halt) {
+  if (halted(halt)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  const int top = L.n << L.lg, stride = 1 << L.lg;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    if (!wall_copied(c) || L.g[c] == nullptr) continue;
+    L.g[c][i] = L.g[c][stride + i];
+    L.g[c][top + i] = L.g[c][top - stride + i];
   }
 }
 
@@ -400,8 +417,9 @@ __global__ void k_energy_partial(const double* __restrict__ rho, const double* _
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   double ke = 0.0, f1 = 0.0, f2 = 0.0, ms = 0.0;
-  if (i < n && j < n) {
-    const Nbr q = nbr(i, j, n, lg);
+  // a channel sums its interior rows 1..n-1 (the grid then has n + 1 rows)
+  if (i < n && j < n + (walls(MODEL) ? 1 : 0) && !(walls(MODEL) && (j == 0 || j == n))) {
+    const Nbr q = nbr_of<MODEL>(i, j, n, lg);
     const double r = rho[q.p];
     ke = 0.5 * r * (u[q.p] * u[q.p] + v[q.p] * v[q.p]);
     ms = r;
@@ -444,24 +462,44 @@ __global__ void k_min_partial(const double* __restrict__ rho, size_t count, doub
 
 // PFC initial guess of the auxiliary unknowns for rho^{k+1} = rho^k:
 // kappa = Delta_h rho, then (second launch) mu = phi^3/3 + alpha phi +
-// Delta_h kappa + 2 Delta_h rho.
+// Delta_h kappa + 2 Delta_h rho.  WL: a channel (n + 1 rows); a wall row
+// takes its adjacent interior row's value (no flux), computed in place.
+template <bool WL = false>
 __global__ void k_pfc_kappa(const double* __restrict__ rho, double* __restrict__ ka, int n, int lg, double h) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= n || j >= n) return;
-  const Nbr q = nbr(i, j, n, lg);
-  ka[q.p] = (rho[q.e] + rho[q.w] + rho[q.n] + rho[q.s] - 4.0 * rho[q.p]) / (h * h);
+  if (i >= n || j >= n + (WL ? 1 : 0)) return;
+  const int jr = !WL ? j : (j == 0 ? 1 : (j == n ? n - 1 : j));
+  const Nbr q = WL ? nbr_of<WPFC>(i, jr, n, lg) : nbr(i, j, n, lg);
+  ka[(j << lg) + i] = (rho[q.e] + rho[q.w] + rho[q.n] + rho[q.s] - 4.0 * rho[q.p]) / (h * h);
 }
 
+template <bool WL = false>
 __global__ void k_pfc_mu(const double* __restrict__ rho, const double* __restrict__ ka,
                          double* __restrict__ mu, int n, int lg, double h, double alpha) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= n || j >= n) return;
-  const Nbr q = nbr(i, j, n, lg);
+  if (i >= n || j >= n + (WL ? 1 : 0)) return;
+  const int jr = !WL ? j : (j == 0 ? 1 : (j == n ? n - 1 : j));
+  const Nbr q = WL ? nbr_of<WPFC>(i, jr, n, lg) : nbr(i, j, n, lg);
   const double phi = rho[q.p] - 1.5;
   const double lk = (ka[q.e] + ka[q.w] + ka[q.n] + ka[q.s] - 4.0 * ka[q.p]) / (h * h);
-  mu[q.p] = phi * phi * phi / 3.0 + alpha * phi + lk + 2.0 * ka[q.p];
+  mu[(j << lg) + i] = phi * phi * phi / 3.0 + alpha * phi + lk + 2.0 * ka[q.p];
+}
+
+// Channel state: u = u_wall and v = 0 on the wall rows, rho on them copied
+// from the adjacent interior rows.  One thread per column.
+__global__ void k_wall_state(double* __restrict__ rho, double* __restrict__ u, double* __restrict__ v, int n,
+                             int lg, double ub, double ut) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int top = n << lg, stride = 1 << lg;
+  rho[i] = rho[stride + i];
+  rho[top + i] = rho[top - stride + i];
+  u[i] = ub;
+  u[top + i] = ut;
+  v[i] = 0.0;
+  v[top + i] = 0.0;
 }
 
 // CDFT kernel of Sec. 6 on the periodic grid, minimum-image displacement:

@@ -33,12 +33,29 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
+  // channel (walls in y): coarse wall rows 0 and C.n take the boundary values
+  // (u = u_wall, v = 0; rho, mu, kappa copy the adjacent coarse row), R g is
+  // formed on the interior coarse rows, whose footprints lie on fine rows
+  // 1..F.n-1, and f_c only there
+  constexpr bool WL = walls(MODEL);
   const int mc = C.n - 1;
   const int X0 = (int)blockIdx.x * RTILE - 1, Y0 = (int)blockIdx.y * RTILE - 1;
   for (int w = threadIdx.x; w < RN; w += RTILE * RTILE) {
     const int ly = w / RX, lx = w - ly * RX;
-    const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
+    const int I = (X0 + lx) & mc;
+    int J = Y0 + ly;
+    if constexpr (WL) {
+      if (J < 0 || J > C.n) continue;  // beyond the walls: never read
+    } else {
+      J &= mc;
+    }
     if constexpr (RK) srk[w] = C.rk[(J << C.lg) + I];
+    if (WL && (J == 0 || J == C.n)) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c)
+        if (!wall_copied(c)) sg[c][w] = (c == 1) ? (J == 0 ? P.ub : P.ut) : T(0);
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < NCm; ++c) sg[c][w] = fw9g(F.g[c], 2 * I, 2 * J, F.n, F.lg);
     if constexpr (CORR) {
@@ -47,6 +64,18 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
     }
   }
   __syncthreads();
+  if constexpr (WL) {
+    const int r0 = -Y0, rn = C.n - Y0;  // LDS rows of the coarse walls
+    for (int w = threadIdx.x; w < RX; w += RTILE * RTILE) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        if (!wall_copied(c)) continue;
+        if (r0 >= 0 && r0 + 1 < RX) sg[c][r0 * RX + w] = sg[c][(r0 + 1) * RX + w];
+        if (rn >= 1 && rn < RX) sg[c][rn * RX + w] = sg[c][(rn - 1) * RX + w];
+      }
+    }
+    __syncthreads();
+  }
   const T* gl[NCm];
 #pragma unroll
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
@@ -55,7 +84,7 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
   const int ty = threadIdx.x / RTILE, tx = threadIdx.x - ty * RTILE;
   const int ly = ty + 1, lx = tx + 1;
-  const int I = (X0 + lx) & mc, J = (Y0 + ly) & mc;
+  const int I = (X0 + lx) & mc, J = WL ? (Y0 + ly) : ((Y0 + ly) & mc);
   const int pc = (J << C.lg) + I;
   Nbr q;
   q.p = ly * RX + lx;
@@ -63,6 +92,25 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   q.w = q.p - 1;
   q.n = q.p + RX;
   q.s = q.p - RX;
+  if constexpr (WL) {
+    // the wall rows: R g (boundary values) only; the block owning row C.n - 1
+    // also writes the top wall row, which belongs to no block
+    if (J == C.n - 1) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        C.g[c][pc + (1 << C.lg)] = sg[c][q.n];
+        C.g0[c][pc + (1 << C.lg)] = sg[c][q.n];
+      }
+    }
+    if (J == 0) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        C.g[c][pc] = sg[c][q.p];
+        C.g0[c][pc] = sg[c][q.p];
+      }
+      return;
+    }
+  }
   T nv[NCm];
   rows_any<MODEL, T, CORR>(gl, bl, srk, C.om, q, pc, C.k, P, nv);
 #pragma unroll

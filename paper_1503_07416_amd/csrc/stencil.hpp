@@ -11,16 +11,22 @@
 namespace hfz {
 
 // PFC and CDFT: the hydrodynamic step (App. G).  GPFC and GCDFT: the
-// gradient-flow variant of the same convex splitting (Thm. thm_grad).
-enum { PFC = 0, CDFT = 1, GPFC = 2, GCDFT = 3 };
+// gradient-flow variant of the same convex splitting (Thm. thm_grad).  WPFC:
+// the hydrodynamic PFC step in a channel, periodic in x with walls in y
+// (Sec. 6, sheared-nanocrystal run).
+enum { PFC = 0, CDFT = 1, GPFC = 2, GCDFT = 3, WPFC = 4 };
 
 __host__ __device__ constexpr bool gradflow(int m) { return m == GPFC || m == GCDFT; }
 __host__ __device__ constexpr bool cdft_like(int m) { return m == CDFT || m == GCDFT; }
+__host__ __device__ constexpr bool walls(int m) { return m == WPFC; }
+// The model whose rows and block solve a model uses.
+__host__ __device__ constexpr int algebra(int m) { return m == WPFC ? PFC : m; }
 
 // Unknowns per node: PFC (rho, u, v, mu, kappa), CDFT (rho, u, v), GPFC
 // (rho, mu, kappa), GCDFT (rho, mu).
 template <int MODEL> struct NC {
-  static constexpr int value = MODEL == PFC ? 5 : (MODEL == CDFT ? 3 : (MODEL == GPFC ? 3 : 2));
+  static constexpr int value =
+      algebra(MODEL) == PFC ? 5 : (MODEL == CDFT ? 3 : (MODEL == GPFC ? 3 : 2));
 };
 // Base fields the correction form is taken about: (rho, u, v), or rho alone
 // in the gradient flow (its only nonlinearities are in rho).
@@ -40,6 +46,7 @@ __device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
 // nothing.
 template <typename T> struct Phys {
   T s, gamma, sigma, alpha, ce, delta, w;
+  T ub, ut;  // channel: u on the walls j = 0 and j = n
   const int* halt;
 };
 
@@ -60,8 +67,9 @@ template <typename T> struct Lvl {
   T* rk;      // frozen rho^k
   T* om;      // frozen omega^k
   T* bg[3];   // correction form only: base state (rho, u, v) the correction is taken about
-  int n;      // grid size n_l
-  int lg;     // log2 n_l
+  int n;      // grid size n_l (x; and y for the periodic models)
+  int ny;     // rows stored: n_l, or n_l + 1 in a channel (node rows 0..n_l, the walls at 0 and n_l)
+  int lg;     // log2 n_l (row stride 2^lg)
   T h;        // spacing h_l
   Coef<T> k;  // stencil coefficients of this level
 };
@@ -123,6 +131,28 @@ __device__ __forceinline__ Nbr nbr(int i, int j, int n, int lg) {
   q.s = (((j - 1) & m) << lg) + i;
   return q;
 }
+
+// Neighbours for the model: in a channel y does not wrap (j an interior row,
+// 1 <= j <= n - 1, whose neighbours are rows of the (n + 1)-row array).
+template <int MODEL> __device__ __forceinline__ Nbr nbr_of(int i, int j, int n, int lg) {
+  if constexpr (walls(MODEL)) {
+    const int m = n - 1;
+    Nbr q;
+    const int row = j << lg;
+    q.p = row + i;
+    q.e = row + ((i + 1) & m);
+    q.w = row + ((i - 1) & m);
+    q.n = q.p + (1 << lg);
+    q.s = q.p - (1 << lg);
+    return q;
+  } else {
+    return nbr(i, j, n, lg);
+  }
+}
+
+// Channel wall rows: u = u_wall, v = 0 (fixed); rho, mu, kappa copy the
+// adjacent interior row (no flux), refreshed whenever that row changes.
+__host__ __device__ constexpr bool wall_copied(int c) { return c == 0 || c == 3 || c == 4; }
 
 // M = the part of mu^{k+1} carried by the unknowns: mu (PFC) or
 // ln rho + 2 c_e rho (CDFT, Lemma CDFT_ineq).
@@ -499,7 +529,7 @@ __device__ __forceinline__ void rows_N(const T* const* g, const T* rk, const T* 
   if constexpr (gradflow(MODEL))
     rows_gf<MODEL, T>(g, q, K, P, out);
   else
-    rows_hydro<MODEL, T, PM>(g, rk, om, q, pf, K, P, out, pm);
+    rows_hydro<algebra(MODEL), T, PM>(g, rk, om, q, pf, K, P, out, pm);
 }
 
 template <int MODEL, typename T, bool PM = false>
@@ -509,7 +539,7 @@ __device__ __forceinline__ void block_update(const T* const* g, const T* const* 
   if constexpr (gradflow(MODEL))
     block_update_gf<MODEL, T>(g, f, q, pf, K, P, out);
   else
-    block_update_hydro<MODEL, T, PM>(g, f, rk, om, q, pf, K, P, out, pm);
+    block_update_hydro<algebra(MODEL), T, PM>(g, f, rk, om, q, pf, K, P, out, pm);
 }
 
 template <int MODEL, typename T, bool PM = false>
@@ -519,7 +549,7 @@ __device__ __forceinline__ void rows_Nd(const T* const* e, const T* const* b, co
   if constexpr (gradflow(MODEL))
     rows_gfd<MODEL, T>(e, b, q, K, P, out);
   else
-    rows_Nd_hydro<MODEL, T, PM>(e, b, rk, om, q, pf, K, P, out, pm);
+    rows_Nd_hydro<algebra(MODEL), T, PM>(e, b, rk, om, q, pf, K, P, out, pm);
 }
 
 template <int MODEL, typename T, bool PM = false>
@@ -529,7 +559,7 @@ __device__ __forceinline__ void block_update_d(const T* const* e, const T* const
   if constexpr (gradflow(MODEL))
     block_update_gfd<MODEL, T>(e, f, b, q, pf, K, P, out);
   else
-    block_update_d_hydro<MODEL, T, PM>(e, f, b, rk, om, q, pf, K, P, out, pm);
+    block_update_d_hydro<algebra(MODEL), T, PM>(e, f, b, rk, om, q, pf, K, P, out, pm);
 }
 
 // Mode dispatch: CORR = false is the full form, CORR = true the correction

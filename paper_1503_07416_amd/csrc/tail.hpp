@@ -28,31 +28,32 @@ template <typename T> struct TailArgs {
 // coefficients (rk, om; none in the gradient flow), g0 below the top, the NB
 // base fields of the correction form, and d where it is held in LDS
 // (l >= d_from; the coarsest level needs none).
-template <int NCm, int NB, int NR>
+// WR = 1 for a channel, whose levels hold n + 1 rows.
+template <int NCm, int NB, int NR, int WR = 0>
 __host__ __device__ inline size_t tail_level_count(int n, int l, int nt, int d_from) {
   const bool dl = l >= d_from && l < nt - 1;
-  return (size_t)n * n * (2 * NCm + NR + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
+  return (size_t)n * (n + WR) * (2 * NCm + NR + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
 }
 
-template <int NCm, int NB, int NR>
+template <int NCm, int NB, int NR, int WR = 0>
 __host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int d_from) {
   size_t tot = 0;
-  for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB, NR>(top_n >> l, l, nt, d_from);
+  for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB, NR, WR>(top_n >> l, l, nt, d_from);
   return tot;
 }
 
 // Level descriptors of the tail: S = the LDS arrays the phases use, G = the
 // global arrays.  Thread t builds level t (same LDS order as tail_lds_count).
-template <int NCm, int NB, int NR, typename T>
+template <int NCm, int NB, int NR, int WR, typename T>
 __device__ inline void tail_lds_levels(const TailArgs<T>& A, T* base, Lvl<T>* S, Lvl<T>* G) {
   const int t = threadIdx.x;
   if (t >= A.nt) return;
   Lvl<T> s = A.Lg[t];
   G[t] = s;
   size_t off = 0;
-  for (int l = 0; l < t; ++l) off += tail_level_count<NCm, NB, NR>(A.top_n >> l, l, A.nt, A.d_from);
+  for (int l = 0; l < t; ++l) off += tail_level_count<NCm, NB, NR, WR>(A.top_n >> l, l, A.nt, A.d_from);
   T* p = base + off;
-  const int cnt = s.n * s.n;
+  const int cnt = s.n * s.ny;
 #pragma unroll
   for (int c = 0; c < NCm; ++c) s.g[c] = p + c * cnt;
   p += NCm * cnt;
@@ -104,19 +105,38 @@ __device__ __forceinline__ Lvl<T> tail_view(const Lvl<T>& s) {
   return L;
 }
 
+// Channel: rho, mu, kappa on the wall rows 0 and n <- the adjacent rows.
+template <int MODEL, typename T> __device__ __forceinline__ void tail_wall_rows(const Lvl<T> L) {
+  if constexpr (walls(MODEL)) {
+    const int top = L.n << L.lg, stride = 1 << L.lg;
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < NC<MODEL>::value; ++c) {
+        if (!wall_copied(c)) continue;
+        L.g[c][i] = L.g[c][stride + i];
+        L.g[c][top + i] = L.g[c][top - stride + i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour) {
-  const int n = L.n, cnt = (n >> 1) * n, lgh = L.lg - 1;
+  // a channel updates its interior rows 1..n-1, then refreshes its wall rows
+  constexpr int J0 = walls(MODEL) ? 1 : 0;
+  const int n = L.n, cnt = (n >> 1) * (n - J0), lgh = L.lg - 1;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
-    const int j = w >> lgh, t = w & ((1 << lgh) - 1);
+    const int j = J0 + (w >> lgh), t = w & ((1 << lgh) - 1);
     const int i = 2 * t + ((j + colour) & 1);
-    const Nbr q = nbr(i, j, n, L.lg);
+    const Nbr q = nbr_of<MODEL>(i, j, n, L.lg);
     T out[NC<MODEL>::value];
     update_any<MODEL, T, CORR>(L.g, L.f, L.bg, L.rk, L.om, q, q.p, L.k, P, out);
 #pragma unroll
     for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][q.p] = out[c];
   }
   __syncthreads();
+  tail_wall_rows<MODEL, T>(L);
 }
 
 template <int MODEL, typename T, bool CORR>
@@ -132,18 +152,34 @@ __device__ __forceinline__ void tail_sweeps(const Lvl<T> L, const Phys<T>& P, in
 // f_c = R d + N_c(R g).
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
+  // channel: d on the fine interior rows; R g on the coarse interior rows (their
+  // footprints are fine interior rows) and the boundary values on the coarse
+  // wall rows; f_c on the coarse interior rows
   constexpr int NCm = NC<MODEL>::value;
-  const int fcnt = F.n * F.n;
+  constexpr bool WL = walls(MODEL);
+  const int fcnt = F.n * F.ny;
   for (int w = threadIdx.x; w < fcnt; w += blockDim.x) {
-    const Nbr q = nbr(w & (F.n - 1), w >> F.lg, F.n, F.lg);
+    const int j = w >> F.lg;
+    if (WL && (j == 0 || j == F.n)) continue;
+    const Nbr q = nbr_of<MODEL>(w & (F.n - 1), j, F.n, F.lg);
     T nv[NCm];
     rows_any<MODEL, T, CORR>(F.g, F.bg, F.rk, F.om, q, q.p, F.k, P, nv);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) F.d[c][q.p] = F.f[c][q.p] - nv[c];
   }
-  const int cnt = C.n * C.n;
+  const int cnt = C.n * C.ny;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int J = w >> C.lg, I = w & (C.n - 1);
+    if (WL && (J == 0 || J == C.n)) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        if (wall_copied(c)) continue;  // after the interior rows, below
+        const T b = (c == 1) ? (J == 0 ? P.ub : P.ut) : T(0);
+        C.g[c][w] = b;
+        C.g0[c][w] = b;
+      }
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < NCm; ++c) {
       const T gr = fw9(F.g[c], 2 * I, 2 * J, F.n, F.lg);
@@ -156,9 +192,22 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
     }
   }
   __syncthreads();
+  if constexpr (WL) {
+    const int top = C.n << C.lg, stride = 1 << C.lg;
+    for (int i = threadIdx.x; i < C.n; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        if (!wall_copied(c)) continue;
+        C.g[c][i] = C.g0[c][i] = C.g0[c][stride + i];
+        C.g[c][top + i] = C.g0[c][top + i] = C.g0[c][top - stride + i];
+      }
+    }
+    __syncthreads();
+  }
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int J = w >> C.lg, I = w & (C.n - 1);
-    const Nbr q = nbr(I, J, C.n, C.lg);
+    if (WL && (J == 0 || J == C.n)) continue;
+    const Nbr q = nbr_of<MODEL>(I, J, C.n, C.lg);
     T nv[NCm];
     rows_any<MODEL, T, CORR>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv);
 #pragma unroll
@@ -169,11 +218,16 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
 
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
+  // channel: the interior fine rows take the correction (the coarse wall rows
+  // hold zero correction for u, v and the adjacent row's for rho, mu, kappa),
+  // then the fine wall rows are refreshed
   constexpr int NCm = NC<MODEL>::value;
-  const int cnt = F.n * F.n, mc = C.n - 1;
+  constexpr bool WL = walls(MODEL);
+  const int cnt = F.n * F.ny, mc = C.n - 1;
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int j = w >> F.lg, i = w & (F.n - 1);
-    const int I = i >> 1, J = j >> 1, I1 = (I + 1) & mc, J1 = (J + 1) & mc;
+    if (WL && (j == 0 || j == F.n)) continue;
+    const int I = i >> 1, J = j >> 1, I1 = (I + 1) & mc, J1 = WL ? (J + 1) : ((J + 1) & mc);
     const int p00 = (J << C.lg) + I, p10 = (J << C.lg) + I1;
     const int p01 = (J1 << C.lg) + I, p11 = (J1 << C.lg) + I1;
     const int pi = i & 1, pj = j & 1;
@@ -199,6 +253,7 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
     }
   }
   __syncthreads();
+  tail_wall_rows<MODEL, T>(F);
 }
 
 template <int MODEL, typename T, bool CORR>
@@ -206,17 +261,18 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 0;
   constexpr int NR = NCoef<MODEL>::value;
+  constexpr int WR = walls(MODEL) ? 1 : 0;
   extern __shared__ __align__(16) unsigned char tail_smem[];
   // level descriptors in LDS: S = LDS copies, G = the global arrays
   __shared__ Lvl<T> S[TAIL_MAX_LEVELS];
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
-  tail_lds_levels<NCm, NB, NR, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
+  tail_lds_levels<NCm, NB, NR, WR, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
   __syncthreads();
   // load: every global value a thread moves is read before it is stored
   for (int l = 0; l < A.nt; ++l) {
     const Lvl<T> s = tail_view<NCm, NB, NR, false>(S[l]);
     const Lvl<T> g = lvl_global(G[l]);
-    const int cnt = g.n * g.n;
+    const int cnt = g.n * g.ny;
     if (NR == 0 && l > 0) break;  // only the top level has anything to load
     for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
       T x[2 * NCm + NB + 2];
@@ -267,7 +323,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   {
     const Lvl<T> s = tail_view<NCm, NB, NR, false>(S[0]);
     const Lvl<T> g = lvl_global(G[0]);
-    const int cnt = g.n * g.n;
+    const int cnt = g.n * g.ny;
     for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
       T x[NCm];
 #pragma unroll

@@ -58,6 +58,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   // and half sweep into sm, for the nodes of the colour not being updated,
   // instead of at each of their four neighbours.
   constexpr bool PM = MODEL == CDFT;
+  // channel (walls in y): rows outside 0..n are not loaded, only interior rows
+  // are updated, and the wall rows of rho, mu, kappa are refreshed in LDS
+  // after every half sweep (the block touching a wall holds both it and the
+  // adjacent row: its region spans H >= 2 rows beyond its owned block)
+  constexpr bool WL = walls(MODEL);
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
@@ -67,7 +72,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   __shared__ T sx[(SE > SM ? SE : SM) > 0 ? (SE > SM ? SE : SM) : 1];
   T(*se)[CRN] = reinterpret_cast<T(*)[CRN]>(sx);
   T* sm = sx;
-  const int m = L.n - 1, lg = L.lg;
+  const int m = L.n - 1, lg = L.lg, nn = L.n;
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
   const int x0 = (int)blockIdx.x * TILE_X - H, y0 = (int)blockIdx.y * TILE_Y - H;
   const int X0c = x0 >> 1, Y0c = y0 >> 1;  // floor halves (arithmetic shift)
@@ -75,7 +80,13 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     const int mc = C.n - 1;
     for (int w = threadIdx.x; w < CRN; w += TILE_THREADS) {
       const int cy = w / CRX, cx = w - cy * CRX;
-      const int pc = (((Y0c + cy) & mc) << C.lg) + ((X0c + cx) & mc);
+      int cj = Y0c + cy;
+      if constexpr (WL) {
+        if (cj < 0 || cj > C.n) continue;  // beyond the coarse walls: never read
+      } else {
+        cj &= mc;
+      }
+      const int pc = (cj << C.lg) + ((X0c + cx) & mc);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) se[c][w] = C.g[c][pc] - C.g0[c][pc];
     }
@@ -83,7 +94,13 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   }
   for (int w = threadIdx.x; w < RN; w += TILE_THREADS) {
     const int ly = w / RX, lx = w - ly * RX;
-    const int gi = (x0 + lx) & m, gj = (y0 + ly) & m;
+    const int gi = (x0 + lx) & m;
+    int gj = y0 + ly;
+    if constexpr (WL) {
+      if (gj < 0 || gj > nn) continue;  // beyond the walls: never read
+    } else {
+      gj &= m;
+    }
     const int gp = (gj << lg) + gi;
     if constexpr (RK) srk[w] = L.rk[gp];
     if constexpr (CORR) {
@@ -94,6 +111,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     for (int c = 0; c < NCm; ++c) {
       T x = gin.c[c][gp];
       if constexpr (PRO) {
+        if (WL && (gj == 0 || gj == nn)) {  // wall rows: refreshed below
+          sg[c][w] = x;
+          continue;
+        }
         // bilinear prolongation of e (same arithmetic as k_prolong)
         const int gu = x0 + lx, gv = y0 + ly;
         const int cp = ((gv >> 1) - Y0c) * CRX + ((gu >> 1) - X0c);
@@ -117,6 +138,20 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
   }
   __syncthreads();
+  // LDS rows of the channel's walls (valid when inside 0..RY-1)
+  const int r0 = -y0, rn = nn - y0;
+  auto wall_refresh = [&]() {
+    for (int w = threadIdx.x; w < RX; w += TILE_THREADS) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        if (!wall_copied(c)) continue;
+        if (r0 >= 0 && r0 + 1 < RY) sg[c][r0 * RX + w] = sg[c][(r0 + 1) * RX + w];
+        if (rn >= 1 && rn < RY) sg[c][rn * RX + w] = sg[c][(rn - 1) * RX + w];
+      }
+    }
+    __syncthreads();
+  };
+  if constexpr (WL && PRO) wall_refresh();
   const T* gl[NCm];
 #pragma unroll
   for (int c = 0; c < NCm; ++c) gl[c] = sg[c];
@@ -143,19 +178,23 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       const int r = w / half, t = w - r * half;
       const int ly = k + r;
       const int lx = k + 2 * t + ((k + ly + colour) & 1);
+      if constexpr (WL) {
+        if (y0 + ly < 1 || y0 + ly > nn - 1) continue;
+      }
       Nbr q;
       q.p = ly * RX + lx;
       q.e = q.p + 1;
       q.w = q.p - 1;
       q.n = q.p + RX;
       q.s = q.p - RX;
-      const int pf = (((y0 + ly) & m) << lg) + ((x0 + lx) & m);
+      const int pf = ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
       T out[NCm];
       update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
     }
     __syncthreads();
+    if constexpr (WL) wall_refresh();
   }
   if constexpr (PM && RES != 0) {
     // M on the owned block and its one-node ring, for the residual rows
@@ -171,9 +210,18 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   for (int w = threadIdx.x; w < TILE_X * TILE_Y; w += TILE_THREADS) {
     const int ty = w / TILE_X, tx = w - ty * TILE_X;
     const int lp = (ty + H) * RX + tx + H;
-    const int gp = (((y0 + H + ty) & m) << lg) + ((x0 + H + tx) & m);
+    const int gy = WL ? (y0 + H + ty) : ((y0 + H + ty) & m);
+    const int gp = (gy << lg) + ((x0 + H + tx) & m);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) gout.c[c][gp] = sg[c][lp];
+    if constexpr (WL) {
+      // the top wall row n belongs to no block: the block owning row n - 1 writes it
+      if (gy == nn - 1) {
+#pragma unroll
+        for (int c = 0; c < NCm; ++c) gout.c[c][gp + (1 << lg)] = sg[c][lp + RX];
+      }
+      if (gy == 0) continue;  // the bottom wall row: no equation
+    }
     if constexpr (RES != 0) {
       Nbr q;
       q.p = lp;

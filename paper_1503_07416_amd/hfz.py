@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int),
         ("coarsest_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
         ("precision", ctypes.c_int), ("sigma", ctypes.c_int), ("continuity_fix", ctypes.c_int),
+        ("walls", ctypes.c_int), ("u_wall_bottom", ctypes.c_double), ("u_wall_top", ctypes.c_double),
     ]
 
 
@@ -138,6 +139,10 @@ def make_params(cfg):
         p.continuity_fix = int(bool(cf))
     prec = get("precision", "fp64")
     p.precision = MIXED if prec == "mixed" else FP64
+    if get("walls"):
+        p.walls = 1
+        p.u_wall_bottom = float(get("u_bot", 0.0))
+        p.u_wall_top = float(get("u_top", 0.0))
     return p
 
 
@@ -173,20 +178,26 @@ class Simulation:
         return t.to(self.device).contiguous()
 
     def _empty(self, n=None):
+        """A field of a level of size n: n x n, or (n + 1) x n in a channel."""
         n = self.n if n is None else n
-        return torch.empty((n, n), dtype=torch.float64, device=self.device)
+        return torch.empty((n + self.p.walls, n), dtype=torch.float64, device=self.device)
 
     @property
     def gradflow(self):
         return self.p.model in (PFC_GF, CDFT_GF)
 
     def set_state(self, rho, u=None, v=None):
-        """(rho, u, v); the gradient-flow models take rho alone (u, v ignored)."""
+        """(rho, u, v), each n x n (a channel: (n + 1) x n, rows 0..n); the
+        gradient-flow models take rho alone (u, v ignored)."""
+        shape = (self.n + self.p.walls, self.n)
         r = self._dev(rho)
         if self.gradflow:
             uu = vv = None
         else:
             uu, vv = self._dev(u), self._dev(v)
+        for t in (r, uu, vv):
+            if t is not None and tuple(t.shape) != shape:
+                raise ValueError(f"state field of shape {tuple(t.shape)}, expected {shape}")
         torch.cuda.current_stream(self.device).synchronize()
         check(self.lib.hfz_set_state(self.h, _ptr(r), _ptr(uu), _ptr(vv)), "hfz_set_state")
 

@@ -1,0 +1,191 @@
+"""GPU parity of the PFC step in a channel (walls in y; Sec. 6 sheared-
+nanocrystal run) through the C ABI against the CPU FP64 oracle
+(oracle/walls.py): stage by stage and step by step, the Couette steady state,
+and at the benchmark size (the 13-atom nucleate on 256 x 257 nodes) the
+properties the oracle evaluates in one pass."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import walls
+from tests.helpers import oracle_stepper, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-10
+
+
+def np_(t):
+    return t.cpu().numpy()
+
+
+def case(n, seed=0, u_wall=0.1):
+    """A channel of n x (n + 1) nodes: the nucleate recipe with noise (at small
+    n the nucleate covers the channel)."""
+    return workloads.channel(n, u_wall=u_wall, seed=seed, amp=0.05)
+
+
+def sim_for(cfg, rho, u, v):
+    import paper_1503_07416_amd as pkg
+    s = pkg.Simulation(cfg)
+    s.set_state(rho, u, v)
+    return s
+
+
+def random_flow(n, seed):
+    u, v = workloads.random_velocity(n, seed, 0.02)
+    u = np.vstack([u, u[:1]])
+    v = np.vstack([v, v[:1]])
+    return u, v
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_source_and_coefficients(n):
+    cfg, rho, _, _ = case(n, seed=1)
+    u, v = random_flow(n, 11)
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    # the state's wall rows hold the boundary values
+    r, uu, vv = [np_(x) for x in sim.get_state()]
+    assert rel_err(r, ora.rho) == 0.0 and rel_err(uu, ora.u) == 0.0 and np.abs(vv - ora.v).max() == 0.0
+    mu, ka = sim.get_aux()
+    assert rel_err(np_(mu), ora.g[3]) < 1e-12 and rel_err(np_(ka), ora.g[4]) < 1e-12
+    sim.begin_step()
+    S, om = ora.build_source()
+    for c in range(5):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+    assert rel_err(np_(sim.read(3, 0, 1)), om) < 1e-12
+    sol = ora.solver(om)
+    for l, lev in enumerate(sol.levels):
+        assert rel_err(np_(sim.read(3, l, 0)), lev.rho_k) < 1e-13, l
+        if np.abs(lev.omega_k).max() > 0:
+            assert rel_err(np_(sim.read(3, l, 1)), lev.omega_k) < 1e-12, l
+    assert sim.levels() == len(sol.levels)
+
+
+@pytest.mark.parametrize("n", [8, 32, 64, 128])
+def test_sweeps_and_residual(n):
+    """One and two sweeps on the finest level (the per-colour kernel below
+    32, the LDS-tiled kernel from 32 up) and the residual norm."""
+    cfg, rho, _, _ = case(n, seed=2)
+    u, v = random_flow(n, 12)
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    lev = sol.levels[0]
+    g = ora.g.copy()
+    r0 = sol.resnorm(g, S, lev)
+    assert abs(sim.residual() - r0) < 1e-11 * r0
+    sim.smooth(0, 1)
+    walls.sweep(g, S, lev, cfg.w)
+    for c in range(5):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    sim.smooth(0, 2)
+    walls.sweep(g, S, lev, cfg.w)
+    walls.sweep(g, S, lev, cfg.w)
+    for c in range(5):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    r2 = sol.resnorm(g, S, lev)
+    assert abs(sim.residual() - r2) < 1e-10 * r2
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_vcycles(n):
+    cfg, rho, _, _ = case(n, seed=3)
+    u, v = random_flow(n, 13)
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    g = ora.g.copy()
+    for k in range(3):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(5)]
+        assert max(errs) < 1e-11, (k, errs)
+    r = sol.resnorm(g, S, sol.levels[0])
+    assert abs(sim.residual() - r) < 1e-9 * r
+
+
+@pytest.mark.parametrize("n,u_wall", [(32, 0.1), (64, 0.5)])
+def test_steps(n, u_wall):
+    cfg, rho, u, v = case(n, seed=4, u_wall=u_wall)
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    for k in range(4):
+        st = sim.step(1)
+        c, r = ora.step()
+        assert abs(st.cycles_last - c) <= 1, (k, st.cycles_last, c)
+        assert st.residual_last <= cfg.tol
+        rg, ug, vg = [np_(x) for x in sim.get_state()]
+        assert rel_err(rg, ora.rho) < TOL_STEP, k
+        vs = max(np.abs(ora.u).max(), np.abs(ora.v).max())
+        assert np.abs(ug - ora.u).max() < TOL_STEP * vs and np.abs(vg - ora.v).max() < TOL_STEP * vs, k
+    E, Eo = sim.energy(), ora.energy()
+    assert abs(E[0] - Eo[0]) < 1e-10 * abs(Eo[0])
+    assert abs(sim.mass() - ora.mass()) < 1e-12 * ora.mass()
+
+
+def test_couette_steady_state():
+    n, U = 64, 0.3
+    cfg, _, _, _ = case(n, u_wall=U)
+    y = np.arange(n + 1) * cfg.h
+    u = np.repeat((-U + 2 * U * y / (n * cfg.h))[:, None], n, axis=1)
+    rho = np.full((n + 1, n), 0.85)
+    sim = sim_for(cfg, rho, u, np.zeros_like(u))
+    st = sim.step(2)
+    assert st.cycles_total == 0
+    r, uu, vv = [np_(x) for x in sim.get_state()]
+    assert np.abs(r - rho).max() < 1e-14 and np.abs(uu - u).max() < 1e-14 and np.abs(vv).max() < 1e-14
+
+
+def test_full_size_step():
+    """256 x 257 nodes, the 13-atom nucleate, walls at -+0.1: the GPU's iterate
+    solves the oracle's system to tol, the end of the step is the oracle's
+    continuity update of it, and the benchmarked step gives the same state
+    and V-cycle count as the stage-by-stage solve."""
+    cfg, rho, u, v = workloads.channel(256, u_wall=0.1)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    S, om = ora.build_source()
+    lev = ora.solver(om).levels[0]
+    print("channel 256: begin", flush=True)
+    sim = sim_for(cfg, rho, u, v)
+    sim.begin_step()
+    for c in range(5):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+    r = sim.residual()
+    cycles = 0
+    while r > cfg.tol and cycles < cfg.max_cycles:
+        sim.vcycle(1)
+        cycles += 1
+        r = sim.residual()
+    assert r <= cfg.tol
+    g = np.stack([np_(sim.read(0, 0, c)) for c in range(5)])
+    d = S - walls.N(g, lev)
+    r_ora = np.sqrt(lev.h ** 2 * float(np.sum(d * d)))
+    assert r_ora <= cfg.tol and abs(r_ora - r) <= 1e-3 * r + 1e-13, (r_ora, r)
+    sim.finish_step()
+    staged = [np_(x) for x in sim.get_state()]
+    ru, rv = rho * g[1], rho * g[2]
+    from oracle.grid import east, north, south, west
+    rho1 = S[0] - cfg.s / (4 * cfg.h) * (east(ru) - west(ru) + north(rv) - south(rv))
+    assert rel_err(staged[0][1:-1], rho1[1:-1]) < 1e-12
+    assert np.array_equal(staged[0][0], staged[0][1]) and np.array_equal(staged[0][-1], staged[0][-2])
+    sim.close()
+    sim = sim_for(cfg, rho, u, v)
+    st = sim.step(1)
+    print(f"channel 256: cycles {st.cycles_last} (staged {cycles}), residual {st.residual_last:.3e}", flush=True)
+    assert st.cycles_last == cycles
+    for x, y in zip([np_(t) for t in sim.get_state()], staged):
+        assert np.abs(x - y).max() <= 1e-12 * max(np.abs(y).max(), 1e-30)
+    sim.close()

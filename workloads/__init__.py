@@ -55,6 +55,9 @@ class Config:
     sigma: float = 1.0
     continuity_fix: bool = True
     precision: str = "fp64"    # "fp64" or "mixed"
+    walls: bool = False        # PFC in a channel: walls at y = 0 and y = n h
+    u_bot: float = 0.0         # channel: wall speeds (u on the walls, v = 0)
+    u_top: float = 0.0
 
     @property
     def gradflow(self):
@@ -75,7 +78,14 @@ class Config:
             d.pop("alpha")
         if self.gradflow:
             d.pop("gamma"); d.pop("sigma")
+        d.pop("walls"); d.pop("u_bot"); d.pop("u_top")
         return d
+
+    def wall_oracle_kwargs(self):
+        """Keyword arguments of oracle.walls.Stepper for a channel config."""
+        d = self.oracle_kwargs()
+        d.pop("alpha")
+        return dict(d, u_bot=self.u_bot, u_top=self.u_top)
 
 
 def pfc_uniform_noise(n, h, s, seed, rho_bar=PFC_RHO_BAR, amp=0.05, **kw):
@@ -128,6 +138,20 @@ def nucleate(n, h, eps=NANO_EPS, rho_s=NANO_RHO_S, rho_l=NANO_RHO_L, diag_atoms=
     dx, dy = np.abs(X - L / 2), np.abs(Y - L / 2)
     inside = (dy <= math.sqrt(3.0) / 2.0 * R) & (math.sqrt(3.0) * dx + dy <= math.sqrt(3.0) * R)
     return np.where(inside, solid, rho_l)
+
+
+def channel(n=256, u_wall=0.1, seed=None, amp=0.0, **kw):
+    """The sheared-nanocrystal run of Sec. 6 in a channel of n x (n + 1) node
+    rows: eps = 0.4, h = pi/(2 sqrt 3), s = 0.02, walls at -u_wall (bottom) and
+    +u_wall (top), the hexagonal nucleate of ``nucleate`` (13 atoms along its
+    diagonal) in the liquid at rest; with seed given, amp * U(-1, 1) noise is
+    added to rho (smaller grids for tests)."""
+    rho = nucleate(n, NANO_H)
+    if seed is not None:
+        rho = rho + amp * np.random.default_rng(seed).uniform(-1.0, 1.0, rho.shape)
+    z = np.zeros_like(rho)
+    cfg = Config("pfc", n, NANO_H, 0.02, alpha=1.0 - NANO_EPS, walls=True, u_bot=-u_wall, u_top=u_wall, **kw)
+    return cfg, rho, z.copy(), z.copy()
 
 
 def random_velocity(n, seed, amp):
