@@ -26,7 +26,12 @@ Also reported on the same JSON line:
                 PFC free energy at 512^2 and the CDFT free energy at 1024^2 (the
                 freezing runs' constants and initial densities), FP64 and mixed:
                 steps/s, V-cycles per step, F and mass checks, and the roofline of
-                its finest-level smoother.
+                its finest-level smoother;
+  channel       the sheared-nanocrystal run of Sec. 6: PFC (eps = 0.4) in a
+                channel of 256 x 257 nodes with walls at rest and at -+0.1 and
+                -+0.5, the 13-atom hexagonal nucleate in the liquid: steps/s,
+                V-cycles per step, energy (non-increasing with resting walls),
+                and the roofline of its finest-level smoother.
 """
 import argparse
 import dataclasses
@@ -67,6 +72,7 @@ def parse():
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
     ap.add_argument("--gradflow-only", action="store_true", help="only the gradient-flow workloads (for profiles)")
+    ap.add_argument("--channel-only", action="store_true", help="only the channel workloads (for profiles)")
     ap.add_argument("--convergence", action="store_true",
                     help="the paper's convergence study instead of the benchmark (minutes of GPU time)")
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
@@ -418,6 +424,61 @@ def run_gradflow(steps=50, check_steps=10):
     return out
 
 
+def run_channel(steps=50, check_steps=10, n=256):
+    """The sheared-nanocrystal channel (Sec. 6) at wall speeds 0, 0.1, 0.5:
+    `steps` timed steps, then `check_steps` with the energy read after each
+    (not timed).  With resting walls the energy must not increase."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    out = {"workload": f"PFC eps=0.4 channel {n}x{n + 1} nodes, h=pi/(2 sqrt3), s=0.02, 13-atom hexagonal "
+                       f"nucleate, FAS V(2,2) tol 1e-10 FP64, {steps} timed steps (+{check_steps} checked)"}
+    for uw in (0.0, 0.1, 0.5):
+        cfg, rho, u, v = workloads.channel(n, u_wall=uw)
+        sim = pkg.Simulation(cfg, device="cuda:0")
+        sim.set_state(rho, u, v)
+        sim.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        E = [sim.energy()]
+        for _ in range(check_steps):
+            sim.step(1)
+            E.append(sim.energy())
+        r = {"steps_per_s": round(steps / dt, 3), "ms_per_step": round(1e3 * dt / steps, 4),
+             "vcycles_per_step": round(st.cycles_total / steps, 3), "final_residual": st.residual_last,
+             "E_last": E[-1][0], "KE_last": E[-1][1],
+             "energy_increases": sum(1 for a, b in zip(E[:-1], E[1:]) if b[0] > a[0] + 1e-12 * abs(a[0]))}
+        if uw == 0.1:
+            # algorithmic bytes: the interior nodes n x (n - 1)
+            r["roofline"] = smoother_roofline(sim, n, model="WPFC")
+            r["roofline"]["bytes_per_launch"] = 2 * SWEEP_BYTES_PFC * n * (n - 1)
+            t = r["roofline"]["launch_us"] * 1e-6
+            r["roofline"]["achieved"] = round(r["roofline"]["bytes_per_launch"] / t / 1e9, 1)
+            r["roofline"]["frac"] = round(r["roofline"]["achieved"] / HBM_PEAK_GBS, 4)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out[f"u_wall_{uw:g}"] = r
+    # the channel smoother past the 256 MB cache (a grid that fills the device)
+    sweep = {}
+    for m in (1024, 2048):
+        cfg, rho, u, v = workloads.channel(m, u_wall=0.1)
+        sim = pkg.Simulation(cfg, device="cuda:0")
+        sim.set_state(rho, u, v)
+        rl = smoother_roofline(sim, m, model="WPFC")
+        nbytes = 2 * SWEEP_BYTES_PFC * m * (m - 1)
+        sweep[str(m)] = {"launch_us": rl["launch_us"], "achieved": round(nbytes / (rl["launch_us"] * 1e-6) / 1e9, 1),
+                         "kernel": rl["kernel"]}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["smoother_size_sweep_GBs"] = sweep
+    return out
+
+
 def run_convergence(sizes, tf):
     """The paper's convergence study (Sec. 6.1): smooth initial density on
     [0,32)^2, u = 0, refinement path s = 0.025 h^2 to t_f; CDFT with nu = 1 and
@@ -497,6 +558,9 @@ def main():
     if a.gradflow_only:
         print(json.dumps({"gradflow": run_gradflow()}))
         return
+    if a.channel_only:
+        print(json.dumps({"channel": run_channel()}))
+        return
     if a.mixed_only:
         import torch
         import workloads
@@ -552,6 +616,8 @@ def main():
         out["serving"] = run_serving(a.serve_requests, a.serve_budget_gib)
         torch.cuda.empty_cache()
         out["gradflow"] = run_gradflow()
+        torch.cuda.empty_cache()
+        out["channel"] = run_channel()
     print(json.dumps(out))
 
 
