@@ -32,6 +32,9 @@ paper it follows (section, equation label, appendix).  Modules:
               FAS solver and stepper
 ``walls``     the PFC step in a channel (Sec. 6, sheared-nanocrystal run): no-slip
               moving walls and no-flux density in y, periodic in x
+``three_d``   the PFC step in three dimensions (the extension Sec. 3 calls
+              straightforward): 7-point operators, vector vorticity, 3x3
+              velocity block
 
 Pins (see tests/test_oracle_*.py): Fourier symbols and summation by parts of
 the operators; two transcriptions of the scheme agree; FAS equals dense Newton;
@@ -44,5 +47,8 @@ scheme written directly with dF_c, dF_e, dense Newton, the closed-form
 amplification of a Fourier mode, mass, the dissipation identity and energy
 decay for any s (tests/test_oracle_gradflow.py); for the channel dense Newton,
 the Couette steady state and start-up, mirror symmetry, energy decay with
-resting walls and the transfers on linear fields (tests/test_oracle_walls.py).
+resting walls and the transfers on linear fields (tests/test_oracle_walls.py);
+for 3D the reduction to the 2D oracle for z-independent states, axis-rotation
+equivariance, dense Newton, closed-form linear growth, energy and mass for any
+s, the transfers on linear fields (tests/test_oracle_three_d.py).
 """
