@@ -238,6 +238,44 @@ int hfz_batch_release(hfz_batch* b, int i);
 int hfz_batch_step(hfz_batch* b, int nsteps, hfz_stats* stats);
 int hfz_batch_destroy(hfz_batch* b);
 
+/* ---- three dimensions ---------------------------------------------------
+ * The hydrodynamic PFC step on a periodic n x n x n grid (the extension to 3D
+ * that Sec. 3 calls straightforward; the paper works in 2D).  Unknowns per
+ * node (rho, u, v, w, mu, kappa); the rows are App. G's with the third
+ * direction: 7-point Delta_h, wide central differences, the vector vorticity
+ * omega^k = curl_h u^k and the vector form -rho^k omega^k x u of the
+ * advection term.  The smoother keeps App. G's triangular block; its velocity
+ * part is the 3x3 system (a I + [b x]) u = r, a = rho^k + 3 s gamma/h^2,
+ * b = (s/2) sigma rho^k omega^k, solved in closed form.  FAS V(nu1, nu2) with
+ * 27-point full weighting and trilinear prolongation; norm, energy and mass
+ * carry the weight h^3.  Parameters: hfz_params with model HFZ_PFC, FP64, no
+ * walls, 8 <= n <= 512 (HFZ_EINVAL otherwise).  Fields: n^3 FP64 values,
+ * x fastest, then y, then z.  Ownership, streams and errors as for the 2D
+ * calls.  The damped block smoother needs s/h^4 of order 0.5 or less in 3D. */
+typedef struct hfz3_handle hfz3_handle;
+
+int hfz3_workspace_bytes(const hfz_params* p, size_t* bytes);
+int hfz3_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, hfz3_handle** out);
+/* (rho, u, v, w) from device buffers; mu and kappa start consistent with rho^{k+1} = rho^k. */
+int hfz3_set_state(hfz3_handle* hd, const double* rho, const double* u, const double* v, const double* w);
+int hfz3_get_state(hfz3_handle* hd, double* rho, double* u, double* v, double* w);
+/* As hfz_step. */
+int hfz3_step(hfz3_handle* hd, int nsteps, hfz_stats* stats);
+/* out[0] = E = KE + F, out[1] = KE, out[2] = F (the 3D PFC energy, weight h^3).  Host array of 3. */
+int hfz3_energy(hfz3_handle* hd, double* out3);
+int hfz3_mass(hfz3_handle* hd, double* mass);
+/* Stage calls as their 2D counterparts. */
+int hfz3_begin_step(hfz3_handle* hd);
+int hfz3_smooth(hfz3_handle* hd, int level, int sweeps);
+int hfz3_vcycle(hfz3_handle* hd, int count);
+int hfz3_residual(hfz3_handle* hd, double* norm);
+int hfz3_finish_step(hfz3_handle* hd);
+/* which: 0 iterate, 1 right-hand side, 3 frozen coefficients (comp 0 rho^k,
+ * 1..3 omega^k), 5 the auxiliaries of level 0 (comp 0 mu, 1 kappa). */
+int hfz3_read_field(hfz3_handle* hd, int which, int level, int comp, double* dst);
+int hfz3_levels(hfz3_handle* hd, int* levels);
+int hfz3_destroy(hfz3_handle* hd);
+
 #ifdef __cplusplus
 }
 #endif

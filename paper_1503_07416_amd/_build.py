@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhfz.so")
-SOURCES = [os.path.join(HERE, "csrc", "hfz.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "hfz.hip"), os.path.join(HERE, "csrc", "hfz3.hip")]
 DEPS = [os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))]
 
 FLAGS = [

@@ -29,6 +29,9 @@ SYMBOLS = [
     "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_tile_shape", "hfz_destroy", "hfz_strerror",
     "hfz_batch_workspace_bytes", "hfz_batch_init", "hfz_batch_set_state", "hfz_batch_get_state",
     "hfz_batch_energy", "hfz_batch_release", "hfz_batch_step", "hfz_batch_destroy",
+    "hfz3_workspace_bytes", "hfz3_init", "hfz3_set_state", "hfz3_get_state", "hfz3_step", "hfz3_energy",
+    "hfz3_mass", "hfz3_begin_step", "hfz3_smooth", "hfz3_vcycle", "hfz3_residual", "hfz3_finish_step",
+    "hfz3_read_field", "hfz3_levels", "hfz3_destroy",
 ]
 
 
@@ -98,6 +101,21 @@ def load():
         "hfz_batch_release": [vp, i],
         "hfz_batch_step": [vp, i, P(Stats)],
         "hfz_batch_destroy": [vp],
+        "hfz3_workspace_bytes": [P(Params), P(ctypes.c_size_t)],
+        "hfz3_init": [P(Params), vp, ctypes.c_size_t, vp, P(vp)],
+        "hfz3_set_state": [vp, vp, vp, vp, vp],
+        "hfz3_get_state": [vp, vp, vp, vp, vp],
+        "hfz3_step": [vp, i, P(Stats)],
+        "hfz3_energy": [vp, P(d)],
+        "hfz3_mass": [vp, P(d)],
+        "hfz3_begin_step": [vp],
+        "hfz3_smooth": [vp, i, i],
+        "hfz3_vcycle": [vp, i],
+        "hfz3_residual": [vp, P(d)],
+        "hfz3_finish_step": [vp],
+        "hfz3_read_field": [vp, i, i, i, vp],
+        "hfz3_levels": [vp, P(i)],
+        "hfz3_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -279,6 +297,101 @@ class Simulation:
         if self.h is not None:
             self.lib.hfz_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Simulation3:
+    """The PFC step in three dimensions (hfz3_*): one handle over a
+    torch-owned device workspace; fields n x n x n, indexed [z, y, x]."""
+
+    def __init__(self, cfg, device="cuda", stream=None):
+        self.lib = load()
+        self.p = make_params(cfg)
+        self.n = self.p.n
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = ctypes.c_size_t(0)
+        check(self.lib.hfz3_workspace_bytes(ctypes.byref(self.p), ctypes.byref(nb)), "hfz3_workspace_bytes")
+        self.nbytes = nb.value
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(self.lib.hfz3_init(ctypes.byref(self.p), _ptr(self.ws), self.nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hfz3_init")
+        self.h = h
+
+    def _dev(self, a):
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (self.n,) * 3:
+            raise ValueError(f"field of shape {tuple(t.shape)}, expected {(self.n,) * 3}")
+        return t
+
+    def _empty(self, n=None):
+        n = self.n if n is None else n
+        return torch.empty((n, n, n), dtype=torch.float64, device=self.device)
+
+    def set_state(self, rho, u, v, w):
+        t = [self._dev(x) for x in (rho, u, v, w)]
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.lib.hfz3_set_state(self.h, *[_ptr(x) for x in t]), "hfz3_set_state")
+
+    def get_state(self):
+        out = [self._empty() for _ in range(4)]
+        check(self.lib.hfz3_get_state(self.h, *[_ptr(x) for x in out]), "hfz3_get_state")
+        return out
+
+    def step(self, nsteps=1, raise_on_error=True):
+        st = Stats()
+        rc = self.lib.hfz3_step(self.h, int(nsteps), ctypes.byref(st))
+        if raise_on_error:
+            check(rc, "hfz3_step")
+        return (rc, st) if not raise_on_error else st
+
+    def energy(self):
+        out = (ctypes.c_double * 3)()
+        check(self.lib.hfz3_energy(self.h, out), "hfz3_energy")
+        return tuple(out)
+
+    def mass(self):
+        m = ctypes.c_double()
+        check(self.lib.hfz3_mass(self.h, ctypes.byref(m)), "hfz3_mass")
+        return m.value
+
+    def begin_step(self):
+        check(self.lib.hfz3_begin_step(self.h), "hfz3_begin_step")
+
+    def smooth(self, level, sweeps):
+        check(self.lib.hfz3_smooth(self.h, int(level), int(sweeps)), "hfz3_smooth")
+
+    def vcycle(self, count=1):
+        check(self.lib.hfz3_vcycle(self.h, int(count)), "hfz3_vcycle")
+
+    def residual(self):
+        r = ctypes.c_double()
+        check(self.lib.hfz3_residual(self.h, ctypes.byref(r)), "hfz3_residual")
+        return r.value
+
+    def finish_step(self):
+        check(self.lib.hfz3_finish_step(self.h), "hfz3_finish_step")
+
+    def levels(self):
+        lv = ctypes.c_int()
+        check(self.lib.hfz3_levels(self.h, ctypes.byref(lv)), "hfz3_levels")
+        return lv.value
+
+    def read(self, which, level, comp):
+        t = self._empty(self.n >> level)
+        check(self.lib.hfz3_read_field(self.h, which, level, comp, _ptr(t)), "hfz3_read_field")
+        return t
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.hfz3_destroy(self.h)
+            self.h = ctypes.c_void_p()
 
     def __del__(self):
         try:

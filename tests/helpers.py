@@ -2,7 +2,7 @@
 metrics, and the GPU availability switch."""
 import numpy as np
 
-from oracle import gradflow, walls
+from oracle import gradflow, three_d, walls
 from oracle.fas import Stepper
 
 
@@ -11,6 +11,10 @@ def oracle_stepper(cfg):
     its gradient-flow variant)."""
     if getattr(cfg, "gradflow", False):
         return gradflow.Stepper(cfg.base_model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
+    if getattr(cfg, "dims", 2) == 3:
+        kw = cfg.oracle_kwargs()
+        kw.pop("alpha")
+        return three_d.Stepper(cfg.n, cfg.h, cfg.s, cfg.alpha, **kw)
     if getattr(cfg, "walls", False):
         return walls.Stepper(cfg.n, cfg.h, cfg.s, cfg.alpha, **cfg.wall_oracle_kwargs())
     return Stepper(cfg.model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())

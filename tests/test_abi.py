@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "hfz.h")).read()
-    return sorted(set(re.findall(r"\b(hfz_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(hfz3?_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_library_exports_header_symbols():

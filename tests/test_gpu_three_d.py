@@ -1,0 +1,161 @@
+"""GPU parity of the PFC step in three dimensions (hfz3_*) against the CPU
+FP64 oracle (oracle/three_d.py): stage by stage, step by step, the uniform
+fixed point, and at 128^3 the properties the oracle evaluates in one pass."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import three_d as t3
+from tests.helpers import oracle_stepper, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def np_(t):
+    return t.cpu().numpy()
+
+
+def setup(n, seed=0, uamp=0.02):
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v, w = workloads.pfc3d(n, seed=seed, uamp=uamp)
+    sim = pkg.Simulation3(cfg)
+    sim.set_state(rho, u, v, w)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v, w)
+    return cfg, sim, ora
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_source_and_coefficients(n):
+    cfg, sim, ora = setup(n, seed=1)
+    assert rel_err(np_(sim.read(5, 0, 0)), ora.g[4]) < 1e-12
+    assert rel_err(np_(sim.read(5, 0, 1)), ora.g[5]) < 1e-12
+    sim.begin_step()
+    S, om = ora.build_source()
+    for c in range(6):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+    sol = ora.solver(om)
+    assert sim.levels() == len(sol.levels)
+    for l, lev in enumerate(sol.levels):
+        assert rel_err(np_(sim.read(3, l, 0)), lev.rho_k) < 1e-13, l
+        for c in range(3):
+            assert rel_err(np_(sim.read(3, l, 1 + c)), lev.omega_k[c]) < 1e-12, (l, c)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_sweeps_and_residual(n):
+    cfg, sim, ora = setup(n, seed=2)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    lev = sol.levels[0]
+    g = ora.g.copy()
+    r0 = sol.resnorm(g, S, lev)
+    assert abs(sim.residual() - r0) < 1e-11 * r0
+    sim.smooth(0, 1)
+    t3.sweep(g, S, lev, cfg.w)
+    for c in range(6):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    sim.smooth(0, 2)
+    t3.sweep(g, S, lev, cfg.w)
+    t3.sweep(g, S, lev, cfg.w)
+    for c in range(6):
+        assert rel_err(np_(sim.read(0, 0, c)), g[c]) < 1e-12, c
+    r2 = sol.resnorm(g, S, lev)
+    assert abs(sim.residual() - r2) < 1e-10 * r2
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_vcycles(n):
+    cfg, sim, ora = setup(n, seed=3)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    g = ora.g.copy()
+    for k in range(3):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(6)]
+        assert max(errs) < 1e-11, (k, errs)
+    r = sol.resnorm(g, S, sol.levels[0])
+    assert abs(sim.residual() - r) < 1e-9 * r
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_steps(n):
+    cfg, sim, ora = setup(n, seed=4)
+    m0 = sim.mass()
+    for k in range(3):
+        st = sim.step(1)
+        c, r = ora.step()
+        assert abs(st.cycles_last - c) <= 1, (k, st.cycles_last, c)
+        assert st.residual_last <= cfg.tol
+        rg, ug, vg, wg = [np_(x) for x in sim.get_state()]
+        assert rel_err(rg, ora.g[0]) < 1e-10, k
+        vs = np.abs(ora.g[1:4]).max()
+        for x, y in zip((ug, vg, wg), ora.g[1:4]):
+            assert np.abs(x - y).max() < 1e-10 * vs, k
+    E, Eo = sim.energy(), ora.energy()
+    assert abs(E[0] - Eo[0]) < 1e-10 * abs(Eo[0])
+    assert abs(sim.mass() - m0) < 1e-13 * abs(m0)
+
+
+def test_uniform_state_is_a_fixed_point():
+    import paper_1503_07416_amd as pkg
+    n = 16
+    cfg, _, _, _, _ = workloads.pfc3d(n)
+    sim = pkg.Simulation3(cfg)
+    z = np.zeros((n, n, n))
+    rho = np.full((n, n, n), 1.3)
+    sim.set_state(rho, z + 0.1, z - 0.2, z + 0.05)
+    st = sim.step(2)
+    assert st.cycles_total == 0
+    r, u, v, w = [np_(x) for x in sim.get_state()]
+    assert np.abs(r - rho).max() < 1e-14 and np.abs(u - 0.1).max() < 1e-14
+
+
+def test_full_size_step():
+    """128^3: the GPU's iterate solves the oracle's system to tol, the end of the
+    step is the oracle's continuity update, staged == benchmarked step."""
+    import paper_1503_07416_amd as pkg
+    n = 128
+    cfg, rho, u, v, w = workloads.pfc3d(n)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v, w)
+    S, om = ora.build_source()
+    lev = ora.solver(om).levels[0]
+    print("pfc3d 128: begin", flush=True)
+    sim = pkg.Simulation3(cfg)
+    sim.set_state(rho, u, v, w)
+    sim.begin_step()
+    for c in range(6):
+        if np.abs(S[c]).max() > 0:
+            assert rel_err(np_(sim.read(1, 0, c)), S[c]) < 1e-12, c
+    r = sim.residual()
+    cycles = 0
+    while r > cfg.tol and cycles < cfg.max_cycles:
+        sim.vcycle(1)
+        cycles += 1
+        r = sim.residual()
+    assert r <= cfg.tol
+    g = np.stack([np_(sim.read(0, 0, c)) for c in range(6)])
+    dd = S - t3.N(g, lev)
+    r_ora = np.sqrt(lev.h ** 3 * float(np.sum(dd * dd)))
+    # the two evaluations of S - N(g) differ by rounding in each of the 6 x 2M
+    # rows (terms up to ~1/h^2 cancelling to ~1e-11): a few 1e-13 in the norm
+    assert r_ora <= cfg.tol and abs(r_ora - r) <= 1e-2 * r + 1e-12, (r_ora, r)
+    sim.finish_step()
+    staged = [np_(x) for x in sim.get_state()]
+    rho1 = S[0] - cfg.s / (4 * cfg.h) * sum(t3.sh(rho * g[1 + a], t3.AX[a], 1) - t3.sh(rho * g[1 + a], t3.AX[a], -1)
+                                            for a in range(3))
+    assert rel_err(staged[0], rho1) < 1e-12
+    sim.close()
+    sim = pkg.Simulation3(cfg)
+    sim.set_state(rho, u, v, w)
+    st = sim.step(1)
+    print(f"pfc3d 128: cycles {st.cycles_last} (staged {cycles}), residual {st.residual_last:.3e}", flush=True)
+    assert st.cycles_last == cycles
+    for x, y in zip([np_(t) for t in sim.get_state()], staged):
+        assert np.abs(x - y).max() <= 1e-12 * max(np.abs(y).max(), 1e-30)
+    sim.close()

@@ -55,6 +55,7 @@ class Config:
     sigma: float = 1.0
     continuity_fix: bool = True
     precision: str = "fp64"    # "fp64" or "mixed"
+    dims: int = 2              # 3: the PFC step on an n^3 grid
     walls: bool = False        # PFC in a channel: walls at y = 0 and y = n h
     u_bot: float = 0.0         # channel: wall speeds (u on the walls, v = 0)
     u_top: float = 0.0
@@ -78,7 +79,7 @@ class Config:
             d.pop("alpha")
         if self.gradflow:
             d.pop("gamma"); d.pop("sigma")
-        d.pop("walls"); d.pop("u_bot"); d.pop("u_top")
+        d.pop("walls"); d.pop("u_bot"); d.pop("u_top"); d.pop("dims")
         return d
 
     def wall_oracle_kwargs(self):
@@ -152,6 +153,21 @@ def channel(n=256, u_wall=0.1, seed=None, amp=0.0, **kw):
     z = np.zeros_like(rho)
     cfg = Config("pfc", n, NANO_H, 0.02, alpha=1.0 - NANO_EPS, walls=True, u_bot=-u_wall, u_top=u_wall, **kw)
     return cfg, rho, z.copy(), z.copy()
+
+
+def pfc3d(n=128, seed=0, h=0.5, s=0.01, amp=0.05, uamp=0.0, **kw):
+    """The PFC step in three dimensions: the PFC freezing run's law
+    (eps = 0.025, rho = rho_bar + amp U(-1, 1)) on n^3 nodes, h = 0.5,
+    s = 0.01 (s/h^4 = 0.16: the damped block smoother needs s/h^4 below about
+    0.5 in 3D); with uamp, velocities uamp N(0, 1).  Fields [z, y, x]."""
+    rng = np.random.default_rng(seed)
+    rho = PFC_RHO_BAR + amp * rng.uniform(-1.0, 1.0, (n, n, n))
+    if uamp:
+        u, v, w = uamp * rng.standard_normal((3, n, n, n))
+    else:
+        u = v = w = np.zeros((n, n, n))
+    cfg = Config("pfc", n, h, s, dims=3, **kw)
+    return cfg, rho, u, v, w
 
 
 def random_velocity(n, seed, amp):
