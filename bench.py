@@ -31,7 +31,10 @@ Also reported on the same JSON line:
                 channel of 256 x 257 nodes with walls at rest and at -+0.1 and
                 -+0.5, the 13-atom hexagonal nucleate in the liquid: steps/s,
                 V-cycles per step, energy (non-increasing with resting walls),
-                and the roofline of its finest-level smoother.
+                and the roofline of its finest-level smoother;
+  three_d       the PFC step in three dimensions at 128^3 (h = 0.5, s = 0.01):
+                steps/s, V-cycles per step, energy and mass checks, and the
+                roofline of its smoother (and at 256^3).
 """
 import argparse
 import dataclasses
@@ -50,6 +53,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one damped red-black sweep per fine node: read g (5),
 # f (5), rho^k, omega^k, write g (5), FP64
 SWEEP_BYTES_PFC = 17 * 8
+# 3D PFC: read g 6, f 6, rho^k, omega^k 3; write g 6
+SWEEP_BYTES_3D = 22 * 8
 # the gradient flow: read g, f and write g with 3 (PFC) or 2 (CDFT) unknowns
 SWEEP_BYTES_GF = {"pfc_gf": 9 * 8, "cdft_gf": 6 * 8}
 KERNEL_SOURCES = ["paper_1503_07416_amd/csrc/tile.hpp", "paper_1503_07416_amd/csrc/stencil.hpp",
@@ -73,6 +78,7 @@ def parse():
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
     ap.add_argument("--gradflow-only", action="store_true", help="only the gradient-flow workloads (for profiles)")
     ap.add_argument("--channel-only", action="store_true", help="only the channel workloads (for profiles)")
+    ap.add_argument("--three-d-only", action="store_true", help="only the 3D workload (for profiles)")
     ap.add_argument("--convergence", action="store_true",
                     help="the paper's convergence study instead of the benchmark (minutes of GPU time)")
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
@@ -479,6 +485,64 @@ def run_channel(steps=50, check_steps=10, n=256):
     return out
 
 
+def smoother3_roofline(sim, n, sweeps=10):
+    """Average time of one damped red-black sweep of the 3D smoother (two
+    colour launches), HIP events on the library's stream."""
+    import torch
+    sim.begin_step()
+    sim.smooth(0, 1)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    sim.smooth(0, sweeps)
+    stop.record(sim.stream)
+    stop.synchronize()
+    t = start.elapsed_time(stop) * 1e-3 / sweeps
+    nbytes = SWEEP_BYTES_3D * n ** 3
+    ach = nbytes / t / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k3_smooth (both colours of one sweep)", "sweep_us": round(t * 1e6, 3),
+            "bytes_per_sweep": nbytes}
+
+
+def run_three_d(steps=20, check_steps=5, n=128):
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v, w = workloads.pfc3d(n)
+    sim = pkg.Simulation3(cfg, device="cuda:0")
+    sim.set_state(rho, u, v, w)
+    sim.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E, M = [sim.energy()[0]], [sim.mass()]
+    for _ in range(check_steps):
+        sim.step(1)
+        E.append(sim.energy()[0])
+        M.append(sim.mass())
+    out = {"workload": f"PFC 3D {n}^3 h=0.5 s=0.01 eps=0.025 FAS V(2,2) tol 1e-10 FP64, {steps} timed steps "
+                       f"(+{check_steps} checked)",
+           "steps_per_s": round(steps / dt, 3), "ms_per_step": round(1e3 * dt / steps, 3),
+           "vcycles_per_step": round(st.cycles_total / steps, 3), "final_residual": st.residual_last,
+           "energy_increases": sum(1 for a, b in zip(E[:-1], E[1:]) if b > a + 1e-12 * abs(a)),
+           "mass_rel_drift": max(abs(m - M[0]) for m in M) / abs(M[0]),
+           "roofline": smoother3_roofline(sim, n)}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    cfg2, rho2, u2, v2, w2 = workloads.pfc3d(256)
+    sim = pkg.Simulation3(cfg2, device="cuda:0")
+    sim.set_state(rho2, u2, v2, w2)
+    out["roofline_256"] = smoother3_roofline(sim, 256, sweeps=4)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_convergence(sizes, tf):
     """The paper's convergence study (Sec. 6.1): smooth initial density on
     [0,32)^2, u = 0, refinement path s = 0.025 h^2 to t_f; CDFT with nu = 1 and
@@ -561,6 +625,9 @@ def main():
     if a.channel_only:
         print(json.dumps({"channel": run_channel()}))
         return
+    if a.three_d_only:
+        print(json.dumps({"three_d": run_three_d()}))
+        return
     if a.mixed_only:
         import torch
         import workloads
@@ -618,6 +685,8 @@ def main():
         out["gradflow"] = run_gradflow()
         torch.cuda.empty_cache()
         out["channel"] = run_channel()
+        torch.cuda.empty_cache()
+        out["three_d"] = run_three_d()
     print(json.dumps(out))
 
 
