@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--gradflow-only", action="store_true", help="only the gradient-flow workloads (for profiles)")
     ap.add_argument("--channel-only", action="store_true", help="only the channel workloads (for profiles)")
     ap.add_argument("--three-d-only", action="store_true", help="only the 3D workload (for profiles)")
+    ap.add_argument("--counter-probe-3d", action="store_true",
+                    help="only launch the 3D smoothers at 128^3 and a reference copy kernel (for counter runs)")
     ap.add_argument("--convergence", action="store_true",
                     help="the paper's convergence study instead of the benchmark (minutes of GPU time)")
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
@@ -161,6 +163,31 @@ def counter_probe(n, shape):
     torch.cuda.synchronize()
     print(json.dumps({"counter_probe": True, "n": n, "smoother_launches": 5, "copy_bytes_each_way": 2**30,
                       "tile_shape": "x".join(map(str, sim.tile_shape(0))), "source_hash": source_hash()}))
+
+
+def counter_probe_3d(n=128):
+    """Four sweeps at n^3 by the z-marching tiled kernel, four by the two
+    per-colour kernels (HFZ3_TILES=0), and three launches of the reference copy
+    kernel, for the FETCH_SIZE / WRITE_SIZE counter runs of the 3D smoother."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    for tiles in ("128", "0"):
+        os.environ["HFZ3_TILES"] = tiles
+        cfg, rho, u, v, w = workloads.pfc3d(n)
+        sim = pkg.Simulation3(cfg, device="cuda:0")
+        sim.set_state(rho, u, v, w)
+        sim.begin_step()
+        sim.smooth(0, 4)
+        torch.cuda.synchronize()
+        sim.close()
+    os.environ.pop("HFZ3_TILES")
+    x = torch.ones(2**27, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_probe_3d": True, "n": n, "sweeps_each": 4, "copy_bytes_each_way": 2**30}))
 
 
 def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
@@ -486,8 +513,9 @@ def run_channel(steps=50, check_steps=10, n=256):
 
 
 def smoother3_roofline(sim, n, sweeps=10):
-    """Average time of one damped red-black sweep of the 3D smoother (two
-    colour launches), HIP events on the library's stream."""
+    """Average time of one damped red-black sweep of the 3D smoother (one
+    launch of the z-marching tiled kernel from 32^3 up), HIP events on the
+    library's stream."""
     import torch
     sim.begin_step()
     sim.smooth(0, 1)
@@ -501,7 +529,7 @@ def smoother3_roofline(sim, n, sweeps=10):
     ach = nbytes / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k3_smooth (both colours of one sweep)", "sweep_us": round(t * 1e6, 3),
+            "kernel": "k3_sweep_tile (both colours of one sweep)", "sweep_us": round(t * 1e6, 3),
             "bytes_per_sweep": nbytes}
 
 
@@ -607,6 +635,9 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "one GPU only: the solver runs on a single device; --gpus must be 1"}))
         sys.exit(2)
+    if a.counter_probe_3d:
+        counter_probe_3d()
+        return
     if a.counter_probe:
         counter_probe(a.n, a.probe_tile_shape)
         return

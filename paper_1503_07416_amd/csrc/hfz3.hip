@@ -15,15 +15,18 @@
 // full weighting and trilinear prolongation, coarsest grid swept a fixed
 // number of times, stop on (h^3 sum d^2)^(1/2) <= tol tested on the device.
 //
-// One thread per node (per node of a colour in the smoother); the levels are
-// bandwidth- or latency-bound, the neighbour reads served by the caches.
+// One thread per node in the per-level kernels (per node of a colour in the
+// small levels' smoother); on the large levels one launch of a z-marching
+// tiled kernel does a whole sweep through an LDS window (k3_sweep_tile).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "hfz.h"
@@ -37,6 +40,7 @@ struct Lvl {
   double* f[NC];   // right-hand side (level 0: the source S)
   double* g0[NC];  // restricted iterate R g (coarse levels)
   double* d[NC];   // residual f - N(g) before restriction
+  double* gb[NC];  // second iterate buffer of the tiled sweep (levels it runs on)
   double* rk;      // frozen rho^k
   double* om[3];   // frozen omega^k
   int n, lg;       // n = 2^lg nodes per direction
@@ -103,25 +107,57 @@ __device__ __forceinline__ void rows(const Lvl& L, const Phys& P, const double* 
   out[5] = g[5][q.p] - (sum6(g[0], q) - 6.0 * g[0][q.p]) * ih2;
 }
 
-// Damped block update at node q (module comment).
-__device__ __forceinline__ void block(const Lvl& L, const Phys& P, const Nbr& q, double* out) {
-  const double h = L.h, s = P.s, c4 = s / (4.0 * h), c2 = s / (2.0 * h), ih2 = 1.0 / (h * h);
-  const double* rk = L.rk;
-  double* const* g = L.g;
-  const double* u = g[1];
-  const double* v = g[2];
-  const double* w = g[3];
-  const double* mu = g[4];
-  const double rh = L.f[0][q.p] - c4 * (rk[q.e] * u[q.e] - rk[q.w] * u[q.w] + rk[q.n] * v[q.n] - rk[q.s] * v[q.s] +
-                                        rk[q.u] * w[q.u] - rk[q.d] * w[q.d]);
-  const double rkP = rk[q.p];
+// rho^k on the 7-point stencil, omega^k and f at one node.
+struct Coef {
+  double rk[7];
+  double om[3];
+  double f[NC];
+};
+
+__device__ __forceinline__ void load_coef(const Lvl& L, const Nbr& q, Coef& C) {
+  const int k[7] = {q.p, q.e, q.w, q.n, q.s, q.u, q.d};
+#pragma unroll
+  for (int t = 0; t < 7; ++t) C.rk[t] = L.rk[k[t]];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) C.om[c] = L.om[c][q.p];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) C.f[c] = L.f[c][q.p];
+}
+
+// The values a block update reads, gathered: v[c][k] is component c at the
+// node (k = 0) and its neighbours +x, -x, +y, -y, +z, -z (k = 1..6); rk the
+// same for rho^k; om and f at the node.
+struct Gath {
+  double v[NC][7];
+  double rk[7];
+  double om[3];
+  double f[NC];
+};
+
+__device__ __forceinline__ double s6(const double* a) { return a[1] + a[2] + a[3] + a[4] + a[5] + a[6]; }
+
+__device__ __forceinline__ double q2v(const Gath& G, int k) {
+  return G.v[1][k] * G.v[1][k] + G.v[2][k] * G.v[2][k] + G.v[3][k] * G.v[3][k];
+}
+
+// Damped block update from gathered values (module comment).
+__device__ __forceinline__ void block_vals(const Gath& G, double h, const Phys& P, double* out) {
+  const double s = P.s, c4 = s / (4.0 * h), c2 = s / (2.0 * h), ih2 = 1.0 / (h * h);
+  const double* rk = G.rk;
+  const double* u = G.v[1];
+  const double* v = G.v[2];
+  const double* w = G.v[3];
+  const double* mu = G.v[4];
+  const double rh = G.f[0] - c4 * (rk[1] * u[1] - rk[2] * u[2] + rk[3] * v[3] - rk[4] * v[4] + rk[5] * w[5] -
+                                   rk[6] * w[6]);
+  const double rkP = rk[0];
   const double cg = 0.5 * s * P.gamma * ih2;
   const double a = rkP + 6.0 * cg;
   const double bs = 0.5 * s * P.sigma * rkP;
-  const double b0 = bs * L.om[0][q.p], b1 = bs * L.om[1][q.p], b2 = bs * L.om[2][q.p];
-  const double r0 = L.f[1][q.p] - c4 * rkP * (q2(g, q.e) - q2(g, q.w)) - c2 * rkP * (mu[q.e] - mu[q.w]) + cg * sum6(u, q);
-  const double r1 = L.f[2][q.p] - c4 * rkP * (q2(g, q.n) - q2(g, q.s)) - c2 * rkP * (mu[q.n] - mu[q.s]) + cg * sum6(v, q);
-  const double r2 = L.f[3][q.p] - c4 * rkP * (q2(g, q.u) - q2(g, q.d)) - c2 * rkP * (mu[q.u] - mu[q.d]) + cg * sum6(w, q);
+  const double b0 = bs * G.om[0], b1 = bs * G.om[1], b2 = bs * G.om[2];
+  const double r0 = G.f[1] - c4 * rkP * (q2v(G, 1) - q2v(G, 2)) - c2 * rkP * (mu[1] - mu[2]) + cg * s6(u);
+  const double r1 = G.f[2] - c4 * rkP * (q2v(G, 3) - q2v(G, 4)) - c2 * rkP * (mu[3] - mu[4]) + cg * s6(v);
+  const double r2 = G.f[3] - c4 * rkP * (q2v(G, 5) - q2v(G, 6)) - c2 * rkP * (mu[5] - mu[6]) + cg * s6(w);
   const double bb = b0 * b0 + b1 * b1 + b2 * b2;
   const double br = b0 * r0 + b1 * r1 + b2 * r2;
   const double x0 = b1 * r2 - b2 * r1, x1 = b2 * r0 - b0 * r2, x2 = b0 * r1 - b1 * r0;
@@ -129,31 +165,60 @@ __device__ __forceinline__ void block(const Lvl& L, const Phys& P, const Nbr& q,
   const double uh = (a * a * r0 - a * x0 + br * b0) / den;
   const double vh = (a * a * r1 - a * x1 + br * b1) / den;
   const double wh = (a * a * r2 - a * x2 + br * b2) / den;
-  const double kh = L.f[5][q.p] + sum6(g[0], q) * ih2 - 6.0 * rh * ih2;
-  const double pl = g[0][q.p] - 1.5;
-  const double mh = L.f[4][q.p] + (P.alpha + pl * pl) * (rh - 1.5) - (2.0 / 3.0) * pl * pl * pl +
-                    sum6(g[5], q) * ih2 - 6.0 * kh * ih2;
+  const double kh = G.f[5] + s6(G.v[0]) * ih2 - 6.0 * rh * ih2;
+  const double pl = G.v[0][0] - 1.5;
+  const double mh = G.f[4] + (P.alpha + pl * pl) * (rh - 1.5) - (2.0 / 3.0) * pl * pl * pl + s6(G.v[5]) * ih2 -
+                    6.0 * kh * ih2;
   const double wd = P.w, w1 = 1.0 - P.w;
-  out[0] = w1 * rh + wd * g[0][q.p];
-  out[1] = w1 * uh + wd * u[q.p];
-  out[2] = w1 * vh + wd * v[q.p];
-  out[3] = w1 * wh + wd * w[q.p];
-  out[4] = w1 * mh + wd * mu[q.p];
-  out[5] = w1 * kh + wd * g[5][q.p];
+  out[0] = w1 * rh + wd * G.v[0][0];
+  out[1] = w1 * uh + wd * u[0];
+  out[2] = w1 * vh + wd * v[0];
+  out[3] = w1 * wh + wd * w[0];
+  out[4] = w1 * mh + wd * mu[0];
+  out[5] = w1 * kh + wd * G.v[5][0];
 }
 
-// 27-point full weighting at coarse node (I, J, K) = fine (2I, 2J, 2K).
+__device__ __forceinline__ void put_coef(const Coef& C, Gath& G) {
+#pragma unroll
+  for (int k = 0; k < 7; ++k) G.rk[k] = C.rk[k];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) G.om[c] = C.om[c];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) G.f[c] = C.f[c];
+}
+
+// Damped block update at node q of the iterate g.
+__device__ __forceinline__ void block(const Lvl& L, const Phys& P, double* const* g, const Nbr& q, double* out) {
+  Coef C;
+  load_coef(L, q, C);
+  Gath G;
+  put_coef(C, G);
+  const int k[7] = {q.p, q.e, q.w, q.n, q.s, q.u, q.d};
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int t = 0; t < 7; ++t) G.v[c][t] = g[c][k[t]];
+  block_vals(G, L.h, P, out);
+}
+
+// 27-point full weighting at coarse node (I, J, K) = fine (2I, 2J, 2K).  Each
+// fine row's values 2I - 1, 2I, 2I + 1 come from two aligned 16-byte vectors,
+// the pairs (2I - 2, 2I - 1) and (2I, 2I + 1).
 __device__ __forceinline__ double fw27(const double* f, int I, int J, int K, int lgf) {
   const int m = (1 << lgf) - 1;
   double acc = 0.0;
+#pragma unroll
   for (int dk = -1; dk <= 1; ++dk) {
     const int k = (2 * K + dk) & m;
     const double wk = dk == 0 ? 2.0 : 1.0;
+#pragma unroll
     for (int dj = -1; dj <= 1; ++dj) {
       const int j = (2 * J + dj) & m;
       const double wj = dj == 0 ? 2.0 : 1.0;
       const int row = ((k << lgf) + j) << lgf;
-      acc += wk * wj * (f[row + ((2 * I - 1) & m)] + 2.0 * f[row + 2 * I] + f[row + ((2 * I + 1) & m)]);
+      const double2 a = *reinterpret_cast<const double2*>(f + row + ((2 * I - 2) & m));
+      const double2 v = *reinterpret_cast<const double2*>(f + row + 2 * I);
+      acc += wk * wj * (a.y + 2.0 * v.x + v.y);
     }
   }
   return acc * (1.0 / 64.0);
@@ -164,11 +229,16 @@ struct Idx {
 };
 
 // Thread -> node of an n^3 level in 2D launch geometry (x in blockIdx.x, the
-// (y, z) rows in blockIdx.y).
+// (y, z) rows in blockIdx.y).  Workgroups are renumbered so that each XCD
+// (workgroups are dealt to the 8 XCDs in turn) takes a contiguous range of
+// rows, whose y and z neighbour rows then mostly sit in that XCD's L2.
 __device__ __forceinline__ Idx node(int n, int lg) {
   Idx x;
-  x.i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = blockIdx.y * blockDim.y + threadIdx.y;
+  const int nbx = (int)gridDim.x, nb = nbx * (int)gridDim.y;
+  const int bid = (int)blockIdx.y * nbx + (int)blockIdx.x;
+  const int b = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+  x.i = (b % nbx) * blockDim.x + threadIdx.x;
+  const int row = (b / nbx) * blockDim.y + threadIdx.y;
   x.j = row & (n - 1);
   x.l = row >> lg;
   x.ok = x.i < n && row < n * n;
@@ -215,6 +285,7 @@ __global__ void k3_restrict_coef(Lvl F, Lvl C) {
   if (!x.ok) return;
   const int pc = (((x.l << C.lg) + x.j) << C.lg) + x.i;
   C.rk[pc] = fw27(F.rk, x.i, x.j, x.l, F.lg);
+#pragma unroll
   for (int c = 0; c < 3; ++c) C.om[c][pc] = fw27(F.om[c], x.i, x.j, x.l, F.lg);
 }
 
@@ -230,74 +301,438 @@ __global__ void k3_smooth(Lvl L, Phys P, int colour) {
   const int i = 2 * t + ((j + l + colour) & 1);
   const Nbr q = nbr(i, j, l, L.lg);
   double out[NC];
-  block(L, P, q, out);
+  block(L, P, L.g, q, out);
 #pragma unroll
   for (int c = 0; c < NC; ++c) L.g[c][q.p] = out[c];
 }
 
-// d = f - N(g).
-__global__ void k3_residual_field(Lvl L, Phys P) {
+// One damped red-black sweep in one launch (levels from 128^3 up by default).
+//
+// A workgroup owns a TX x TY tile of the x-y plane and ZC planes in z and
+// marches up them.  The sweep's starting iterate gin passes through a
+// four-plane LDS window over the tile plus a two-node ring; each window plane
+// is read from gin once.  At plane l the workgroup
+//   * updates the red nodes (i + j + l + 1 even) of plane l + 1 over the tile
+//     and a one-node ring, in place in the window: a red update reads only
+//     black values of its own plane and of planes l and l + 2, and its own old
+//     value, so in-place writes race with no other red update;
+//   * updates the black nodes of plane l over the tile from the window (their
+//     neighbours are red, now new) and their own old value, and writes plane
+//     l of the tile, red and black, to gout.
+// Before its first plane it updates the red nodes of planes z0 - 1 and z0.
+// The ring's red nodes are recomputed by the workgroups on both sides; gin is
+// never written, so all of them read the same starting iterate.  The next
+// window plane is loaded into registers one plane ahead, each phase's
+// coefficients (rho^k at the 7-point stencil, omega^k, f) one phase ahead.
+// Workgroups are numbered so that each XCD (workgroups are dealt to the 8
+// XCDs in turn) takes a contiguous range of tiles, whose rings then overlap
+// in that XCD's L2.
+constexpr int TX3 = 32, TY3 = 16, ZC3 = 16, NT3 = 512;
+constexpr int WX3 = TX3 + 4, WY3 = TY3 + 4, WP3 = WX3 * WY3;  // window plane (tile + 2-node ring)
+constexpr int RX3 = TX3 + 2, RY3 = TY3 + 2;                    // red region (tile + 1-node ring)
+constexpr int NRED3 = RX3 * RY3 / 2, NBLK3 = TX3 * TY3 / 2;   // red region nodes, tile nodes of a colour
+constexpr int LDPT3 = (WP3 + NT3 - 1) / NT3;                   // window nodes per thread
+static_assert(NRED3 <= NT3 && 2 * NBLK3 == NT3 && RX3 % 2 == 0 && TX3 % 2 == 0, "tile shape");
+
+struct G6 {
+  double* c[NC];
+};
+
+// Window coordinates (a, b) of the red node r (x + y + p even, par = x0 + y0 +
+// p) of the tile plus one-node ring; the ring offsets are even and n is even,
+// so the periodic wrap keeps parities.
+__device__ __forceinline__ void red_pos(int r, int par, int& a, int& b) {
+  b = r / (RX3 / 2);
+  a = 2 * (r - b * (RX3 / 2)) + ((par + b) & 1);
+  a += 1;
+  b += 1;
+}
+
+// Window coordinates of the tile node r whose x + y + p has the parity of par.
+__device__ __forceinline__ void tile_pos(int r, int par, int& a, int& b) {
+  b = r / (TX3 / 2);
+  a = 2 * (r - b * (TX3 / 2)) + ((par + b) & 1);
+  a += 2;
+  b += 2;
+}
+
+__global__ __launch_bounds__(NT3) void k3_sweep_tile(Lvl L, G6 gin, G6 gout, Phys P) {
   if (halted(P.halt)) return;
-  const Idx x = node(L.n, L.lg);
-  if (!x.ok) return;
-  const Nbr q = nbr(x.i, x.j, x.l, L.lg);
+  __shared__ double win[4][NC][WP3];
+  const int m = L.n - 1, lg = L.lg;
+  // XCD-contiguous tile numbering
+  const int ntx = L.n / TX3, nty = L.n / TY3, nb = ntx * nty * (L.n / ZC3);
+  const int bid = (int)blockIdx.x;
+  const int tid = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int tx = tid % ntx, ty = (tid / ntx) % nty, tz = tid / (ntx * nty);
+  const int x0 = tx * TX3, y0 = ty * TY3, z0 = tz * ZC3;
+  const int t = threadIdx.x;
+  auto slot = [&](int p) { return (p - z0 + 8) & 3; };
+  auto gidx = [&](int a, int b, int p) { return ((((p & m) << lg) + ((y0 - 2 + b) & m)) << lg) + ((x0 - 2 + a) & m); };
+  auto gnbr = [&](int a, int b, int p) { return nbr((x0 - 2 + a) & m, (y0 - 2 + b) & m, p & m, lg); };
+  // window loads through registers
+  double pre[LDPT3][NC];
+  auto fetch = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < LDPT3; ++k) {
+      const int w = t + k * NT3;
+      if (w < WP3) {
+        const int b = w / WX3, a = w - b * WX3;
+        const int gi = gidx(a, b, p);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pre[k][c] = gin.c[c][gi];
+      }
+    }
+  };
+  auto store = [&](int p) {
+    const int sl = slot(p);
+#pragma unroll
+    for (int k = 0; k < LDPT3; ++k) {
+      const int w = t + k * NT3;
+      if (w < WP3) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) win[sl][c][w] = pre[k][c];
+      }
+    }
+  };
+  // the update of the node at window (a, b) of plane p from the window
+  auto update = [&](int a, int b, int p, const Coef& C, double* out) {
+    const int w = b * WX3 + a, sc = slot(p), su = slot(p + 1), sd = slot(p - 1);
+    Gath G;
+    put_coef(C, G);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      G.v[c][0] = win[sc][c][w];
+      G.v[c][1] = win[sc][c][w + 1];
+      G.v[c][2] = win[sc][c][w - 1];
+      G.v[c][3] = win[sc][c][w + WX3];
+      G.v[c][4] = win[sc][c][w - WX3];
+      G.v[c][5] = win[su][c][w];
+      G.v[c][6] = win[sd][c][w];
+    }
+    block_vals(G, L.h, P, out);
+  };
+  // red node of this thread at plane p: coefficients, then the in-place update
+  const bool has_red = t < NRED3;
+  auto red_coef = [&](int p, Coef& C) {
+    if (has_red) {
+      int a, b;
+      red_pos(t, x0 + y0 + p, a, b);
+      load_coef(L, gnbr(a, b, p), C);
+    }
+  };
+  auto red_update = [&](int p, const Coef& C) {
+    if (has_red) {
+      int a, b;
+      red_pos(t, x0 + y0 + p, a, b);
+      double out[NC];
+      update(a, b, p, C, out);
+      const int w = b * WX3 + a, sc = slot(p);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) win[sc][c][w] = out[c];
+    }
+  };
+  // black half of the threads: the black tile nodes; red half: copies the red tile nodes
+  const bool is_black = t < NBLK3;
+  const int r = is_black ? t : t - NBLK3;
+  auto black_coef = [&](int p, Coef& C) {
+    if (is_black) {
+      int a, b;
+      tile_pos(r, x0 + y0 + p + 1, a, b);
+      load_coef(L, gnbr(a, b, p), C);
+    }
+  };
+  auto finish_plane = [&](int p, const Coef& C) {
+    int a, b;
+    tile_pos(r, x0 + y0 + p + (is_black ? 1 : 0), a, b);
+    double out[NC];
+    if (is_black) {
+      update(a, b, p, C, out);
+    } else {
+      const int w = b * WX3 + a, sc = slot(p);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) out[c] = win[sc][c][w];
+    }
+    const int gi = gidx(a, b, p);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) gout.c[c][gi] = out[c];
+  };
+
+  // prologue: planes z0 - 2 .. z0 + 1, red of planes z0 - 1 and z0
+  Coef cr, cb;
+  {
+    Coef c0, c1;
+    red_coef(z0 - 1, c0);
+    red_coef(z0, c1);
+    for (int p = z0 - 2; p <= z0 + 1; ++p) {
+      fetch(p);
+      store(p);
+    }
+    __syncthreads();
+    red_update(z0 - 1, c0);
+    red_update(z0, c1);
+  }
+  red_coef(z0 + 1, cr);
+  fetch(z0 + 2);
+  __syncthreads();
+  // each phase's coefficients are loaded during the phase before it
+  for (int k = 0; k < ZC3; ++k) {
+    const int l = z0 + k;
+    store(l + 2);  // its slot held plane l - 2, last read before the previous barrier
+    if (k + 1 < ZC3) fetch(l + 3);
+    black_coef(l, cb);
+    __syncthreads();
+    red_update(l + 1, cr);
+    if (k + 1 < ZC3) red_coef(l + 2, cr);
+    __syncthreads();
+    finish_plane(l, cb);
+    __syncthreads();
+  }
+}
+
+// d = f - N(g).
+__device__ __forceinline__ void residual_node(const Lvl& L, const Phys& P, int i, int j, int l) {
+  const Nbr q = nbr(i, j, l, L.lg);
   double nv[NC];
   rows(L, P, L.g, q, nv);
 #pragma unroll
   for (int c = 0; c < NC; ++c) L.d[c][q.p] = L.f[c][q.p] - nv[c];
 }
 
-// g_c = g0_c = R g, f_c = R d.
+__global__ void k3_residual_field(Lvl L, Phys P) {
+  if (halted(P.halt)) return;
+  const Idx x = node(L.n, L.lg);
+  if (!x.ok) return;
+  residual_node(L, P, x.i, x.j, x.l);
+}
+
+// g_c = g0_c = R g, f_c = R d at coarse node (I, J, K).
+__device__ __forceinline__ void restrict_node(const Lvl& F, const Lvl& C, int I, int J, int K) {
+  const int pc = (((K << C.lg) + J) << C.lg) + I;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double gr = fw27(F.g[c], I, J, K, F.lg);
+    C.g[c][pc] = gr;
+    C.g0[c][pc] = gr;
+    C.f[c][pc] = fw27(F.d[c], I, J, K, F.lg);
+  }
+}
+
 __global__ void k3_restrict(Lvl F, Lvl C, const int* halt) {
   if (halted(halt)) return;
   const Idx x = node(C.n, C.lg);
   if (!x.ok) return;
-  const int pc = (((x.l << C.lg) + x.j) << C.lg) + x.i;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const double gr = fw27(F.g[c], x.i, x.j, x.l, F.lg);
-    C.g[c][pc] = gr;
-    C.g0[c][pc] = gr;
-    C.f[c][pc] = fw27(F.d[c], x.i, x.j, x.l, F.lg);
-  }
+  restrict_node(F, C, x.i, x.j, x.l);
 }
 
 // f_c += N_c(R g).
-__global__ void k3_fas_rhs(Lvl C, Phys P) {
-  if (halted(P.halt)) return;
-  const Idx x = node(C.n, C.lg);
-  if (!x.ok) return;
-  const Nbr q = nbr(x.i, x.j, x.l, C.lg);
+__device__ __forceinline__ void fas_rhs_node(const Lvl& C, const Phys& P, int i, int j, int l) {
+  const Nbr q = nbr(i, j, l, C.lg);
   double nv[NC];
   rows(C, P, C.g0, q, nv);
 #pragma unroll
   for (int c = 0; c < NC; ++c) C.f[c][q.p] += nv[c];
 }
 
-// g += P(g_c - R g), trilinear.
-__global__ void k3_prolong(Lvl F, Lvl C, const int* halt) {
-  if (halted(halt)) return;
-  const Idx x = node(F.n, F.lg);
+__global__ void k3_fas_rhs(Lvl C, Phys P) {
+  if (halted(P.halt)) return;
+  const Idx x = node(C.n, C.lg);
   if (!x.ok) return;
-  const int mc = C.n - 1, lc = C.lg;
-  const int I0 = x.i >> 1, J0 = x.j >> 1, K0 = x.l >> 1;
-  const int I1 = (I0 + (x.i & 1)) & mc, J1 = (J0 + (x.j & 1)) & mc, K1 = (K0 + (x.l & 1)) & mc;
-  auto at = [&](int I, int J, int K) { return (((K << lc) + J) << lc) + I; };
-  const int c000 = at(I0, J0, K0), c100 = at(I1, J0, K0), c010 = at(I0, J1, K0), c110 = at(I1, J1, K0);
-  const int c001 = at(I0, J0, K1), c101 = at(I1, J0, K1), c011 = at(I0, J1, K1), c111 = at(I1, J1, K1);
-  const int pf = (((x.l << F.lg) + x.j) << F.lg) + x.i;
+  fas_rhs_node(C, P, x.i, x.j, x.l);
+}
+
+// g += P (g_c - g0), trilinear.  One thread per coarse node (I, J, K) adds the
+// interpolated correction at the eight fine nodes (2I + a, 2J + b, 2K + c),
+// a, b, c in {0, 1}, whose stencils lie in the coarse cell from (I, J, K) to
+// (I + 1, J + 1, K + 1): averages along x, then y, then z, with the second
+// corner equal to the first where the offset is 0 (a coincident node enters
+// with weight 1).  The x pairs are read and written as 16-byte vectors.
+__device__ __forceinline__ void prolong_cell(const Lvl& F, const Lvl& C, int I, int J, int K) {
+  const int mc = C.n - 1, lc = C.lg, lf = F.lg;
+  const int I1 = (I + 1) & mc, J1 = (J + 1) & mc, K1 = (K + 1) & mc;
+  auto at = [&](int ii, int jj, int kk) { return (((kk << lc) + jj) << lc) + ii; };
+  // corner (di, dj, dk) at index di + 2 dj + 4 dk
+  const int cc[8] = {at(I, J, K), at(I1, J, K), at(I, J1, K), at(I1, J1, K),
+                     at(I, J, K1),  at(I1, J, K1),  at(I, J1, K1),  at(I1, J1, K1)};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double* gc = C.g[c];
-    const double* g0 = C.g0[c];
-    auto e = [&](int k) { return gc[k] - g0[k]; };
-    // averages along x, then y, then z (a coincident node enters with weight 1)
-    const double ex00 = 0.5 * (e(c000) + e(c100)), ex10 = 0.5 * (e(c010) + e(c110));
-    const double ex01 = 0.5 * (e(c001) + e(c101)), ex11 = 0.5 * (e(c011) + e(c111));
-    const double exy0 = 0.5 * (ex00 + ex10), exy1 = 0.5 * (ex01 + ex11);
-    F.g[c][pf] += 0.5 * (exy0 + exy1);
+    double e[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[k] = C.g[c][cc[k]] - C.g0[c][cc[k]];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        double v[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const double ex00 = 0.5 * (e[0] + e[a]), ex10 = 0.5 * (e[2 * b] + e[a + 2 * b]);
+          const double ex01 = 0.5 * (e[4 * cz] + e[a + 4 * cz]), ex11 = 0.5 * (e[2 * b + 4 * cz] + e[a + 2 * b + 4 * cz]);
+          const double exy0 = 0.5 * (ex00 + ex10), exy1 = 0.5 * (ex01 + ex11);
+          v[a] = 0.5 * (exy0 + exy1);
+        }
+        const int pf = ((((2 * K + cz) << lf) + 2 * J + b) << lf) + 2 * I;
+        double2* q = reinterpret_cast<double2*>(F.g[c] + pf);
+        double2 o = *q;
+        o.x += v[0];
+        o.y += v[1];
+        *q = o;
+      }
   }
 }
+
+__global__ void k3_prolong(Lvl F, Lvl C, const int* halt) {
+  if (halted(halt)) return;
+  const Idx x = node(C.n, C.lg);
+  if (!x.ok) return;
+  prolong_cell(F, C, x.i, x.j, x.l);
+}
+
+// The coarse end of the V-cycle in one workgroup: from the tail top (8^3 or
+// smaller) down to the coarsest grid and back, every phase (a smoother
+// colour, the residual, restriction, the coarse right-hand side, the
+// coarsest sweeps, prolongation) runs over the level's nodes in a loop of
+// the workgroup's threads, with a workgroup barrier between phases instead
+// of a kernel boundary.  Every tail level lives in LDS for the kernel's
+// duration: the top level's g, f and every level's rho^k, omega^k are loaded
+// once, the top level's g is written back at the end.  The per-node device
+// code is that of the per-level kernels, so the results are the same.
+constexpr int TAIL3_TOP = 8, TAIL3_THREADS = 512, TAIL3_MAX = 4;
+constexpr int TAIL3_LDS = 13312;  // doubles: an 8^3 top and two coarser levels need 13232
+
+// LDS doubles of tail level l of nt (size n): g, f, rho^k, omega^k; g0 below
+// the top; d above the coarsest.
+__host__ __device__ inline int tail3_count(int n, int l, int nt) {
+  return n * n * n * (2 * NC + 4 + (l > 0 ? NC : 0) + (l < nt - 1 ? NC : 0));
+}
+
+struct Tail3 {
+  const Lvl* L;  // device array: the tail's levels (global arrays), top first
+  int nt, nu1, nu2, coarse_sweeps;
+};
+
+__device__ __forceinline__ double* lds_ptr(double* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_assume(__builtin_amdgcn_is_shared((const void*)p));
+#endif
+  return p;
+}
+
+// The LDS view of a tail level built by k3_tail.
+__device__ __forceinline__ Lvl lds_view(const Lvl& s) {
+  Lvl L = s;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    L.g[c] = lds_ptr(s.g[c]);
+    L.f[c] = lds_ptr(s.f[c]);
+    L.g0[c] = lds_ptr(s.g0[c]);
+    L.d[c] = lds_ptr(s.d[c]);
+  }
+  L.rk = lds_ptr(s.rk);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) L.om[c] = lds_ptr(s.om[c]);
+  return L;
+}
+
+__device__ void t3_colour(const Lvl& L, const Phys& P, int colour) {
+  const int n = L.n, cnt = (n >> 1) * n * n, lh = L.lg - 1;
+  for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
+    const int t = w & ((1 << lh) - 1), row = w >> lh;
+    const int j = row & (n - 1), l = row >> L.lg;
+    const Nbr q = nbr(2 * t + ((j + l + colour) & 1), j, l, L.lg);
+    double out[NC];
+    block(L, P, L.g, q, out);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.g[c][q.p] = out[c];
+  }
+  __syncthreads();
+}
+
+__device__ void t3_sweeps(const Lvl& L, const Phys& P, int sweeps) {
+  for (int k = 0; k < sweeps; ++k) {
+    t3_colour(L, P, 0);
+    t3_colour(L, P, 1);
+  }
+}
+
+// each loop covers the nodes i fastest, then j, then l
+#define T3_NODES(L_, i_, j_, l_, body)                                         \
+  for (int w_ = threadIdx.x; w_ < (L_).n * (L_).n * (L_).n; w_ += blockDim.x) { \
+    const int i_ = w_ & ((L_).n - 1), j_ = (w_ >> (L_).lg) & ((L_).n - 1);     \
+    const int l_ = w_ >> (2 * (L_).lg);                                        \
+    body;                                                                      \
+  }                                                                            \
+  __syncthreads();
+
+__global__ __launch_bounds__(TAIL3_THREADS) void k3_tail(Tail3 T, Phys P) {
+  if (halted(P.halt)) return;
+  __shared__ __align__(16) double smem[TAIL3_LDS];
+  __shared__ Lvl S[TAIL3_MAX];
+  const int t = threadIdx.x;
+  if (t < T.nt) {
+    // thread t lays out level t's LDS arrays (in the order of tail3_count)
+    Lvl s = T.L[t];
+    int off = 0;
+    for (int l = 0; l < t; ++l) off += tail3_count(T.L[l].n, l, T.nt);
+    double* p = smem + off;
+    const int cnt = s.n * s.n * s.n;
+    for (int c = 0; c < NC; ++c, p += cnt) s.g[c] = p;
+    for (int c = 0; c < NC; ++c, p += cnt) s.f[c] = p;
+    s.rk = p;
+    p += cnt;
+    for (int c = 0; c < 3; ++c, p += cnt) s.om[c] = p;
+    // arrays a level does not have point at the LDS base (lds_view assumes
+    // every pointer is in LDS; they are never accessed)
+    for (int c = 0; c < NC; ++c) {
+      s.g0[c] = t > 0 ? p + c * cnt : smem;
+      s.gb[c] = smem;
+    }
+    if (t > 0) p += NC * cnt;
+    for (int c = 0; c < NC; ++c) s.d[c] = t < T.nt - 1 ? p + c * cnt : smem;
+    S[t] = s;
+  }
+  __syncthreads();
+  // load: the top level's g and f, every level's rho^k and omega^k
+  for (int l = 0; l < T.nt; ++l) {
+    const Lvl G = T.L[l], V = S[l];
+    const int cnt = G.n * G.n * G.n;
+    for (int w = t; w < cnt; w += blockDim.x) {
+      V.rk[w] = G.rk[w];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) V.om[c][w] = G.om[c][w];
+      if (l == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          V.g[c][w] = G.g[c][w];
+          V.f[c][w] = G.f[c][w];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int last = T.nt - 1;
+  for (int l = 0; l < last; ++l) {
+    const Lvl F = lds_view(S[l]), C = lds_view(S[l + 1]);
+    t3_sweeps(F, P, T.nu1);
+    T3_NODES(F, i, j, k, residual_node(F, P, i, j, k));
+    T3_NODES(C, i, j, k, restrict_node(F, C, i, j, k));
+    T3_NODES(C, i, j, k, fas_rhs_node(C, P, i, j, k));
+  }
+  t3_sweeps(lds_view(S[last]), P, T.coarse_sweeps);
+  for (int l = last - 1; l >= 0; --l) {
+    const Lvl F = lds_view(S[l]), C = lds_view(S[l + 1]);
+    T3_NODES(C, i, j, k, prolong_cell(F, C, i, j, k));
+    t3_sweeps(F, P, T.nu2);
+  }
+  {
+    const Lvl G = T.L[0], V = S[0];
+    const int cnt = G.n * G.n * G.n;
+    for (int w = t; w < cnt; w += blockDim.x)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) G.g[c][w] = V.g[c][w];
+  }
+}
+#undef T3_NODES
 
 // Block sum in a fixed order.
 __device__ __forceinline__ double block_sum(double x, double* lds) {
@@ -445,6 +880,16 @@ __global__ void k3_copy(const double* __restrict__ a, double* __restrict__ b, si
   if (t < count) b[t] = a[t];
 }
 
+// Copies the six components back after an odd number of tiled sweeps; a
+// no-op once the stop flag is set (the sweeps were then no-ops too).
+__global__ void k3_copy_back(G6 a, G6 b, size_t count, const int* halt) {
+  if (halted(halt)) return;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b.c[c][t] = a.c[c][t];
+}
+
 // ------------------------------------------------------------------ host --
 struct Dims {
   dim3 grid, block;
@@ -497,9 +942,19 @@ struct hfz3_handle {
   int cycle_hint = 4;
   int graph_state = 0;
   hipGraphExec_t cycle_exec = nullptr;
+  // smallest level swept by the z-marching tiled kernel (below: the two
+  // per-colour kernels, which fill the device better on small grids); the
+  // environment variable HFZ3_TILES overrides it (0: never)
+  int tile_from = 128;
+  // first level of the one-workgroup tail (-1: none; HFZ3_TAIL=0 switches it off)
+  int tail_top = -1;
+  Lvl* tail_desc = nullptr;  // device copies of the tail's level descriptors
 };
 
 namespace {
+
+// Levels the tiled sweep covers exactly (n a multiple of its tile and chunk).
+bool tiled_shape(int n) { return n >= 32 && n % TX3 == 0 && n % TY3 == 0 && n % ZC3 == 0; }
 
 int validate3(const hfz_params* p) {
   if (!p) return HFZ_EINVAL;
@@ -533,6 +988,8 @@ size_t layout3(const hfz_params& p, void* ws, hfz3_handle* hd) {
       for (int k = 0; k < NC; ++k) l.g0[k] = c.take<double>(cnt);
     if (m > p.coarsest_n)
       for (int k = 0; k < NC; ++k) l.d[k] = c.take<double>(cnt);
+    if (tiled_shape(m))
+      for (int k = 0; k < NC; ++k) l.gb[k] = c.take<double>(cnt);
     l.rk = c.take<double>(cnt);
     for (int k = 0; k < 3; ++k) l.om[k] = c.take<double>(cnt);
     L.push_back(l);
@@ -545,7 +1002,9 @@ size_t layout3(const hfz_params& p, void* ws, hfz3_handle* hd) {
   const size_t pcap = std::max<size_t>(4096, N3 / 64 + 64) * 3;
   double* partial = c.take<double>(pcap);
   double* result = c.take<double>(64);
+  Lvl* tail_desc = c.take<Lvl>(TAIL3_MAX);
   if (hd) {
+    hd->tail_desc = tail_desc;
     hd->L = L;
     hd->u = u;
     hd->v = v;
@@ -568,6 +1027,25 @@ void copy_dev(hfz3_handle* hd, const double* a, double* b, size_t count) {
 
 void smooth(hfz3_handle* hd, int l, int sweeps) {
   const Lvl& L = hd->L[l];
+  if (tiled_shape(L.n) && L.n >= hd->tile_from) {
+    // one launch per sweep, g -> gb -> g ...; an odd count copies back
+    G6 home{}, other{};
+    for (int c = 0; c < NC; ++c) {
+      home.c[c] = L.g[c];
+      other.c[c] = L.gb[c];
+    }
+    G6 cur = home, nxt = other;
+    const unsigned grid = (unsigned)((L.n / TX3) * (L.n / TY3) * (L.n / ZC3));
+    for (int k = 0; k < sweeps; ++k) {
+      k3_sweep_tile<<<grid, NT3, 0, hd->stream>>>(L, cur, nxt, hd->P);
+      std::swap(cur, nxt);
+    }
+    if (cur.c[0] != home.c[0]) {
+      const size_t cnt = (size_t)L.n * L.n * L.n;
+      k3_copy_back<<<(unsigned)((cnt + 255) / 256), 256, 0, hd->stream>>>(cur, home, cnt, hd->P.halt);
+    }
+    return;
+  }
   const Dims d = dims(L.n / 2, L.n);
   for (int k = 0; k < sweeps; ++k)
     for (int colour = 0; colour < 2; ++colour) k3_smooth<<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, colour);
@@ -575,6 +1053,11 @@ void smooth(hfz3_handle* hd, int l, int sweeps) {
 
 void vcycle_rec(hfz3_handle* hd, int l) {
   const int last = (int)hd->L.size() - 1;
+  if (l == hd->tail_top) {
+    const Tail3 T{hd->tail_desc, last - l + 1, hd->p.nu1, hd->p.nu2, hd->p.coarse_sweeps};
+    k3_tail<<<1, TAIL3_THREADS, 0, hd->stream>>>(T, hd->P);
+    return;
+  }
   if (l == last) {
     smooth(hd, l, hd->p.coarse_sweeps);
     return;
@@ -587,7 +1070,7 @@ void vcycle_rec(hfz3_handle* hd, int l) {
   k3_restrict<<<dc.grid, dc.block, 0, hd->stream>>>(F, C, hd->P.halt);
   k3_fas_rhs<<<dc.grid, dc.block, 0, hd->stream>>>(C, hd->P);
   vcycle_rec(hd, l + 1);
-  k3_prolong<<<df.grid, df.block, 0, hd->stream>>>(F, C, hd->P.halt);
+  k3_prolong<<<dc.grid, dc.block, 0, hd->stream>>>(F, C, hd->P.halt);
   smooth(hd, l, hd->p.nu2);
 }
 
@@ -747,6 +1230,29 @@ int hfz3_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_stre
   hd->P.alpha = p->alpha;
   hd->P.w = p->w_damp;
   hd->P.halt = hd->ctl;
+  if (const char* e = std::getenv("HFZ3_TILES")) {
+    const int v = std::atoi(e);
+    hd->tile_from = v > 0 ? v : INT32_MAX;
+  }
+  // the tail starts at the first level of at most 8^3, if its levels fit
+  const char* te = std::getenv("HFZ3_TAIL");
+  if (!(te && std::atoi(te) == 0)) {
+    const int nl = (int)hd->L.size();
+    for (int l = 0; l < nl; ++l)
+      if (hd->L[l].n <= TAIL3_TOP) {
+        const int nt = nl - l;
+        int need = 0;
+        for (int k = 0; k < nt; ++k) need += tail3_count(hd->L[l + k].n, k, nt);
+        if (nt <= TAIL3_MAX && need <= TAIL3_LDS) hd->tail_top = l;
+        break;
+      }
+  }
+  if (hd->tail_top >= 0 &&
+      hipMemcpyAsync(hd->tail_desc, hd->L.data() + hd->tail_top, (hd->L.size() - hd->tail_top) * sizeof(Lvl),
+                     hipMemcpyHostToDevice, hd->stream) != hipSuccess) {
+    delete hd;
+    return HFZ_EHIP;
+  }
   k3_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
   if (hipStreamSynchronize(hd->stream) != hipSuccess || last_error() != HFZ_OK) {
     delete hd;

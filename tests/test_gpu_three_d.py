@@ -43,8 +43,13 @@ def test_source_and_coefficients(n):
             assert rel_err(np_(sim.read(3, l, 1 + c)), lev.omega_k[c]) < 1e-12, (l, c)
 
 
-@pytest.mark.parametrize("n", [8, 16, 32])
-def test_sweeps_and_residual(n):
+# levels from 128^3 up are swept by the z-marching tiled kernel, smaller ones
+# by two per-colour launches; HFZ3_TILES=32 moves the switch down to 32^3
+@pytest.mark.parametrize("n,tiles", [(8, None), (16, None), (32, None), (32, "32"), (64, None), (64, "32"),
+                                     (128, None)])
+def test_sweeps_and_residual(n, tiles, monkeypatch):
+    if tiles:
+        monkeypatch.setenv("HFZ3_TILES", tiles)
     cfg, sim, ora = setup(n, seed=2)
     sim.begin_step()
     S, om = ora.build_source()
@@ -66,8 +71,46 @@ def test_sweeps_and_residual(n):
     assert abs(sim.residual() - r2) < 1e-10 * r2
 
 
+def test_tiled_sweep_matches_per_colour_kernels(monkeypatch):
+    """The z-marching tiled kernel (forced down to 32^3 by HFZ3_TILES=32) and
+    the two per-colour launches (HFZ3_TILES=0) evaluate the same block update
+    on the same values: an odd and an even sweep count (the odd one copies
+    back from the second buffer)."""
+    out = {}
+    for tiles in ("32", "0"):
+        monkeypatch.setenv("HFZ3_TILES", tiles)
+        cfg, sim, _ = setup(64, seed=4)
+        sim.begin_step()
+        got = []
+        for k in (3, 2):
+            sim.smooth(0, k)
+            got.append([np_(sim.read(0, 0, c)) for c in range(6)])
+        out[tiles] = got
+    for a, b in zip(out["32"], out["0"]):
+        for c in range(6):
+            assert rel_err(a[c], b[c]) < 1e-14, c
+
+
 @pytest.mark.parametrize("n", [16, 32])
-def test_vcycles(n):
+def test_tail_matches_per_level_kernels(n, monkeypatch):
+    """The levels from 16^3 down run in one workgroup (k3_tail); with it
+    switched off (HFZ3_TAIL=0) the per-level kernels run.  Both use the same
+    per-node device code: three V-cycles agree to rounding."""
+    out = {}
+    for tail in ("1", "0"):
+        monkeypatch.setenv("HFZ3_TAIL", tail)
+        cfg, sim, _ = setup(n, seed=6)
+        sim.begin_step()
+        sim.vcycle(3)
+        out[tail] = [np_(sim.read(0, 0, c)) for c in range(6)]
+    for c in range(6):
+        assert rel_err(out["1"][c], out["0"][c]) < 1e-14, c
+
+
+@pytest.mark.parametrize("n,tiles", [(16, None), (32, None), (32, "32"), (64, "32")])
+def test_vcycles(n, tiles, monkeypatch):
+    if tiles:
+        monkeypatch.setenv("HFZ3_TILES", tiles)
     cfg, sim, ora = setup(n, seed=3)
     sim.begin_step()
     S, om = ora.build_source()
@@ -82,8 +125,10 @@ def test_vcycles(n):
     assert abs(sim.residual() - r) < 1e-9 * r
 
 
-@pytest.mark.parametrize("n", [16, 32])
-def test_steps(n):
+@pytest.mark.parametrize("n,tiles", [(16, None), (32, None), (32, "32")])
+def test_steps(n, tiles, monkeypatch):
+    if tiles:
+        monkeypatch.setenv("HFZ3_TILES", tiles)
     cfg, sim, ora = setup(n, seed=4)
     m0 = sim.mass()
     for k in range(3):
