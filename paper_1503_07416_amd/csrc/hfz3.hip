@@ -187,6 +187,66 @@ __device__ __forceinline__ void put_coef(const Coef& C, Gath& G) {
   for (int c = 0; c < NC; ++c) G.f[c] = C.f[c];
 }
 
+// Rows of N(g) from gathered values (same arithmetic as rows()).
+__device__ __forceinline__ void rows_vals(const Gath& G, double h, const Phys& P, double* out) {
+  const double s = P.s, c4 = s / (4.0 * h), c2 = s / (2.0 * h), ih2 = 1.0 / (h * h);
+  const double* rk = G.rk;
+  const double* u = G.v[1];
+  const double* v = G.v[2];
+  const double* w = G.v[3];
+  const double* mu = G.v[4];
+  out[0] = G.v[0][0] + c4 * (rk[1] * u[1] - rk[2] * u[2] + rk[3] * v[3] - rk[4] * v[4] + rk[5] * w[5] - rk[6] * w[6]);
+  const double rkP = rk[0];
+  const double o0 = G.om[0], o1 = G.om[1], o2 = G.om[2];
+  const double uP = u[0], vP = v[0], wP = w[0];
+  const double cx = o1 * wP - o2 * vP, cy = o2 * uP - o0 * wP, cz = o0 * vP - o1 * uP;
+  const double bs = 0.5 * s * P.sigma * rkP, gl = 0.5 * s * P.gamma * ih2;
+  out[1] = rkP * uP + bs * cx + c4 * rkP * (q2v(G, 1) - q2v(G, 2)) + c2 * rkP * (mu[1] - mu[2]) - gl * (s6(u) - 6.0 * uP);
+  out[2] = rkP * vP + bs * cy + c4 * rkP * (q2v(G, 3) - q2v(G, 4)) + c2 * rkP * (mu[3] - mu[4]) - gl * (s6(v) - 6.0 * vP);
+  out[3] = rkP * wP + bs * cz + c4 * rkP * (q2v(G, 5) - q2v(G, 6)) + c2 * rkP * (mu[5] - mu[6]) - gl * (s6(w) - 6.0 * wP);
+  const double phi = G.v[0][0] - 1.5;
+  out[4] = mu[0] - phi * phi * phi * (1.0 / 3.0) - P.alpha * phi - (s6(G.v[5]) - 6.0 * G.v[5][0]) * ih2;
+  out[5] = G.v[5][0] - (s6(G.v[0]) - 6.0 * G.v[0][0]) * ih2;
+}
+
+// The 7-point values of field f at the x pair (i0, i0 + 1) (i0 even) of the
+// row at `row` (its j-neighbour rows yn, ys and l-neighbour rows zu, zd):
+// seven aligned 16-byte loads give both nodes' stencils, a for i0, b for i0 + 1.
+__device__ __forceinline__ void pair7(const double* f, int row, int yn, int ys, int zu, int zd, int i0, int m,
+                                      double* a, double* b) {
+  const double2 P0 = *reinterpret_cast<const double2*>(f + row + i0);
+  const double2 PL = *reinterpret_cast<const double2*>(f + row + ((i0 - 2) & m));
+  const double2 PR = *reinterpret_cast<const double2*>(f + row + ((i0 + 2) & m));
+  const double2 N = *reinterpret_cast<const double2*>(f + yn + i0);
+  const double2 S = *reinterpret_cast<const double2*>(f + ys + i0);
+  const double2 U = *reinterpret_cast<const double2*>(f + zu + i0);
+  const double2 D = *reinterpret_cast<const double2*>(f + zd + i0);
+  a[0] = P0.x, a[1] = P0.y, a[2] = PL.y, a[3] = N.x, a[4] = S.x, a[5] = U.x, a[6] = D.x;
+  b[0] = P0.y, b[1] = PR.x, b[2] = P0.x, b[3] = N.y, b[4] = S.y, b[5] = U.y, b[6] = D.y;
+}
+
+// Rows of N(g) at the x pair (i0, i0 + 1) of row (j, l), from 16-byte loads.
+__device__ __forceinline__ void rows_pair(const Lvl& L, const Phys& P, double* const* g, int i0, int j, int l,
+                                          double* na, double* nb, int& pa) {
+  const int n = L.n, m = n - 1, lg = L.lg;
+  const int row = ((l << lg) + j) << lg;
+  const int yn = ((l << lg) + ((j + 1) & m)) << lg, ys = ((l << lg) + ((j - 1) & m)) << lg;
+  const int zu = ((((l + 1) & m) << lg) + j) << lg, zd = ((((l - 1) & m) << lg) + j) << lg;
+  Gath A, B;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) pair7(g[c], row, yn, ys, zu, zd, i0, m, A.v[c], B.v[c]);
+  pair7(L.rk, row, yn, ys, zu, zd, i0, m, A.rk, B.rk);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double2 o = *reinterpret_cast<const double2*>(L.om[c] + row + i0);
+    A.om[c] = o.x;
+    B.om[c] = o.y;
+  }
+  rows_vals(A, L.h, P, na);
+  rows_vals(B, L.h, P, nb);
+  pa = row + i0;
+}
+
 // Damped block update at node q of the iterate g.
 __device__ __forceinline__ void block(const Lvl& L, const Phys& P, double* const* g, const Nbr& q, double* out) {
   Coef C;
@@ -232,7 +292,8 @@ struct Idx {
 // (y, z) rows in blockIdx.y).  Workgroups are renumbered so that each XCD
 // (workgroups are dealt to the 8 XCDs in turn) takes a contiguous range of
 // rows, whose y and z neighbour rows then mostly sit in that XCD's L2.
-__device__ __forceinline__ Idx node(int n, int lg) {
+// (node_x: nx nodes per row, n^2 rows.)
+__device__ __forceinline__ Idx node_x(int nx, int n, int lg) {
   Idx x;
   const int nbx = (int)gridDim.x, nb = nbx * (int)gridDim.y;
   const int bid = (int)blockIdx.y * nbx + (int)blockIdx.x;
@@ -241,9 +302,11 @@ __device__ __forceinline__ Idx node(int n, int lg) {
   const int row = (b / nbx) * blockDim.y + threadIdx.y;
   x.j = row & (n - 1);
   x.l = row >> lg;
-  x.ok = x.i < n && row < n * n;
+  x.ok = x.i < nx && row < n * n;
   return x;
 }
+
+__device__ __forceinline__ Idx node(int n, int lg) { return node_x(n, n, lg); }
 
 // ---------------------------------------------------------------- kernels --
 // omega^k = curl_h u^k and S from the state (rho^k, u^k, v^k, w^k); the iterate
@@ -499,11 +562,19 @@ __device__ __forceinline__ void residual_node(const Lvl& L, const Phys& P, int i
   for (int c = 0; c < NC; ++c) L.d[c][q.p] = L.f[c][q.p] - nv[c];
 }
 
-__global__ void k3_residual_field(Lvl L, Phys P) {
+// d = f - N(g), one thread per x pair of nodes (launch geometry of n/2 x n^2).
+__global__ __launch_bounds__(256) void k3_residual_field(Lvl L, Phys P) {
   if (halted(P.halt)) return;
-  const Idx x = node(L.n, L.lg);
+  const Idx x = node_x(L.n >> 1, L.n, L.lg);
   if (!x.ok) return;
-  residual_node(L, P, x.i, x.j, x.l);
+  double na[NC], nb[NC];
+  int pa;
+  rows_pair(L, P, L.g, 2 * x.i, x.j, x.l, na, nb, pa);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double2 f = *reinterpret_cast<const double2*>(L.f[c] + pa);
+    *reinterpret_cast<double2*>(L.d[c] + pa) = make_double2(f.x - na[c], f.y - nb[c]);
+  }
 }
 
 // g_c = g0_c = R g, f_c = R d at coarse node (I, J, K).
@@ -748,19 +819,22 @@ __device__ __forceinline__ double block_sum(double x, double* lds) {
 }
 
 // Per-block partial sums of sum_c (f - N(g))^2 on a level.
-__global__ void k3_residual_partial(Lvl L, Phys P, double* __restrict__ partial) {
+// (One thread per x pair of nodes, launch geometry of n/2 x n^2.)
+__global__ __launch_bounds__(256) void k3_residual_partial(Lvl L, Phys P, double* __restrict__ partial) {
   if (halted(P.halt)) return;
   __shared__ double lds[16];
-  const Idx x = node(L.n, L.lg);
+  const Idx x = node_x(L.n >> 1, L.n, L.lg);
   double acc = 0.0;
   if (x.ok) {
-    const Nbr q = nbr(x.i, x.j, x.l, L.lg);
-    double nv[NC];
-    rows(L, P, L.g, q, nv);
+    double na[NC], nb[NC];
+    int pa;
+    rows_pair(L, P, L.g, 2 * x.i, x.j, x.l, na, nb, pa);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double dd = L.f[c][q.p] - nv[c];
-      acc += dd * dd;
+      const double2 f = *reinterpret_cast<const double2*>(L.f[c] + pa);
+      const double da = f.x - na[c], db = f.y - nb[c];
+      acc += da * da;
+      acc += db * db;
     }
   }
   const double r = block_sum(acc, lds);
@@ -1065,8 +1139,8 @@ void vcycle_rec(hfz3_handle* hd, int l) {
   const Lvl& F = hd->L[l];
   const Lvl& C = hd->L[l + 1];
   smooth(hd, l, hd->p.nu1);
-  const Dims df = dims(F.n, F.n), dc = dims(C.n, C.n);
-  k3_residual_field<<<df.grid, df.block, 0, hd->stream>>>(F, hd->P);
+  const Dims dp = dims(F.n / 2, F.n), dc = dims(C.n, C.n);  // dp: one thread per x pair
+  k3_residual_field<<<dp.grid, dp.block, 0, hd->stream>>>(F, hd->P);
   k3_restrict<<<dc.grid, dc.block, 0, hd->stream>>>(F, C, hd->P.halt);
   k3_fas_rhs<<<dc.grid, dc.block, 0, hd->stream>>>(C, hd->P);
   vcycle_rec(hd, l + 1);
@@ -1076,7 +1150,7 @@ void vcycle_rec(hfz3_handle* hd, int l) {
 
 void residual_launch(hfz3_handle* hd, bool stop, bool counted) {
   const Lvl& L = hd->L[0];
-  const Dims d = dims(L.n, L.n);
+  const Dims d = dims(L.n / 2, L.n);  // one thread per x pair
   k3_residual_partial<<<d.grid, d.block, 0, hd->stream>>>(L, hd->P, hd->partial);
   const int count = (int)(d.grid.x * d.grid.y);
   const double h3 = L.h * L.h * L.h;

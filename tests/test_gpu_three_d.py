@@ -15,9 +15,9 @@ def np_(t):
     return t.cpu().numpy()
 
 
-def setup(n, seed=0, uamp=0.02):
+def setup(n, seed=0, uamp=0.02, **kw):
     import paper_1503_07416_amd as pkg
-    cfg, rho, u, v, w = workloads.pfc3d(n, seed=seed, uamp=uamp)
+    cfg, rho, u, v, w = workloads.pfc3d(n, seed=seed, uamp=uamp, **kw)
     sim = pkg.Simulation3(cfg)
     sim.set_state(rho, u, v, w)
     ora = oracle_stepper(cfg)
@@ -105,6 +105,24 @@ def test_tail_matches_per_level_kernels(n, monkeypatch):
         out[tail] = [np_(sim.read(0, 0, c)) for c in range(6)]
     for c in range(6):
         assert rel_err(out["1"][c], out["0"][c]) < 1e-14, c
+
+
+@pytest.mark.parametrize("coarsest,nu1,nu2,sweeps", [(8, 2, 2, 4), (16, 2, 2, 6), (4, 1, 0, 4), (4, 0, 3, 3)])
+def test_vcycle_variants(coarsest, nu1, nu2, sweeps):
+    """Other cycle shapes at 32^3 against the oracle's V-cycles: coarsest grid
+    8^3 (the one-workgroup tail is then only the coarsest sweeps), 16^3 (no
+    tail), and V(1,0) and V(0,3) through the tail."""
+    cfg, sim, ora = setup(32, seed=8, coarsest_n=coarsest, nu1=nu1, nu2=nu2, coarse_sweeps=sweeps)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    assert sim.levels() == len(sol.levels)
+    g = ora.g.copy()
+    for k in range(2):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(6)]
+        assert max(errs) < 1e-11, (k, errs)
 
 
 @pytest.mark.parametrize("n,tiles", [(16, None), (32, None), (32, "32"), (64, "32")])
