@@ -251,7 +251,12 @@ int hfz_batch_destroy(hfz_batch* b);
  * carry the weight h^3.  Parameters: hfz_params with model HFZ_PFC, FP64, no
  * walls, 8 <= n <= 512 (HFZ_EINVAL otherwise).  Fields: n^3 FP64 values,
  * x fastest, then y, then z.  Ownership, streams and errors as for the 2D
- * calls.  The damped block smoother needs s/h^4 of order 0.5 or less in 3D. */
+ * calls.  The damped block smoother needs s/h^4 of order 0.5 or less in 3D.
+ * Kernel choice (same results, read at hfz3_init): levels from 128^3 up are
+ * swept by a one-launch tiled kernel, smaller ones by one launch per colour,
+ * and the levels from 8^3 down run in one workgroup; the environment
+ * variables HFZ3_TILES (smallest level of the tiled sweep, 0: never) and
+ * HFZ3_TAIL (0: no one-workgroup tail) override this. */
 typedef struct hfz3_handle hfz3_handle;
 
 int hfz3_workspace_bytes(const hfz_params* p, size_t* bytes);
