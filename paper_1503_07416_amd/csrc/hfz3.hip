@@ -689,6 +689,14 @@ __device__ __forceinline__ double* lds_ptr(double* p) {
   return p;
 }
 
+__device__ __forceinline__ double* glb_ptr(double* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return (double*)((__attribute__((address_space(1))) double*)(uintptr_t)p);
+#else
+  return p;
+#endif
+}
+
 // The LDS view of a tail level built by k3_tail.
 __device__ __forceinline__ Lvl lds_view(const Lvl& s) {
   Lvl L = s;
@@ -765,17 +773,17 @@ __global__ __launch_bounds__(TAIL3_THREADS) void k3_tail(Tail3 T, Phys P) {
   __syncthreads();
   // load: the top level's g and f, every level's rho^k and omega^k
   for (int l = 0; l < T.nt; ++l) {
-    const Lvl G = T.L[l], V = S[l];
+    const Lvl G = T.L[l], V = lds_view(S[l]);
     const int cnt = G.n * G.n * G.n;
     for (int w = t; w < cnt; w += blockDim.x) {
-      V.rk[w] = G.rk[w];
+      V.rk[w] = glb_ptr(G.rk)[w];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) V.om[c][w] = G.om[c][w];
+      for (int c = 0; c < 3; ++c) V.om[c][w] = glb_ptr(G.om[c])[w];
       if (l == 0) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          V.g[c][w] = G.g[c][w];
-          V.f[c][w] = G.f[c][w];
+          V.g[c][w] = glb_ptr(G.g[c])[w];
+          V.f[c][w] = glb_ptr(G.f[c])[w];
         }
       }
     }
@@ -796,11 +804,11 @@ __global__ __launch_bounds__(TAIL3_THREADS) void k3_tail(Tail3 T, Phys P) {
     t3_sweeps(F, P, T.nu2);
   }
   {
-    const Lvl G = T.L[0], V = S[0];
+    const Lvl G = T.L[0], V = lds_view(S[0]);
     const int cnt = G.n * G.n * G.n;
     for (int w = t; w < cnt; w += blockDim.x)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) G.g[c][w] = V.g[c][w];
+      for (int c = 0; c < NC; ++c) glb_ptr(G.g[c])[w] = V.g[c][w];
   }
 }
 #undef T3_NODES
