@@ -666,8 +666,9 @@ __global__ void k3_prolong(Lvl F, Lvl C, const int* halt) {
 // the workgroup's threads, with a workgroup barrier between phases instead
 // of a kernel boundary.  Every tail level lives in LDS for the kernel's
 // duration: the top level's g, f and every level's rho^k, omega^k are loaded
-// once, the top level's g is written back at the end.  The per-node device
-// code is that of the per-level kernels, so the results are the same.
+// once, the top level's g is written back at the end.  The per-node
+// arithmetic is that of the per-level kernels (the same expressions), so the
+// results agree with theirs to rounding.
 constexpr int TAIL3_TOP = 8, TAIL3_THREADS = 512, TAIL3_MAX = 4;
 constexpr int TAIL3_LDS = 13312;  // doubles: an 8^3 top and two coarser levels need 13232
 
