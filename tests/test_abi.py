@@ -95,3 +95,30 @@ def test_gradient_flow_models_validate():
     assert ws(model=4, n=64)[0] == -1
     p = hfz.Params()
     assert lib.hfz_default_params(4, ctypes.byref(p)) == -1
+
+
+def ws3(**kw):
+    lib = hfz.load()
+    p = hfz.Params()
+    assert lib.hfz_default_params(0, ctypes.byref(p)) == 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    nb = ctypes.c_size_t(0)
+    return lib.hfz3_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)), nb.value
+
+
+def test_three_d_workspace_and_validation():
+    """hfz3_workspace_bytes (host only): the 3D step takes PFC, FP64, no walls,
+    8 <= n <= 512; its workspace holds at least the finest level's 28 arrays
+    (g, f, d, the tiled sweep's second iterate, rho^k, omega^k) and grows by
+    about 8x per doubling of n."""
+    rc, nb = ws3(n=128, h=0.5)
+    assert rc == 0 and nb > 28 * 128 ** 3 * 8
+    rc2, nb2 = ws3(n=256, h=0.5)
+    assert rc2 == 0 and 7.5 < nb2 / nb < 8.5
+    assert ws3(n=8, h=0.5)[0] == 0
+    for bad in [dict(n=100), dict(n=4), dict(n=1024), dict(model=1), dict(walls=1), dict(precision=1),
+                dict(coarsest_n=2), dict(coarsest_n=64, n=32), dict(h=0.0), dict(s=-1.0), dict(w_damp=1.0),
+                dict(nu1=0, nu2=0), dict(coarse_sweeps=0), dict(sigma=0), dict(tol=0.0)]:
+        rc, _ = ws3(**bad)
+        assert rc == -1, bad
