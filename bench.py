@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--gradflow-only", action="store_true", help="only the gradient-flow workloads (for profiles)")
     ap.add_argument("--channel-only", action="store_true", help="only the channel workloads (for profiles)")
     ap.add_argument("--three-d-only", action="store_true", help="only the 3D workload (for profiles)")
+    ap.add_argument("--size-sweep-only", action="store_true",
+                    help="only the headline smoother at 1024^2, 2048^2, 4096^2")
     ap.add_argument("--counter-probe-3d", action="store_true",
                     help="only launch the 3D smoothers at 128^3 and a reference copy kernel (for counter runs)")
     ap.add_argument("--convergence", action="store_true",
@@ -512,6 +514,27 @@ def run_channel(steps=50, check_steps=10, n=256):
     return out
 
 
+def run_size_sweep(sizes=(1024, 2048, 4096)):
+    """The headline smoother (PFC, FP64, two fused sweeps per launch, the
+    tuner's tile shape) on grids past the 256 MB Infinity Cache: at 2048^2 one
+    launch moves 2.3 GB of algorithmic bytes, at 4096^2 9.1 GB."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    out = {}
+    for m in sizes:
+        cfg, rho, u, v = workloads.pfc_uniform_noise(m, 0.25, 0.01, 0)
+        sim = pkg.Simulation(cfg, device="cuda:0")
+        sim.set_state(rho, u, v)
+        rl = smoother_roofline(sim, m, launches=10)
+        out[str(m)] = {"launch_us": rl["launch_us"], "achieved": rl["achieved"], "frac": rl["frac"],
+                       "kernel": rl["kernel"]}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def smoother3_roofline(sim, n, sweeps=10):
     """Average time of one damped red-black sweep of the 3D smoother (one
     launch of the z-marching tiled kernel from 32^3 up), HIP events on the
@@ -656,6 +679,9 @@ def main():
     if a.channel_only:
         print(json.dumps({"channel": run_channel()}))
         return
+    if a.size_sweep_only:
+        print(json.dumps({"smoother_size_sweep": run_size_sweep()}))
+        return
     if a.three_d_only:
         print(json.dumps({"three_d": run_three_d()}))
         return
@@ -718,6 +744,8 @@ def main():
         out["channel"] = run_channel()
         torch.cuda.empty_cache()
         out["three_d"] = run_three_d()
+        torch.cuda.empty_cache()
+        out["smoother_size_sweep"] = run_size_sweep()
     print(json.dumps(out))
 
 
