@@ -60,6 +60,8 @@ SWEEP_BYTES_GF = {"pfc_gf": 9 * 8, "cdft_gf": 6 * 8}
 KERNEL_SOURCES = ["paper_1503_07416_amd/csrc/tile.hpp", "paper_1503_07416_amd/csrc/stencil.hpp",
                   "paper_1503_07416_amd/csrc/kernels.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_pfc512_fp64_hbm_counters.md")
+KERNEL_SOURCES_3D = ["paper_1503_07416_amd/csrc/hfz3.hip"]
+TRAFFIC_SUMMARY_3D = os.path.join(ROOT, "profiles", "pfc3d128_fp64_kernels.md")
 
 
 def parse():
@@ -94,12 +96,28 @@ def parse():
     return ap.parse_args()
 
 
-def source_hash():
+def source_hash(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def committed_traffic_3d(n):
+    """HBM bytes per 3D smoother sweep at n^3 from the committed counter
+    summary, or None if it is missing, was taken from other sources or at
+    another size."""
+    try:
+        with open(TRAFFIC_SUMMARY_3D) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"source_hash_3d:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_sweep_%d:\s*([0-9.eE+]+)" % n, text)
+    if not m or not t or m.group(1) != source_hash(KERNEL_SOURCES_3D):
+        return None
+    return float(t.group(1))
 
 
 def committed_traffic(shape):
@@ -189,7 +207,8 @@ def counter_probe_3d(n=128):
     for _ in range(3):
         torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
-    print(json.dumps({"counter_probe_3d": True, "n": n, "sweeps_each": 4, "copy_bytes_each_way": 2**30}))
+    print(json.dumps({"counter_probe_3d": True, "n": n, "sweeps_each": 4, "copy_bytes_each_way": 2**30,
+                      "source_hash_3d": source_hash(KERNEL_SOURCES_3D)}))
 
 
 def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
@@ -551,7 +570,7 @@ def smoother3_roofline(sim, n, sweeps=10):
     nbytes = SWEEP_BYTES_3D * n ** 3
     ach = nbytes / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": committed_traffic_3d(n),
             "kernel": "k3_sweep_tile (both colours of one sweep)", "sweep_us": round(t * 1e6, 3),
             "bytes_per_sweep": nbytes}
 
