@@ -1133,6 +1133,20 @@ BatchLayout batch_layout(const hfz_params* ps, int count) {
   return bl;
 }
 
+// Tile shape of the batched smoother on an n x n level: 64x16 tiles of 512
+// threads (shape 2) from 128^2 up, else 32x16 of 256 (shape 0); the
+// environment variable HFZ_BATCH_TILE (0 or 2) overrides it where the shape
+// divides n.
+int batch_tile_shape(int n) {
+  static const int forced = [] {
+    const char* e = std::getenv("HFZ_BATCH_TILE");
+    return e ? std::atoi(e) : -1;
+  }();
+  const auto fits = [n](int ts) { return n % kTileShapes[ts].tx == 0 && n % kTileShapes[ts].ty == 0; };
+  if ((forced == 0 || forced == 2) && fits(forced)) return forced;
+  return n >= 128 && fits(2) ? 2 : 0;
+}
+
 template <int MODEL, typename T, bool CORR>
 void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_max,
                  const Cycle& K, int l) {
@@ -1155,15 +1169,22 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
   Lvl<T>* Dl = D + (size_t)l * count;
   Lvl<T>* Dc = D + (size_t)(l + 1) * count;
   const int n = R[l].n, nc = R[l + 1].n;
-  const dim3 grid(n / TILE_X, n / TILE_Y, count);
+  const int ts = batch_tile_shape(n);
+  const dim3 grid(n / kTileShapes[ts].tx, n / kTileShapes[ts].ty, count);
   int inb = 0;
   auto sweeps = [&](int total, bool pro, int res_last) {
     while (total > 0) {
       const int nsw = total >= 2 ? 2 : 1;
       const int res = (total == nsw) ? res_last : 0;
-#define HFZ_BT(NSW, PRO, RES)                                                                                 \
-  k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR><<<grid, TILE_THREADS, 0, K.stream>>>(Dl, Dc, Ps, B->active, inb, \
-                                                                                      B->partial, B->pstride)
+#define HFZ_BT(NSW, PRO, RES)                                                                                  \
+  do {                                                                                                         \
+    if (ts == 2)                                                                                               \
+      k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR, 2><<<grid, kTileShapes[2].nt, 0, K.stream>>>(             \
+          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride);                                                 \
+    else                                                                                                       \
+      k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR, 0><<<grid, kTileShapes[0].nt, 0, K.stream>>>(             \
+          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride);                                                 \
+  } while (0)
       if (nsw == 2) {
         if (pro) {
           if (res == 2) HFZ_BT(2, true, 2); else if (res == 1) HFZ_BT(2, true, 1); else HFZ_BT(2, true, 0);
@@ -1212,7 +1233,9 @@ template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
     bvcycle_rec<MODEL, double, false>(B, h0->H.L, B->D64, B->T64, B->P64, B->lds64, K, 0);
     const bool tiled_top = n > K.tail_n;
     if (tiled_top) {
-      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / TILE_X) * (n / TILE_Y), B->pstride, B->D64,
+      const int ts = batch_tile_shape(n);  // the shape of the level-0 launch that wrote the partial sums
+      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / kTileShapes[ts].tx) * (n / kTileShapes[ts].ty),
+                                                     B->pstride, B->D64,
                                                      B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
     } else {
       k_residual_partial_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);

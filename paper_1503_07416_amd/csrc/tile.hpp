@@ -259,9 +259,9 @@ __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fl
 // Batched form: instance blockIdx.z of equally sized instances, descriptors in
 // device arrays, skipped when not active.  The iterate is read from g (inb =
 // 0) or gb (inb = 1) and written to the other buffer; partial sums go to
-// partial + z * pstride.
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR>
-__global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile_b(const Lvl<T>* Ls, const Lvl<T>* Cs,
+// partial + z * pstride.  TS: tile shape (0 or 2).
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
+__global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile_b(const Lvl<T>* Ls, const Lvl<T>* Cs,
                                                                 const Phys<T>* Ps, const int* active, int inb,
                                                                 double* partial, int pstride) {
   const int z = blockIdx.z;
@@ -274,8 +274,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_sweeps_tile_b(const Lvl<T>* Ls
     b.c[c] = L.gb[c];
   }
   const Lvl<T> C = PRO ? lvl_global(Cs[z]) : L;
-  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR>(L, inb ? b : a, inb ? a : b, C, Ps[z],
-                                                  partial + (size_t)z * pstride);
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, inb ? b : a, inb ? a : b, C, Ps[z],
+                                                      partial + (size_t)z * pstride);
 }
 
 }  // namespace hfz
