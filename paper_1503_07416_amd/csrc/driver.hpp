@@ -75,9 +75,10 @@ template <int MODEL, typename T> void smooth_level(Hier<T>& H, Cycle& K, int l, 
 template <int MODEL, typename T, bool CORR> bool tail_plan(int top_n, int nt, size_t lds_max, int* d_from) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
   constexpr int WR = walls(MODEL) ? 1 : 0;
-  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB, NR, WR>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
+  constexpr int PMA = tail_pm<MODEL>();
+  if (nt > TAIL_MAX_LEVELS || tail_lds_count<NCm, NB, NR, WR, PMA>(top_n, nt, nt) * sizeof(T) > lds_max) return false;
   int df = nt;
-  while (df > 0 && tail_lds_count<NCm, NB, NR, WR>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
+  while (df > 0 && tail_lds_count<NCm, NB, NR, WR, PMA>(top_n, nt, df - 1) * sizeof(T) <= lds_max) --df;
   if (d_from) *d_from = df;
   return true;
 }
@@ -92,7 +93,8 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
   tail_plan<MODEL, T, CORR>(A.top_n, A.nt, H.tail_lds_max, &A.d_from);
-  const size_t sh = tail_lds_count<NCm, NB, NR, walls(MODEL) ? 1 : 0>(A.top_n, A.nt, A.d_from) * sizeof(T);
+  const size_t sh =
+      tail_lds_count<NCm, NB, NR, walls(MODEL) ? 1 : 0, tail_pm<MODEL>()>(A.top_n, A.nt, A.d_from) * sizeof(T);
   k_tail<MODEL, T, CORR><<<1, TAIL_THREADS, sh, K.stream>>>(A, H.P);
 }
 

@@ -1162,7 +1162,7 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
     A.nu2 = K.nu2;
     A.coarse_sweeps = K.coarse_sweeps;
     A.d_from = d_from;
-    const size_t sh = tail_lds_count<NCm, NB, NR>(A.top_n, A.nt, A.d_from) * sizeof(T);
+    const size_t sh = tail_lds_count<NCm, NB, NR, 0, tail_pm<MODEL>()>(A.top_n, A.nt, A.d_from) * sizeof(T);
     k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
     return;
   }

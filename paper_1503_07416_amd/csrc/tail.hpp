@@ -35,12 +35,17 @@ __host__ __device__ inline size_t tail_level_count(int n, int l, int nt, int d_f
   return (size_t)n * (n + WR) * (2 * NCm + NR + NB + (l > 0 ? NCm : 0) + (dl ? NCm : 0));
 }
 
-template <int NCm, int NB, int NR, int WR = 0>
+// PMA: scratch arrays of the top level's size after the levels (one for the
+// CDFT potential M, see tail_smooth).
+template <int NCm, int NB, int NR, int WR = 0, int PMA = 0>
 __host__ __device__ inline size_t tail_lds_count(int top_n, int nt, int d_from) {
   size_t tot = 0;
   for (int l = 0; l < nt; ++l) tot += tail_level_count<NCm, NB, NR, WR>(top_n >> l, l, nt, d_from);
-  return tot;
+  return tot + (size_t)PMA * top_n * (top_n + WR);
 }
+
+// Scratch arrays the tail of MODEL needs (tail_lds_count's PMA).
+template <int MODEL> constexpr int tail_pm() { return MODEL == CDFT ? 1 : 0; }
 
 // Level descriptors of the tail: S = the LDS arrays the phases use, G = the
 // global arrays.  Thread t builds level t (same LDS order as tail_lds_count).
@@ -121,17 +126,30 @@ template <int MODEL, typename T> __device__ __forceinline__ void tail_wall_rows(
   }
 }
 
+// One colour of a damped red-black sweep.  CDFT: the potential M (a logarithm
+// per node) is first evaluated once at each node of the other colour into sm
+// (its values are final for this half sweep), instead of at the four
+// neighbours of every updated node.
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour) {
+__device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour, T* sm) {
   // a channel updates its interior rows 1..n-1, then refreshes its wall rows
   constexpr int J0 = walls(MODEL) ? 1 : 0;
+  constexpr bool PM = tail_pm<MODEL>() > 0;
   const int n = L.n, cnt = (n >> 1) * (n - J0), lgh = L.lg - 1;
+  if constexpr (PM) {
+    for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
+      const int j = w >> lgh, t = w & ((1 << lgh) - 1);
+      const int p = (j << L.lg) + 2 * t + ((j + colour + 1) & 1);
+      sm[p] = potential_any<MODEL, T, CORR>(L.g, L.bg, p, P);
+    }
+    __syncthreads();
+  }
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int j = J0 + (w >> lgh), t = w & ((1 << lgh) - 1);
     const int i = 2 * t + ((j + colour) & 1);
     const Nbr q = nbr_of<MODEL>(i, j, n, L.lg);
     T out[NC<MODEL>::value];
-    update_any<MODEL, T, CORR>(L.g, L.f, L.bg, L.rk, L.om, q, q.p, L.k, P, out);
+    update_any<MODEL, T, CORR, PM>(L.g, L.f, L.bg, L.rk, L.om, q, q.p, L.k, P, out, sm);
 #pragma unroll
     for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][q.p] = out[c];
   }
@@ -140,30 +158,36 @@ __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, in
 }
 
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void tail_sweeps(const Lvl<T> L, const Phys<T>& P, int sweeps) {
+__device__ __forceinline__ void tail_sweeps(const Lvl<T> L, const Phys<T>& P, int sweeps, T* sm) {
   for (int k = 0; k < sweeps; ++k) {
-    tail_smooth<MODEL, T, CORR>(L, P, 0);
-    tail_smooth<MODEL, T, CORR>(L, P, 1);
+    tail_smooth<MODEL, T, CORR>(L, P, 0, sm);
+    tail_smooth<MODEL, T, CORR>(L, P, 1, sm);
   }
 }
 
 // FAS restriction in two phases: d = f - N(g) on the fine level and
 // g_c = g0_c = R g (correction form: also the coarse base R bg), then
-// f_c = R d + N_c(R g).
+// f_c = R d + N_c(R g).  CDFT: the potential M of g (then of R g) is evaluated
+// once per node into sm before the rows that read it at four neighbours.
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
+__device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P, T* sm) {
   // channel: d on the fine interior rows; R g on the coarse interior rows (their
   // footprints are fine interior rows) and the boundary values on the coarse
   // wall rows; f_c on the coarse interior rows
   constexpr int NCm = NC<MODEL>::value;
   constexpr bool WL = walls(MODEL);
+  constexpr bool PM = tail_pm<MODEL>() > 0;
   const int fcnt = F.n * F.ny;
+  if constexpr (PM) {
+    for (int w = threadIdx.x; w < fcnt; w += blockDim.x) sm[w] = potential_any<MODEL, T, CORR>(F.g, F.bg, w, P);
+    __syncthreads();
+  }
   for (int w = threadIdx.x; w < fcnt; w += blockDim.x) {
     const int j = w >> F.lg;
     if (WL && (j == 0 || j == F.n)) continue;
     const Nbr q = nbr_of<MODEL>(w & (F.n - 1), j, F.n, F.lg);
     T nv[NCm];
-    rows_any<MODEL, T, CORR>(F.g, F.bg, F.rk, F.om, q, q.p, F.k, P, nv);
+    rows_any<MODEL, T, CORR, PM>(F.g, F.bg, F.rk, F.om, q, q.p, F.k, P, nv, sm);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) F.d[c][q.p] = F.f[c][q.p] - nv[c];
   }
@@ -204,12 +228,16 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
     }
     __syncthreads();
   }
+  if constexpr (PM) {
+    for (int w = threadIdx.x; w < cnt; w += blockDim.x) sm[w] = potential_any<MODEL, T, CORR>(C.g0, C.bg, w, P);
+    __syncthreads();
+  }
   for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
     const int J = w >> C.lg, I = w & (C.n - 1);
     if (WL && (J == 0 || J == C.n)) continue;
     const Nbr q = nbr_of<MODEL>(I, J, C.n, C.lg);
     T nv[NCm];
-    rows_any<MODEL, T, CORR>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv);
+    rows_any<MODEL, T, CORR, PM>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv, sm);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) C.f[c][w] = fw9(F.d[c], 2 * I, 2 * J, F.n, F.lg) + nv[c];
   }
@@ -267,6 +295,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   __shared__ Lvl<T> S[TAIL_MAX_LEVELS];
   __shared__ Lvl<T> G[TAIL_MAX_LEVELS];
   tail_lds_levels<NCm, NB, NR, WR, T>(A, reinterpret_cast<T*>(tail_smem), S, G);
+  // the scratch array after the levels (CDFT potential)
+  T* sm = tail_pm<MODEL>() ? as_lds(reinterpret_cast<T*>(tail_smem) + tail_lds_count<NCm, NB, NR, WR>(A.top_n, A.nt, A.d_from))
+                           : nullptr;
   __syncthreads();
   // load: every global value a thread moves is read before it is stored
   for (int l = 0; l < A.nt; ++l) {
@@ -308,17 +339,17 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
     const Lvl<T> F = tail_view<NCm, NB, NR, false>(S[l]);
-    tail_sweeps<MODEL, T, CORR>(F, P, A.nu1);
+    tail_sweeps<MODEL, T, CORR>(F, P, A.nu1, sm);
     if (l >= A.d_from)
-      tail_restrict<MODEL, T, CORR>(tail_view<NCm, NB, NR, false, true>(S[l]), tail_view<NCm, NB, NR, true>(S[l + 1]), P);
+      tail_restrict<MODEL, T, CORR>(tail_view<NCm, NB, NR, false, true>(S[l]), tail_view<NCm, NB, NR, true>(S[l + 1]), P, sm);
     else
-      tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, NR, true>(S[l + 1]), P);
+      tail_restrict<MODEL, T, CORR>(F, tail_view<NCm, NB, NR, true>(S[l + 1]), P, sm);
   }
-  tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, NR, false>(S[last]), P, A.coarse_sweeps);
+  tail_sweeps<MODEL, T, CORR>(tail_view<NCm, NB, NR, false>(S[last]), P, A.coarse_sweeps, sm);
   for (int l = last - 1; l >= 0; --l) {
     const Lvl<T> F = tail_view<NCm, NB, NR, false>(S[l]);
     tail_prolong<MODEL, T, CORR>(F, tail_view<NCm, NB, NR, true>(S[l + 1]), P);
-    tail_sweeps<MODEL, T, CORR>(F, P, A.nu2);
+    tail_sweeps<MODEL, T, CORR>(F, P, A.nu2, sm);
   }
   {
     const Lvl<T> s = tail_view<NCm, NB, NR, false>(S[0]);
