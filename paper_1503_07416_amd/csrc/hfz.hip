@@ -1069,6 +1069,7 @@ const char* hfz_strerror(int code) {
 struct hfz_batch {
   int count = 0;
   hfz_params p{};  // model, n, precision, nu1, nu2, ... shared by all instances
+  int tile_force = -1;  // smoother tile shape forced by HFZ_BATCH_TILE at init (-1: by level size)
   hipStream_t stream = nullptr;
   std::vector<hfz_handle*> inst;
   int nlev = 0;
@@ -1134,14 +1135,10 @@ BatchLayout batch_layout(const hfz_params* ps, int count) {
 }
 
 // Tile shape of the batched smoother on an n x n level: 64x16 tiles of 512
-// threads (shape 2) from 128^2 up, else 32x16 of 256 (shape 0); the
-// environment variable HFZ_BATCH_TILE (0 or 2) overrides it where the shape
-// divides n.
-int batch_tile_shape(int n) {
-  static const int forced = [] {
-    const char* e = std::getenv("HFZ_BATCH_TILE");
-    return e ? std::atoi(e) : -1;
-  }();
+// threads (shape 2) from 128^2 up, else 32x16 of 256 (shape 0); forced (0 or
+// 2, from the environment variable HFZ_BATCH_TILE at hfz_batch_init)
+// overrides it where the shape divides n.
+int batch_tile_shape(int n, int forced) {
   const auto fits = [n](int ts) { return n % kTileShapes[ts].tx == 0 && n % kTileShapes[ts].ty == 0; };
   if ((forced == 0 || forced == 2) && fits(forced)) return forced;
   return n >= 128 && fits(2) ? 2 : 0;
@@ -1169,7 +1166,7 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
   Lvl<T>* Dl = D + (size_t)l * count;
   Lvl<T>* Dc = D + (size_t)(l + 1) * count;
   const int n = R[l].n, nc = R[l + 1].n;
-  const int ts = batch_tile_shape(n);
+  const int ts = batch_tile_shape(n, B->tile_force);
   const dim3 grid(n / kTileShapes[ts].tx, n / kTileShapes[ts].ty, count);
   int inb = 0;
   auto sweeps = [&](int total, bool pro, int res_last) {
@@ -1233,7 +1230,7 @@ template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
     bvcycle_rec<MODEL, double, false>(B, h0->H.L, B->D64, B->T64, B->P64, B->lds64, K, 0);
     const bool tiled_top = n > K.tail_n;
     if (tiled_top) {
-      const int ts = batch_tile_shape(n);  // the shape of the level-0 launch that wrote the partial sums
+      const int ts = batch_tile_shape(n, B->tile_force);  // the shape of the level-0 launch that wrote the partial sums
       k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / kTileShapes[ts].tx) * (n / kTileShapes[ts].ty),
                                                      B->pstride, B->D64,
                                                      B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
@@ -1360,6 +1357,7 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   if (!B) return HFZ_ENOMEM;
   B->count = count;
   B->p = params[0];
+  if (const char* e = std::getenv("HFZ_BATCH_TILE")) B->tile_force = std::atoi(e);
   B->stream = static_cast<hipStream_t>(hip_stream);
   const BatchLayout bl = batch_layout(params, count);
   char* base = static_cast<char*>(dev_ws);
