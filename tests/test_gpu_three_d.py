@@ -222,3 +222,47 @@ def test_full_size_step():
     for x, y in zip([np_(t) for t in sim.get_state()], staged):
         assert np.abs(x - y).max() <= 1e-12 * max(np.abs(y).max(), 1e-30)
     sim.close()
+
+
+def test_sweep_sampled_at_256():
+    """256^3, one sweep of the z-marching tiled kernel in the launch bench.py
+    times (2048 workgroups, 256 per XCD): at sampled nodes (random ones and
+    ones on tile, z-chunk and periodic boundaries) the GPU's value equals the
+    oracle's sweep of a 12^3 patch around the node.  A node's value after one
+    red-black sweep depends on the state within two nodes of it (its red
+    neighbours' new values read black values one node further, and S, omega^k,
+    mu, kappa read one node beyond those), so the patch's periodic wrap, which
+    corrupts values within two nodes of its edge, does not reach it; the patch
+    origin keeps the colour (i + j + l) mod 2 of the global grid."""
+    import paper_1503_07416_amd as pkg
+    n, P = 256, 12
+    cfg, rho, u, v, w = workloads.pfc3d(n, seed=3, uamp=0.02)
+    sim = pkg.Simulation3(cfg)
+    sim.set_state(rho, u, v, w)
+    sim.begin_step()
+    sim.smooth(0, 1)
+    rng = np.random.default_rng(17)
+    pts = [tuple(int(x) for x in rng.integers(0, n, 3)) for _ in range(48)]
+    pts += [(0, 0, 0), (n - 1, n - 1, n - 1), (31, 15, 15), (32, 16, 16), (95, 47, 111), (96, 48, 112),
+            (63, 0, 255), (224, 255, 0), (1, 17, 33), (30, 14, 14)]
+    idx = np.array([(l * n + j) * n + i for i, j, l in pts])
+    gpu = np.stack([sim.read(0, 0, c).reshape(-1)[idx].cpu().numpy() for c in range(6)])
+    for k, (i, j, l) in enumerate(pts):
+        par = (i + j + l) & 1
+        o = [i - 6 - par, j - 6, l - 6]          # origin with even coordinate sum: colours agree
+        ii = (np.arange(P) + o[0]) % n
+        jj = (np.arange(P) + o[1]) % n
+        ll = (np.arange(P) + o[2]) % n
+        cut = lambda f: f[np.ix_(ll, jj, ii)]
+        st = t3.Stepper(P, cfg.h, cfg.s, cfg.alpha, gamma=cfg.gamma, sigma=cfg.sigma)
+        st.set_state(cut(rho), cut(u), cut(v), cut(w))
+        S, om = st.build_source()
+        lev = t3.Level3(cfg.h, cfg.s, cfg.gamma, cfg.sigma, cfg.alpha, st.g[0], om)
+        g = st.g.copy()
+        t3.sweep(g, S, lev, cfg.w)
+        lc = (6 + par, 6, 6)                     # the sample in the patch (x, y, z)
+        inner = g[:, 2:-2, 2:-2, 2:-2]
+        for c in range(6):
+            ref = g[c, lc[2], lc[1], lc[0]]
+            scale = max(np.abs(inner[c]).max(), 1e-300)
+            assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j, l), c, gpu[c, k], ref)
