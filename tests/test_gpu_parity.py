@@ -227,3 +227,34 @@ def test_mixed_precision_steps(model, n, steps):
     print(f"mixed {model} {n}^2: max rel err vs FP64 oracle {worst:.2e}")
     E = sim.energy()
     assert abs(E[0] - ora.energy()[0]) < 1e-6 * abs(ora.energy()[0])
+
+
+# the tuner picks among these by timing at init; each is forced here once
+SHAPES = [(32, 16, 256), (32, 16, 512), (64, 16, 512), (16, 16, 256)]
+VARIANTS = ([("HFZ_TILE", str(t)) for t in range(len(SHAPES))] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
+            + [("HFZ_SWEEPS", "1")])
+
+
+@pytest.mark.parametrize("model", ["pfc", "cdft"])
+@pytest.mark.parametrize("var", VARIANTS, ids=[f"{k}={v}" for k, v in VARIANTS])
+def test_forced_kernel_variants(model, var, monkeypatch):
+    """Every tile shape of the tiled smoother, every FAS restriction variant
+    and the one-sweep-per-launch schedule, each forced through its
+    environment variable (read at init) at 128^2: two V-cycles agree with the
+    oracle's, so whichever the tuner picks on a device is covered."""
+    monkeypatch.setenv(*var)
+    cfg, rho, u, vel = CASES[model](n=128)
+    sim = sim_for(cfg, rho, u, vel)
+    if var[0] == "HFZ_TILE":
+        assert sim.tile_shape(0) == SHAPES[int(var[1])]
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, vel)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    g = ora.initial_guess()
+    for k in range(2):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(g.shape[0])]
+        assert max(errs) < 1e-11, (k, errs)
