@@ -200,3 +200,29 @@ def test_full_size_step(model, n):
     assert F1 <= F0 + 1e-12 * abs(F0)
     assert abs(m1 - m0) <= 1e-13 * abs(m0)
     sim.close()
+
+
+# the tuner picks among these by timing at init; each is forced here once
+VARIANTS = ([("HFZ_TILE", str(t)) for t in range(4)] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
+            + [("HFZ_SWEEPS", "1")])
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("var", VARIANTS, ids=[f"{k}={v}" for k, v in VARIANTS])
+def test_forced_kernel_variants(model, var, monkeypatch):
+    """Each tile shape, restriction variant and the one-sweep schedule, forced
+    at 128^2: two V-cycles of the gradient flow agree with the oracle's."""
+    monkeypatch.setenv(*var)
+    cfg, rho, _, _ = case(model, 128, seed=4)
+    sim = sim_for(cfg, rho)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho)
+    sim.begin_step()
+    S = ora.build_source()
+    sol = ora.solver()
+    g = ora.initial_guess()
+    for k in range(2):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(g.shape[0])]
+        assert max(errs) < 1e-11, (k, errs)

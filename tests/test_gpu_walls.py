@@ -189,3 +189,29 @@ def test_full_size_step():
     for x, y in zip([np_(t) for t in sim.get_state()], staged):
         assert np.abs(x - y).max() <= 1e-12 * max(np.abs(y).max(), 1e-30)
     sim.close()
+
+
+# the tuner picks among these by timing at init; each is forced here once
+VARIANTS = ([("HFZ_TILE", str(t)) for t in range(4)] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
+            + [("HFZ_SWEEPS", "1")])
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=[f"{k}={v}" for k, v in VARIANTS])
+def test_forced_kernel_variants(var, monkeypatch):
+    """Each tile shape, restriction variant and the one-sweep schedule, forced
+    on a 128 x 129 channel: two V-cycles agree with the oracle's."""
+    monkeypatch.setenv(*var)
+    cfg, rho, _, _ = case(128, seed=5)
+    u, v = random_flow(128, 15)
+    sim = sim_for(cfg, rho, u, v)
+    ora = oracle_stepper(cfg)
+    ora.set_state(rho, u, v)
+    sim.begin_step()
+    S, om = ora.build_source()
+    sol = ora.solver(om)
+    g = ora.g.copy()
+    for k in range(2):
+        sim.vcycle(1)
+        sol.vcycle(g, S)
+        errs = [rel_err(np_(sim.read(0, 0, c)), g[c]) for c in range(5)]
+        assert max(errs) < 1e-11, (k, errs)
