@@ -1,6 +1,6 @@
 """GPU at the benchmark sizes: PFC 512^2 (FP64 and mixed precision) and CDFT
-1024^2 (FP64), with the kernels, tile shapes and restriction variants the
-tuner picks for the benchmark.  The oracle cannot run FAS at these sizes in
+1024^2 (FP64), and at CDFT's largest grid, 2048^2, with the kernels, tile
+shapes and restriction variants the tuner picks there.  The oracle cannot run FAS at these sizes in
 seconds, but it can evaluate the paper's system there in one vectorised pass,
 so the checks are properties that hold at any size:
 
@@ -27,6 +27,7 @@ CASES = {
     "pfc512": lambda: workloads.config2(0),
     "pfc512_mixed": lambda: workloads.config2(0, precision="mixed"),
     "cdft1024": lambda: workloads.config3(0),
+    "cdft2048": lambda: workloads.config3(1, n=2048),   # the largest CDFT grid the ABI accepts
 }
 
 
