@@ -1,5 +1,6 @@
 """GPU at the largest grids the ABI accepts, in the launch configuration the
-tuner picks there: PFC 8192^2 (two damped sweeps) and the 3D step at 512^3
+tuner picks there: PFC 8192^2 (two damped sweeps), the PFC gradient flow at
+8192^2 (two sweeps) and the 3D step at 512^3
 (one sweep of the z-marching tiled kernel).  At sampled nodes (random ones and
 ones on tile and periodic boundaries) the GPU's value equals the oracle's
 sweeps of a small patch around the node: after k red-black sweeps a node's
@@ -14,6 +15,7 @@ import pytest
 
 import workloads
 from oracle import fas, smoother
+from oracle import gradflow as gf
 from oracle import three_d as t3
 
 pytestmark = pytest.mark.gpu
@@ -85,3 +87,37 @@ def test_pfc3d_512_sweep_sampled():
             ref = g[c, 6, 6, 6 + par]
             scale = max(np.abs(inner[c]).max(), 1e-300)
             assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j, l), c, gpu[c, k], ref)
+
+
+def test_pfc_gradflow_8192_two_sweeps_sampled():
+    import paper_1503_07416_amd as pkg
+    n, P, R = 8192, 24, 8
+    cfg, rho, _, _ = workloads.gradflow("pfc_gf", n, 9)
+    print("pfc_gf 8192: init", flush=True)
+    sim = pkg.Simulation(cfg)
+    sim.set_state(rho)
+    tx, ty, _ = sim.tile_shape(0)
+    sim.begin_step()
+    sim.smooth(0, 2)
+    rng = np.random.default_rng(25)
+    pts = [tuple(int(x) for x in rng.integers(0, n, 2)) for _ in range(40)]
+    pts += [(0, 0), (n - 1, n - 1), (tx - 1, ty - 1), (tx, ty), (n - 1, 0)]
+    idx = np.array([j * n + i for i, j in pts])
+    nc = 3
+    gpu = np.stack([sim.read(0, 0, c).reshape(-1)[idx].cpu().numpy() for c in range(nc)])
+    for k, (i, j) in enumerate(pts):
+        par = (i + j) & 1
+        ii = (np.arange(P) + i - R - par) % n
+        jj = (np.arange(P) + j - R) % n
+        st = gf.Stepper(cfg.base_model, P, cfg.h, cfg.s, **cfg.oracle_kwargs())
+        st.set_state(rho[np.ix_(jj, ii)])
+        S = st.build_source()
+        lev = st.solver().levels[0]
+        g = st.initial_guess()
+        gf.sweep(g, S, lev, cfg.w)
+        gf.sweep(g, S, lev, cfg.w)
+        inner = g[:, 6:-6, 6:-6]
+        for c in range(nc):
+            ref = g[c, R, R + par]
+            scale = max(np.abs(inner[c]).max(), 1e-300)
+            assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j), c, gpu[c, k], ref)
