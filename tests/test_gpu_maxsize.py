@@ -1,6 +1,8 @@
 """GPU at the largest grids the ABI accepts, in the launch configuration the
 tuner picks there: PFC 8192^2 (two damped sweeps), the PFC gradient flow at
-8192^2 (two sweeps) and the 3D step at 512^3
+8192^2 (two sweeps), the channel at 8192 x 8193 (two sweeps; the patch takes
+the true wall as its own where the node is near one, elsewhere both patch
+walls are far from it) and the 3D step at 512^3
 (one sweep of the z-marching tiled kernel).  At sampled nodes (random ones and
 ones on tile and periodic boundaries) the GPU's value equals the oracle's
 sweeps of a small patch around the node: after k red-black sweeps a node's
@@ -17,6 +19,7 @@ import workloads
 from oracle import fas, smoother
 from oracle import gradflow as gf
 from oracle import three_d as t3
+from oracle import walls
 
 pytestmark = pytest.mark.gpu
 
@@ -120,4 +123,41 @@ def test_pfc_gradflow_8192_two_sweeps_sampled():
         for c in range(nc):
             ref = g[c, R, R + par]
             scale = max(np.abs(inner[c]).max(), 1e-300)
+            assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j), c, gpu[c, k], ref)
+
+
+def test_channel_8192_two_sweeps_sampled():
+    import paper_1503_07416_amd as pkg
+    n, P, H = 8192, 24, 12
+    cfg, rho, u, v = workloads.channel(n, u_wall=0.1, seed=6, amp=0.05)
+    rng = np.random.default_rng(27)
+    u = u + 0.02 * rng.standard_normal(u.shape)
+    v = v + 0.02 * rng.standard_normal(v.shape)
+    print("channel 8192: init", flush=True)
+    sim = pkg.Simulation(cfg)
+    sim.set_state(rho, u, v)
+    sim.begin_step()
+    sim.smooth(0, 2)
+    pts = [(int(rng.integers(0, n)), int(rng.integers(0, n + 1))) for _ in range(32)]
+    pts += [(0, 0), (5, 1), (n - 1, 3), (17, n - 2), (n - 7, n), (4096, 4096), (31, 15), (32, 16)]
+    idx = np.array([j * n + i for i, j in pts])
+    gpu = np.stack([sim.read(0, 0, c).reshape(-1)[idx].cpu().numpy() for c in range(5)])
+    kw = cfg.wall_oracle_kwargs()
+    for k, (i, j) in enumerate(pts):
+        j0 = min(max(j - H, 0), n - P)
+        ox = i - H
+        ox -= (ox + j0) & 1                       # keeps the colour (i + j) mod 2
+        ii = (np.arange(P) + ox) % n
+        jj = np.arange(P + 1) + j0
+        cut = lambda f: f[np.ix_(jj, ii)]
+        st = walls.Stepper(P, cfg.h, cfg.s, cfg.alpha, **kw)
+        st.set_state(cut(rho), cut(u), cut(v))
+        S, om = st.build_source()
+        lev = st.solver(om).levels[0]
+        g = st.g.copy()
+        walls.sweep(g, S, lev, cfg.w)
+        walls.sweep(g, S, lev, cfg.w)
+        for c in range(5):
+            ref = g[c, j - j0, i - ox]
+            scale = max(np.abs(g[c]).max(), 1e-300)
             assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j), c, gpu[c, k], ref)
