@@ -58,6 +58,26 @@
  *    mass, residual) synchronise that stream.
  *  - A handle is not thread safe; distinct handles with distinct workspaces
  *    may be used concurrently.
+ *
+ * Kernel choice.  Results do not depend on it beyond rounding; the library
+ * picks by level size and, for the 2D tiled kernels, by timing candidates at
+ * hfz_init (cached per process).  Environment variables, read at init
+ * (hfz_init, hfz_batch_init, hfz3_init), override the choices for testing
+ * and measurement:
+ *    HFZ_TILE=<0..3>      tile shape of the 2D smoother where it fits
+ *    HFZ_RESTRICT=<0..3>  FAS restriction variant where it fits
+ *    HFZ_SWEEPS=1         one sweep per smoother launch (default: two fused)
+ *    HFZ_TUNE=0           no timing: shape 0, variant 0, fused sweeps
+ *    HFZ_TILES=0          per-colour smoother kernels instead of the tiled one
+ *                         (FP64 periodic only; mixed precision and the
+ *                         channel always use the tiled kernels)
+ *    HFZ_TAIL_N=<n>       largest level of the one-workgroup tail (0: none)
+ *    HFZ_GRAPH=0          no HIP graph capture of the V-cycle
+ *    HFZ_MP_INNER=<1..8>  FP32 V-cycles per outer FP64 iteration (mixed)
+ *    HFZ_BATCH_TILE=<0|2> tile shape of the batched smoother
+ *    HFZ3_TILES=<n>       smallest 3D level swept by the tiled kernel (0: none)
+ *    HFZ3_TAIL=0          no one-workgroup tail in 3D
+ *    HFZ_VERBOSE=1        the choices made, on stderr
  */
 #ifndef HFZ_H
 #define HFZ_H
