@@ -266,3 +266,27 @@ def test_sweep_sampled_at_256():
             ref = g[c, lc[2], lc[1], lc[0]]
             scale = max(np.abs(inner[c]).max(), 1e-300)
             assert abs(gpu[c, k] - ref) <= 1e-12 * scale, ((i, j, l), c, gpu[c, k], ref)
+
+
+@pytest.mark.parametrize("n", [16, 128])
+def test_step_that_does_not_converge_leaves_state(n):
+    """A step that reaches max_cycles before the tolerance returns
+    HFZ_ENOCONV, completes no step and leaves the state as it was (through
+    the one-workgroup tail at 16^3, through the tiled sweep and the device
+    stop test at 128^3); the next step with enough cycles then converges."""
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v, w = workloads.pfc3d(n, seed=9, uamp=0.02)
+    cfg.max_cycles = 2
+    sim = pkg.Simulation3(cfg)
+    sim.set_state(rho, u, v, w)
+    before = [np_(x) for x in sim.get_state()]
+    rc, st = sim.step(1, raise_on_error=False)
+    assert rc == -4 and st.steps_done == 0
+    after = [np_(x) for x in sim.get_state()]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    cfg.max_cycles = 100
+    sim2 = pkg.Simulation3(cfg)
+    sim2.set_state(rho, u, v, w)
+    st2 = sim2.step(1)
+    assert st2.steps_done == 1 and st2.cycles_last > 2 and st2.residual_last <= cfg.tol
