@@ -130,9 +130,14 @@ template <int MODEL, typename T> __device__ __forceinline__ void tail_wall_rows(
 // per node) is first evaluated once at each node of the other colour into sm
 // (its values are final for this half sweep), instead of at the four
 // neighbours of every updated node.
+//
+// A channel updates its interior rows 1..n-1; the updater of a node on row 1
+// (n - 1) also writes the wall copies of rho, mu, kappa on row 0 (n) below
+// (above) it.  No other update of the half sweep reads that wall node, and a
+// wall node next to a node of the other colour already holds its value, so
+// the wall rows end the half sweep as a refresh of them would leave them.
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, int colour, T* sm) {
-  // a channel updates its interior rows 1..n-1, then refreshes its wall rows
   constexpr int J0 = walls(MODEL) ? 1 : 0;
   constexpr bool PM = tail_pm<MODEL>() > 0;
   const int n = L.n, cnt = (n >> 1) * (n - J0), lgh = L.lg - 1;
@@ -152,9 +157,16 @@ __device__ __forceinline__ void tail_smooth(const Lvl<T> L, const Phys<T>& P, in
     update_any<MODEL, T, CORR, PM>(L.g, L.f, L.bg, L.rk, L.om, q, q.p, L.k, P, out, sm);
 #pragma unroll
     for (int c = 0; c < NC<MODEL>::value; ++c) L.g[c][q.p] = out[c];
+    if constexpr (walls(MODEL)) {
+      if (j == 1 || j == n - 1) {
+        const int wp = (j == 1 ? 0 : n << L.lg) + i;
+#pragma unroll
+        for (int c = 0; c < NC<MODEL>::value; ++c)
+          if (wall_copied(c)) L.g[c][wp] = out[c];
+      }
+    }
   }
   __syncthreads();
-  tail_wall_rows<MODEL, T>(L);
 }
 
 template <int MODEL, typename T, bool CORR>
