@@ -59,9 +59,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   // instead of at each of their four neighbours.
   constexpr bool PM = MODEL == CDFT;
   // channel (walls in y): rows outside 0..n are not loaded, only interior rows
-  // are updated, and the wall rows of rho, mu, kappa are refreshed in LDS
-  // after every half sweep (the block touching a wall holds both it and the
-  // adjacent row: its region spans H >= 2 rows beyond its owned block)
+  // are updated, and the wall rows of rho, mu, kappa in LDS follow the
+  // adjacent rows: refreshed after the fused prolongation, and written by the
+  // updaters of rows 1 and n - 1 in each half sweep (the block touching a
+  // wall holds both it and the adjacent row: its region spans H >= 2 rows
+  // beyond its owned block)
   constexpr bool WL = walls(MODEL);
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RK ? RN : 1];
@@ -192,9 +194,19 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
+      if constexpr (WL) {
+        // the wall copies of rho, mu, kappa next to a node on row 1 or n - 1:
+        // no other update of this half sweep reads them, and the wall nodes
+        // next to nodes not updated here already hold their values
+        if (y0 + ly == 1 || y0 + ly == nn - 1) {
+          const int wp = q.p + (y0 + ly == 1 ? -RX : RX);
+#pragma unroll
+          for (int c = 0; c < NCm; ++c)
+            if (wall_copied(c)) sg[c][wp] = out[c];
+        }
+      }
     }
     __syncthreads();
-    if constexpr (WL) wall_refresh();
   }
   if constexpr (PM && RES != 0) {
     // M on the owned block and its one-node ring, for the residual rows
