@@ -93,8 +93,9 @@ def lap(f, h):
 # --- inner products and norms (App. E, "Discrete Norms") --------------------
 
 def ip(a, b, h):
-    """(a || b) = h^2 sum a b."""
-    return h * h * float(np.sum(np.asarray(a) * np.asarray(b)))
+    """(a || b) = h^2 sum a b (a NumPy scalar: float64 for real grid functions,
+    complex128 for the complex-step derivative checks of the energies)."""
+    return h * h * np.sum(np.asarray(a) * np.asarray(b))
 
 
 def norm2(a, h):
