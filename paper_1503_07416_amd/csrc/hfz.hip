@@ -26,6 +26,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kTailLdsMax = 160 * 1024;
+constexpr int kTailNMax = 32;  // largest level the one-workgroup tail kernel takes
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -81,6 +82,12 @@ int validate(const hfz_params* p) {
   if (p->walls != 0 && p->walls != 1) return HFZ_EINVAL;
   if (p->walls && (p->model != HFZ_PFC || p->precision != HFZ_FP64 || p->nu1 < 1 || p->nu2 < 1 ||
                    !std::isfinite(p->u_wall_bottom) || !std::isfinite(p->u_wall_top)))
+    return HFZ_EINVAL;
+  // The FP32 correction-form inner solve and the channel run only on the
+  // tiled kernels, whose pre-sweep launch leaves the residual field and whose
+  // first post-sweep launch applies the coarse-grid correction, and on the
+  // one-workgroup tail, which must hold the coarsest level.
+  if ((p->precision == HFZ_MIXED || p->walls) && (p->nu1 < 1 || p->nu2 < 1 || p->coarsest_n > kTailNMax))
     return HFZ_EINVAL;
   return HFZ_OK;
 }
@@ -291,6 +298,18 @@ size_t lds_optin(const void* kernel) {
   }
   (void)hipGetLastError();
   return got;
+}
+
+// Whether the one-workgroup tail holds every level from the first one of
+// size <= tail_n down to the coarsest: the tiled V-cycle path has no
+// coarsest-level smoother, so the correction form, the channel and the batch
+// need the coarsest level in the tail.
+template <int MODEL, typename T, bool CORR> bool tail_holds_bottom(const std::vector<Lvl<T>>& L, int tail_n,
+                                                                   size_t lds_max) {
+  const int nlev = (int)L.size();
+  for (int l = 0; l < nlev; ++l)
+    if (L[l].n <= tail_n) return tail_plan<MODEL, T, CORR>(L[l].n, nlev - l, lds_max, nullptr);
+  return false;
 }
 
 // ---- V-cycle entry points (driver.hpp) -------------------------------------
@@ -774,9 +793,20 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   if (p->precision == HFZ_MIXED || p->walls) {
     // the correction-form inner solve, and a channel, run only on the tiled
     // and tail kernels: every level above the tail must be tileable (>= 32
-    // with a >= 16 coarse)
+    // with a >= 16 coarse), and the coarsest level (<= 32, validate()) must
+    // be a tail level
     hd->use_tiles = true;
-    if (hd->tail_n < 16) hd->tail_n = 32;
+    if (hd->tail_n < 16) hd->tail_n = kTailNMax;
+    hd->tail_n = std::max(hd->tail_n, p->coarsest_n);
+    const bool held = by_model(hd->km, [&](auto m) {
+      constexpr int M = decltype(m)::value;
+      return p->precision == HFZ_MIXED ? tail_holds_bottom<M, float, true>(hd->H32.L, hd->tail_n, hd->H32.tail_lds_max)
+                                       : tail_holds_bottom<M, double, false>(hd->H.L, hd->tail_n, hd->H.tail_lds_max);
+    });
+    if (!held) {
+      delete hd;
+      return HFZ_EINVAL;
+    }
   }
   if (hd->use_tiles) {
     const Cycle K = cycle_ctx(hd);
@@ -1339,7 +1369,9 @@ int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes
     if (model_gf(params[i].model) || params[i].walls) return HFZ_EINVAL;
     if (!batch_compatible(params[0], params[i])) return HFZ_EINVAL;
   }
-  if (params[0].nu1 < 1 || params[0].nu2 < 1) return HFZ_EINVAL;
+  // the batched V-cycle runs the tiled kernels above the one-workgroup tail,
+  // which takes the coarsest level
+  if (params[0].nu1 < 1 || params[0].nu2 < 1 || params[0].coarsest_n > kTailNMax) return HFZ_EINVAL;
   *bytes = batch_layout(params, count).total;
   return HFZ_OK;
 }
@@ -1368,8 +1400,10 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
       hfz_batch_destroy(B);
       return rc;
     }
-    // the batched cycle needs every level above the tail tileable
-    if (h->tail_n < 16) h->tail_n = 32;
+    // the batched cycle needs every level above the tail tileable and the
+    // coarsest level (<= 32, hfz_batch_workspace_bytes) in the tail
+    if (h->tail_n < 16) h->tail_n = kTailNMax;
+    h->tail_n = std::max(h->tail_n, params[i].coarsest_n);
     h->use_tiles = true;
     B->inst.push_back(h);
   }
@@ -1418,6 +1452,18 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   } else {
     B->lds64 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, double, false>));
     B->lds32 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, float, true>));
+  }
+  {
+    hfz_handle* h0 = B->inst[0];
+    const bool held = B->p.model == HFZ_PFC
+                          ? (mixed ? tail_holds_bottom<PFC, float, true>(h0->H32.L, h0->tail_n, B->lds32)
+                                   : tail_holds_bottom<PFC, double, false>(h0->H.L, h0->tail_n, B->lds64))
+                          : (mixed ? tail_holds_bottom<CDFT, float, true>(h0->H32.L, h0->tail_n, B->lds32)
+                                   : tail_holds_bottom<CDFT, double, false>(h0->H.L, h0->tail_n, B->lds64));
+    if (!held) {
+      hfz_batch_destroy(B);
+      return HFZ_EINVAL;
+    }
   }
   B->h_active.assign(count, 1);
   B->h_norm2.assign(count, 0.0);

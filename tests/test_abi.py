@@ -122,3 +122,62 @@ def test_three_d_workspace_and_validation():
                 dict(nu1=0, nu2=0), dict(coarse_sweeps=0), dict(sigma=0), dict(tol=0.0)]:
         rc, _ = ws3(**bad)
         assert rc == -1, bad
+
+
+def test_cycle_shapes_the_tiled_paths_cannot_run_are_refused():
+    """The FP32 correction-form inner solve (mixed precision), the channel and
+    the batch run only on the tiled kernels, whose pre-sweep launch writes the
+    residual field and whose first post-sweep launch applies the coarse-grid
+    correction, and on the one-workgroup tail (levels <= 32^2), which must hold
+    the coarsest level.  So nu1 = 0, nu2 = 0 and coarsest_n > 32 are refused
+    there (HFZ_EINVAL, host only), while the FP64 periodic solve, which has
+    per-level kernels for them, accepts them."""
+    lib = hfz.load()
+    for kw in [dict(nu1=0), dict(nu2=0), dict(coarsest_n=64)]:
+        assert ws(n=256, precision=1, **kw)[0] == -1, kw
+        assert ws(n=256, walls=1, **kw)[0] == -1, kw
+        assert ws(n=256, **kw)[0] == 0, kw
+    assert ws(n=256, precision=1, coarsest_n=32)[0] == 0
+    assert ws(n=256, precision=1, nu1=1, nu2=1)[0] == 0
+    assert ws(model=1, n=256, precision=1, nu1=0, nu2=3)[0] == -1
+    for kw, want in [(dict(coarsest_n=64), -1), (dict(coarsest_n=32), 0), (dict(nu1=0), -1),
+                     (dict(coarsest_n=8), 0)]:
+        for precision in (0, 1):
+            p = hfz.Params()
+            assert lib.hfz_default_params(0, ctypes.byref(p)) == 0
+            p.n, p.precision = 256, precision
+            for k, v in kw.items():
+                setattr(p, k, v)
+            arr = (hfz.Params * 2)(p, p)
+            nb = ctypes.c_size_t(0)
+            assert lib.hfz_batch_workspace_bytes(arr, 2, ctypes.byref(nb)) == want, (kw, precision)
+
+
+def test_workspace_too_small_is_enomem():
+    """hfz_init, hfz_batch_init and hfz3_init refuse a workspace smaller than
+    the size the *_workspace_bytes call reports with HFZ_ENOMEM, before any
+    device work (the pointer is never dereferenced)."""
+    lib = hfz.load()
+    fake = ctypes.c_void_p(1 << 20)  # a 256-byte aligned address nothing reads
+    out = ctypes.c_void_p(None)
+    for model in (0, 1, 2, 3):
+        p = hfz.Params()
+        assert lib.hfz_default_params(model, ctypes.byref(p)) == 0
+        p.n = 64
+        nb = ctypes.c_size_t(0)
+        assert lib.hfz_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+        assert lib.hfz_init(ctypes.byref(p), fake, nb.value - 1, None, ctypes.byref(out)) == -2
+        assert not out.value
+        assert lib.hfz_init(ctypes.byref(p), None, nb.value, None, ctypes.byref(out)) == -2
+        if model < 2:
+            arr = (hfz.Params * 3)(p, p, p)
+            assert lib.hfz_batch_workspace_bytes(arr, 3, ctypes.byref(nb)) == 0
+            assert lib.hfz_batch_init(arr, 3, fake, nb.value - 1, None, ctypes.byref(out)) == -2
+            assert not out.value
+    p = hfz.Params()
+    assert lib.hfz_default_params(0, ctypes.byref(p)) == 0
+    p.n, p.h = 16, 0.5
+    nb = ctypes.c_size_t(0)
+    assert lib.hfz3_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert lib.hfz3_init(ctypes.byref(p), fake, nb.value - 1, None, ctypes.byref(out)) == -2
+    assert not out.value

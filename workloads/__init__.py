@@ -105,6 +105,26 @@ def cdft_gauss_noise(n, h, s, seed, rho_bar=CDFT_RHO_BAR, amp=0.02, **kw):
     return Config("cdft", n, h, s, **kw), rho, z.copy(), z.copy()
 
 
+def cdft_vacuum_lattice(n, seed=0, h=0.53125, period=4.25, rho_min=1e-3, amp=2.0, speed=0.6, s=0.03, **kw):
+    """A CDFT state near vacuum between its peaks, for the positivity projection
+    of Sec. 6: a square lattice of peaks of the given period,
+    rho = rho_min + amp * b (1 + 0.05 U(-1, 1)), b = [(1 + cos kx)(1 + cos ky)/4]^2,
+    k = 2 pi / period, so rho falls to rho_min in the troughs, and a flow out of
+    the troughs, u = -speed sin(kx)(1 + 0.1 U(-1, 1)), v = -speed sin(ky)(...),
+    strong enough (with s = 0.03) that the continuity update of the first
+    V-cycle goes negative at some trough nodes.  n must be a multiple of
+    period / h (8 at the defaults)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x)
+    k = 2.0 * math.pi / period
+    bump = ((1.0 + np.cos(k * X)) * (1.0 + np.cos(k * Y)) / 4.0) ** 2
+    rho = rho_min + amp * bump * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, (n, n)))
+    u = -speed * np.sin(k * X) * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, (n, n)))
+    v = -speed * np.sin(k * Y) * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, (n, n)))
+    return Config("cdft", n, h, s, **kw), rho, u, v
+
+
 def gradflow(model, n, seed=0, precision="fp64", **kw):
     """Gradient-flow workload: "pfc_gf" draws rho as the PFC freezing run
     (rho_bar + 0.05 U(-1, 1), h = 0.25, s = 0.01), "cdft_gf" as the CDFT run
