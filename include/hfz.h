@@ -51,7 +51,8 @@
  *  - Device pointers are plain HIP device addresses on the device current
  *    when hfz_init ran.  The caller owns all device memory: the workspace
  *    (hfz_workspace_bytes) and the state buffers.  The library never
- *    allocates device memory.
+ *    allocates device memory (hfz_step_noalloc works in a static device
+ *    array of the library instead of a caller workspace).
  *  - All device work is enqueued on the stream given to hfz_init
  *    (a hipStream_t passed as void*, NULL for the default stream).  Entry
  *    points that return host values (hfz_step's convergence test, energy,
@@ -96,7 +97,8 @@ enum {
   HFZ_ENOCONV = -4,  /* max_cycles V-cycles without reaching tol; state not advanced */
   HFZ_ENAN = -5,     /* non-finite residual or energy; state not advanced */
   HFZ_EHIP = -6,     /* HIP runtime error */
-  HFZ_ESTATE = -7    /* call out of order (e.g. step before set_state) */
+  HFZ_ESTATE = -7,   /* call out of order (e.g. step before set_state) */
+  HFZ_ESCRATCH = -8  /* hfz_step_noalloc: the problem does not fit HFZ_NOALLOC_SCRATCH_BYTES */
 };
 
 /* Hydrodynamic PFC / CDFT step (Eqs. discrete_a-d), or the gradient-flow
@@ -118,9 +120,12 @@ typedef struct hfz_params {
   double delta;       /* CDFT (both schemes): rho <- sqrt(rho^2 + delta^2) after each rho update */
   double w_damp;      /* damping, x <- (1 - w) x_GS + w x_old, 0 <= w < 1 */
   double tol;         /* residual tolerance on ||S - N(g)||_2 (h^2-weighted) */
-  int nu1, nu2;       /* pre / post smoothing sweeps per level (>= 0, sum >= 1) */
+  int nu1, nu2;       /* pre / post smoothing sweeps per level (>= 0, sum >= 1; >= 1 each for
+                         mixed precision, the channel and the batch) */
   int max_cycles;     /* V-cycle cap per step (>= 1) */
-  int coarsest_n;     /* coarsest grid size, power of two, 4 <= coarsest_n <= n */
+  int coarsest_n;     /* coarsest grid size, power of two, 4 <= coarsest_n <= n (<= 32 for mixed
+                         precision, the channel and the batch: their coarsest level runs in the
+                         one-workgroup tail) */
   int coarse_sweeps;  /* sweeps on the coarsest grid per V-cycle (>= 1) */
   int precision;      /* HFZ_FP64, or HFZ_MIXED: FP32 smoothing inside FP64 defect correction
                          (three FP32 V-cycles per outer FP64 iteration) */
@@ -225,6 +230,34 @@ int hfz_tile_shape(hfz_handle* hd, int level, int* tx, int* ty, int* threads);
 
 int hfz_destroy(hfz_handle* hd);
 const char* hfz_strerror(int code);
+
+/* ---- the step without device allocation ---------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It does
+ * what hfz_init + hfz_set_state + hfz_step + hfz_get_state do, with the
+ * workspace in a static device array of the library (HFZ_NOALLOC_SCRATCH_BYTES,
+ * 72 MiB, reserved on every GPU the library runs on until the process ends)
+ * instead of a caller buffer; it calls no hipMalloc, hipFree or other
+ * allocating routine (host bookkeeping uses the C++ heap), uploads its level
+ * descriptors through kernel arguments, does not time kernel candidates (the
+ * tile shapes cached in this process by an earlier hfz_init, else the
+ * defaults) and launches no HIP graph; the results equal hfz_step's up to
+ * rounding.
+ *  p:     parameters as for hfz_init; HFZ_ESCRATCH if hfz_workspace_bytes(p)
+ *         exceeds HFZ_NOALLOC_SCRATCH_BYTES (it holds e.g. PFC FP64 512^2,
+ *         CDFT FP64 512^2, PFC mixed 256^2).
+ *  rho, u, v: caller device buffers of n*n doubles (a channel: (n + 1) * n),
+ *         the state before the call on entry and after it on return (u, v
+ *         may be NULL for the gradient flow).  On HFZ_ENOCONV / HFZ_ENAN they
+ *         hold the state after the last completed step.  The auxiliaries of
+ *         PFC (mu, kappa) start from the state, as after hfz_set_state.
+ *  nsteps, stats: as for hfz_step.  hip_stream: as for hfz_init.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * there; the call initialises everything it reads.  Calls that overlap on one
+ * GPU (other host threads or streams) race on the array: serialise them. */
+#define HFZ_NOALLOC_SCRATCH_BYTES ((size_t)72 << 20)
+int hfz_step_noalloc(const hfz_params* p, double* rho, double* u, double* v, int nsteps, void* hip_stream,
+                     hfz_stats* stats);
 
 /* ---- batched solve ------------------------------------------------------
  * `count` independent instances advance together: each V-cycle phase of all

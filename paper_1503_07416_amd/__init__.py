@@ -5,4 +5,4 @@ The numerical work runs in ``libhfz.so`` (HIP kernels behind the C ABI of
 include/hfz.h); :mod:`.hfz` is its ctypes binding.
 """
 from .hfz import (CDFT, CDFT_GF, FP64, MIXED, PFC, PFC_GF, Batch, HfzError, Simulation,  # noqa: F401
-                  Simulation3, load, make_params, workspace_bytes)
+                  Simulation3, load, make_params, step_noalloc, workspace_bytes)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -698,6 +699,113 @@ double* field_ptr(hfz_handle* hd, int which, int level, int comp) {
   }
 }
 
+// Uploads count values from host to device memory on `stream`: with
+// by_kernel one small kernel per value carries it in its arguments (no
+// host-to-device copy), else one hipMemcpyAsync.
+template <typename T> bool upload(T* dst, const T* src, size_t count, hipStream_t stream, bool by_kernel) {
+  if (!by_kernel)
+    return hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, stream) == hipSuccess;
+  for (size_t k = 0; k < count; ++k) k_put<T><<<1, 64, 0, stream>>>(dst + k, src[k]);
+  return hipGetLastError() == hipSuccess;
+}
+
+// Sets up a handle over the workspace dev_ws (validated and large enough):
+// layout, level descriptors on the device, physics, kernel choices, the CDFT
+// kernel table.  by_kernel (hfz_step_noalloc): uploads by kernel arguments,
+// no timing of kernel candidates (the choices cached in this process, else
+// the defaults) and no HIP graphs.
+int init_handle(hfz_handle* hd, const hfz_params& p, void* dev_ws, void* hip_stream, bool by_kernel) {
+  hd->p = p;
+  hd->km = kernel_model(p);
+  hd->stream = static_cast<hipStream_t>(hip_stream);
+  layout(p, dev_ws, hd);
+  bool ok = upload(hd->H.desc, hd->H.L.data(), hd->H.L.size(), hd->stream, by_kernel);
+  if (ok && p.precision == HFZ_MIXED) ok = upload(hd->H32.desc, hd->H32.L.data(), hd->H32.L.size(), hd->stream, by_kernel);
+  if (!ok || hipStreamSynchronize(hd->stream) != hipSuccess) return HFZ_EHIP;
+  hd->H.P.s = p.s;
+  hd->H.P.gamma = p.gamma;
+  hd->H.P.sigma = (double)p.sigma;
+  hd->H.P.alpha = p.alpha;
+  hd->H.P.delta = p.delta;
+  hd->H.P.w = p.w_damp;
+  hd->H.P.ce = 0.0;
+  hd->H.P.ub = p.u_wall_bottom;
+  hd->H.P.ut = p.u_wall_top;
+  hd->H32.P.s = (float)p.s;
+  hd->H32.P.gamma = (float)p.gamma;
+  hd->H32.P.sigma = (float)p.sigma;
+  hd->H32.P.alpha = (float)p.alpha;
+  hd->H32.P.delta = (float)p.delta;
+  hd->H32.P.w = (float)p.w_damp;
+  hd->H32.P.ce = 0.0f;
+  hd->H32.P.ub = (float)p.u_wall_bottom;
+  hd->H32.P.ut = (float)p.u_wall_top;
+  hd->H.P.halt = hd->ctl;
+  hd->H32.P.halt = hd->ctl;
+  k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
+  // opt in to the large LDS of a gfx950 CU for the tail kernels
+  by_model(hd->km, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, double, false>));
+    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, float, true>));
+  });
+  if (const char* e = std::getenv("HFZ_TAIL_N")) {
+    const int t = std::atoi(e);
+    if (t == 0 || is_pow2(t)) hd->tail_n = t;
+  }
+  if (const char* e = std::getenv("HFZ_GRAPH")) hd->use_graph = std::atoi(e) != 0;
+  if (const char* e = std::getenv("HFZ_TILES")) hd->use_tiles = std::atoi(e) != 0;
+  if (p.precision == HFZ_MIXED || p.walls) {
+    // the correction-form inner solve, and a channel, run only on the tiled
+    // and tail kernels: every level above the tail must be tileable (>= 32
+    // with a >= 16 coarse), and the coarsest level (<= 32, validate()) must
+    // be a tail level
+    hd->use_tiles = true;
+    if (hd->tail_n < 16) hd->tail_n = kTailNMax;
+    hd->tail_n = std::max(hd->tail_n, p.coarsest_n);
+    const bool held = by_model(hd->km, [&](auto m) {
+      constexpr int M = decltype(m)::value;
+      return p.precision == HFZ_MIXED ? tail_holds_bottom<M, float, true>(hd->H32.L, hd->tail_n, hd->H32.tail_lds_max)
+                                       : tail_holds_bottom<M, double, false>(hd->H.L, hd->tail_n, hd->H.tail_lds_max);
+    });
+    if (!held) return HFZ_EINVAL;
+  }
+  if (by_kernel) hd->use_graph = false;
+  if (hd->use_tiles) {
+    const Cycle K = cycle_ctx(hd);
+    by_model(hd->km, [&](auto m) {
+      constexpr int M = decltype(m)::value;
+      tune_tile_shapes<M, double, false>(hd->H, K, !by_kernel);
+      if (p.precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K, !by_kernel);
+    });
+  }
+  if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));
+  if (std::getenv("HFZ_VERBOSE")) {
+    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p.n, hd->nlev,
+                 hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
+    for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
+    std::fprintf(stderr, " restriction:");
+    for (size_t l = 0; l < hd->H.restrict_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.restrict_shape[l]);
+    std::fprintf(stderr, " sweeps/launch:");
+    for (size_t l = 0; l < hd->H.sweep_fuse.size(); ++l) std::fprintf(stderr, " %d", hd->H.sweep_fuse[l]);
+    for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
+    std::fprintf(stderr, "\n");
+  }
+  if (model_cdft(p.model)) {
+    const int rc = cdft_setup(hd);
+    if (rc != HFZ_OK) return rc;
+  }
+  {
+    const StateB sb{hd->u, hd->v, hd->mu, hd->ka, hd->jrho};
+    const int one = 1;
+    const bool up = upload(hd->state1, &sb, 1, hd->stream, by_kernel) &&
+                    upload(hd->phys1, &hd->H.P, 1, hd->stream, by_kernel) &&
+                    upload(hd->on1, &one, 1, hd->stream, by_kernel) && hipStreamSynchronize(hd->stream) == hipSuccess;
+    if (!up) return HFZ_EHIP;
+  }
+  return HFZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -744,109 +852,10 @@ int hfz_init(const hfz_params* p, void* dev_ws, size_t ws_bytes, void* hip_strea
   if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return HFZ_EINVAL;
   hfz_handle* hd = new (std::nothrow) hfz_handle();
   if (!hd) return HFZ_ENOMEM;
-  hd->p = *p;
-  hd->km = kernel_model(*p);
-  hd->stream = static_cast<hipStream_t>(hip_stream);
-  layout(*p, dev_ws, hd);
-  bool ok = hipMemcpyAsync(hd->H.desc, hd->H.L.data(), hd->H.L.size() * sizeof(Lvl<double>),
-                           hipMemcpyHostToDevice, hd->stream) == hipSuccess;
-  if (ok && p->precision == HFZ_MIXED)
-    ok = hipMemcpyAsync(hd->H32.desc, hd->H32.L.data(), hd->H32.L.size() * sizeof(Lvl<float>),
-                        hipMemcpyHostToDevice, hd->stream) == hipSuccess;
-  if (!ok || hipStreamSynchronize(hd->stream) != hipSuccess) {
+  rc = init_handle(hd, *p, dev_ws, hip_stream, false);
+  if (rc != HFZ_OK) {
     delete hd;
-    return HFZ_EHIP;
-  }
-  hd->H.P.s = p->s;
-  hd->H.P.gamma = p->gamma;
-  hd->H.P.sigma = (double)p->sigma;
-  hd->H.P.alpha = p->alpha;
-  hd->H.P.delta = p->delta;
-  hd->H.P.w = p->w_damp;
-  hd->H.P.ce = 0.0;
-  hd->H.P.ub = p->u_wall_bottom;
-  hd->H.P.ut = p->u_wall_top;
-  hd->H32.P.s = (float)p->s;
-  hd->H32.P.gamma = (float)p->gamma;
-  hd->H32.P.sigma = (float)p->sigma;
-  hd->H32.P.alpha = (float)p->alpha;
-  hd->H32.P.delta = (float)p->delta;
-  hd->H32.P.w = (float)p->w_damp;
-  hd->H32.P.ce = 0.0f;
-  hd->H32.P.ub = (float)p->u_wall_bottom;
-  hd->H32.P.ut = (float)p->u_wall_top;
-  hd->H.P.halt = hd->ctl;
-  hd->H32.P.halt = hd->ctl;
-  k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
-  // opt in to the large LDS of a gfx950 CU for the tail kernels
-  by_model(hd->km, [&](auto m) {
-    constexpr int M = decltype(m)::value;
-    hd->H.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, double, false>));
-    hd->H32.tail_lds_max = lds_optin(reinterpret_cast<const void*>(&k_tail<M, float, true>));
-  });
-  if (const char* e = std::getenv("HFZ_TAIL_N")) {
-    const int t = std::atoi(e);
-    if (t == 0 || is_pow2(t)) hd->tail_n = t;
-  }
-  if (const char* e = std::getenv("HFZ_GRAPH")) hd->use_graph = std::atoi(e) != 0;
-  if (const char* e = std::getenv("HFZ_TILES")) hd->use_tiles = std::atoi(e) != 0;
-  if (p->precision == HFZ_MIXED || p->walls) {
-    // the correction-form inner solve, and a channel, run only on the tiled
-    // and tail kernels: every level above the tail must be tileable (>= 32
-    // with a >= 16 coarse), and the coarsest level (<= 32, validate()) must
-    // be a tail level
-    hd->use_tiles = true;
-    if (hd->tail_n < 16) hd->tail_n = kTailNMax;
-    hd->tail_n = std::max(hd->tail_n, p->coarsest_n);
-    const bool held = by_model(hd->km, [&](auto m) {
-      constexpr int M = decltype(m)::value;
-      return p->precision == HFZ_MIXED ? tail_holds_bottom<M, float, true>(hd->H32.L, hd->tail_n, hd->H32.tail_lds_max)
-                                       : tail_holds_bottom<M, double, false>(hd->H.L, hd->tail_n, hd->H.tail_lds_max);
-    });
-    if (!held) {
-      delete hd;
-      return HFZ_EINVAL;
-    }
-  }
-  if (hd->use_tiles) {
-    const Cycle K = cycle_ctx(hd);
-    by_model(hd->km, [&](auto m) {
-      constexpr int M = decltype(m)::value;
-      tune_tile_shapes<M, double, false>(hd->H, K);
-      if (p->precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K);
-    });
-  }
-  if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));
-  if (std::getenv("HFZ_VERBOSE")) {
-    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p->n, hd->nlev,
-                 hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
-    for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
-    std::fprintf(stderr, " restriction:");
-    for (size_t l = 0; l < hd->H.restrict_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.restrict_shape[l]);
-    std::fprintf(stderr, " sweeps/launch:");
-    for (size_t l = 0; l < hd->H.sweep_fuse.size(); ++l) std::fprintf(stderr, " %d", hd->H.sweep_fuse[l]);
-    for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
-    std::fprintf(stderr, "\n");
-  }
-  if (model_cdft(p->model)) {
-    rc = cdft_setup(hd);
-    if (rc != HFZ_OK) {
-      delete hd;
-      return rc;
-    }
-  }
-  {
-    const StateB sb{hd->u, hd->v, hd->mu, hd->ka, hd->jrho};
-    const int one = 1;
-    const bool up = hipMemcpyAsync(hd->state1, &sb, sizeof(sb), hipMemcpyHostToDevice, hd->stream) == hipSuccess &&
-                    hipMemcpyAsync(hd->phys1, &hd->H.P, sizeof(Phys<double>), hipMemcpyHostToDevice, hd->stream) ==
-                        hipSuccess &&
-                    hipMemcpyAsync(hd->on1, &one, sizeof(int), hipMemcpyHostToDevice, hd->stream) == hipSuccess &&
-                    hipStreamSynchronize(hd->stream) == hipSuccess;
-    if (!up) {
-      delete hd;
-      return HFZ_EHIP;
-    }
+    return rc;
   }
   *out = hd;
   return HFZ_OK;
@@ -871,8 +880,8 @@ int hfz_set_state(hfz_handle* hd, const double* rho, const double* u, const doub
   copy_dev(hd, rho, L0.rk, N2);
   if (gf) {
     // the gradient flow has no velocity: u = v = 0 (KE = 0 in the energy)
-    HIPCHK(hipMemsetAsync(hd->u, 0, N2 * sizeof(double), hd->stream));
-    HIPCHK(hipMemsetAsync(hd->v, 0, N2 * sizeof(double), hd->stream));
+    k_fill<<<(unsigned)((N2 + 255) / 256), 256, 0, hd->stream>>>(hd->u, 0.0, N2);
+    k_fill<<<(unsigned)((N2 + 255) / 256), 256, 0, hd->stream>>>(hd->v, 0.0, N2);
   } else {
     copy_dev(hd, u, hd->u, N2);
     copy_dev(hd, v, hd->v, N2);
@@ -1079,12 +1088,69 @@ const char* hfz_strerror(int code) {
       return "HIP runtime error";
     case HFZ_ESTATE:
       return "no state loaded";
+    case HFZ_ESCRATCH:
+      return "problem needs more device memory than the static scratch of hfz_step_noalloc holds";
     default:
       return "unknown error";
   }
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// The step without device allocation (hfz_step_noalloc): the handle's
+// workspace is the file-scope device array `scratch`, of which every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes `scratch` itself to a kernel or a copy (in host code the name is a
+// host-side stand-in, not the device address): the address of each device's
+// copy is queried once per device with hipGetSymbolAddress, with that device
+// current, and kept in scratch_addr.
+// ===========================================================================
+
+static __device__ __align__(256) unsigned char scratch[HFZ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (nullptr on a HIP error).
+void* scratch_addr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[dev] = ptr;
+  }
+  return g_scratch_addr[dev];
+}
+
+}  // namespace
+
+extern "C" int hfz_step_noalloc(const hfz_params* p, double* rho, double* u, double* v, int nsteps,
+                                void* hip_stream, hfz_stats* stats) {
+  if (stats) *stats = hfz_stats{};
+  int rc = validate(p);
+  if (rc != HFZ_OK) return rc;
+  if (!rho || nsteps < 0 || (!model_gf(p->model) && (!u || !v))) return HFZ_EINVAL;
+  if (layout(*p, nullptr, nullptr) > HFZ_NOALLOC_SCRATCH_BYTES) return HFZ_ESCRATCH;
+  void* ws = scratch_addr();
+  if (!ws) return HFZ_EHIP;
+  hfz_handle hd;
+  rc = init_handle(&hd, *p, ws, hip_stream, true);
+  if (rc == HFZ_OK) rc = hfz_set_state(&hd, rho, u, v);
+  if (rc != HFZ_OK) return rc;
+  rc = hfz_step(&hd, nsteps, stats);
+  // the state after the last completed step (a failing step is rolled back)
+  const int rc_get = hfz_get_state(&hd, rho, model_gf(p->model) ? nullptr : u, model_gf(p->model) ? nullptr : v);
+  return rc != HFZ_OK ? rc : rc_get;
+}
 
 // ===========================================================================
 // Batched solve: many independent instances of one model, grid size and

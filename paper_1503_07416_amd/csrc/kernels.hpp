@@ -324,6 +324,19 @@ __global__ void k_ctl_reset(int* ctl) {
   if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
 
+// Stores one value of a trivially copyable type (a level descriptor, the
+// physics block) into device memory: an upload from the host through the
+// kernel's arguments, with no host-to-device copy.
+template <typename T> __global__ void k_put(T* dst, T val) {
+  if (threadIdx.x == 0) *dst = val;
+}
+
+// dst[0..count) = x.
+__global__ void k_fill(double* __restrict__ dst, double x, size_t count) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) dst[t] = x;
+}
+
 // --------------------------------------------------------- post-step -----
 // K10: rho^{k+1} = S1 - s/(4h)[(rho^k u)_E - (rho^k u)_W + (rho^k v)_N - (rho^k v)_S]
 // with the converged velocity (Eq. discrete_a), written into dst.

@@ -143,8 +143,10 @@ template <typename F> int pick_fastest(int count, F&& time, const char* what = n
 
 // Fills H.tile_shape and H.restrict_shape for the levels the tiled V-cycle
 // visits (size >= 32 with a coarser level of >= 16, above the tail).
-// HFZ_RESTRICT=<variant> forces a restriction variant where it fits.
-template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cycle K) {
+// HFZ_RESTRICT=<variant> forces a restriction variant where it fits.  With
+// time_them false nothing is launched: a level takes the choices cached for
+// its size in this process, else shape 0, variant 0 and fused sweeps.
+template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cycle K, bool time_them = true) {
   const int nlev = (int)H.L.size();
   H.tile_shape.assign(nlev, 0);
   H.restrict_shape.assign(nlev, 0);
@@ -175,6 +177,7 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
         continue;
       }
     }
+    if (!time_them) continue;
     const int ts = pick_fastest(NUM_TILE_SHAPES, [&](int k) {
       return tile_shape_fits(k, n) ? time_shape<MODEL, T, CORR>(H, K, l, k, 8) : -1.0f;
     }, "tile shape", n);

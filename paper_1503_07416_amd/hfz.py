@@ -16,10 +16,10 @@ LIB_PATH = os.path.join(HERE, "libhfz.so")
 PFC, CDFT, PFC_GF, CDFT_GF = 0, 1, 2, 3
 MODELS = {"pfc": PFC, "cdft": CDFT, "pfc_gf": PFC_GF, "cdft_gf": CDFT_GF}
 FP64, MIXED = 0, 1
-OK, EINVAL, ENOMEM, EDOMAIN, ENOCONV, ENAN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EDOMAIN, ENOCONV, ENAN, EHIP, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
 ERRORS = {0: "HFZ_OK", -1: "HFZ_EINVAL", -2: "HFZ_ENOMEM", -3: "HFZ_EDOMAIN",
-          -4: "HFZ_ENOCONV", -5: "HFZ_ENAN", -6: "HFZ_EHIP", -7: "HFZ_ESTATE"}
+          -4: "HFZ_ENOCONV", -5: "HFZ_ENAN", -6: "HFZ_EHIP", -7: "HFZ_ESTATE", -8: "HFZ_ESCRATCH"}
 
 # names exported by the library (include/hfz.h)
 SYMBOLS = [
@@ -27,6 +27,7 @@ SYMBOLS = [
     "hfz_get_state", "hfz_get_aux", "hfz_step", "hfz_energy", "hfz_mass",
     "hfz_begin_step", "hfz_smooth", "hfz_vcycle", "hfz_residual", "hfz_finish_step",
     "hfz_read_field", "hfz_write_field", "hfz_info", "hfz_tile_shape", "hfz_destroy", "hfz_strerror",
+    "hfz_step_noalloc",
     "hfz_batch_workspace_bytes", "hfz_batch_init", "hfz_batch_set_state", "hfz_batch_get_state",
     "hfz_batch_energy", "hfz_batch_release", "hfz_batch_step", "hfz_batch_destroy",
     "hfz3_workspace_bytes", "hfz3_init", "hfz3_set_state", "hfz3_get_state", "hfz3_step", "hfz3_energy",
@@ -93,6 +94,7 @@ def load():
         "hfz_tile_shape": [vp, i, P(i), P(i), P(i)],
         "hfz_destroy": [vp],
         "hfz_strerror": [i],
+        "hfz_step_noalloc": [P(Params), vp, vp, vp, i, vp, P(Stats)],
         "hfz_batch_workspace_bytes": [P(Params), i, P(ctypes.c_size_t)],
         "hfz_batch_init": [P(Params), i, vp, ctypes.c_size_t, vp, P(vp)],
         "hfz_batch_set_state": [vp, i, vp, vp, vp],
@@ -172,6 +174,27 @@ def workspace_bytes(p):
 
 def _ptr(t):
     return ctypes.c_void_p(None if t is None else t.data_ptr())
+
+
+def step_noalloc(cfg, rho, u=None, v=None, nsteps=1, stream=None, raise_on_error=True):
+    """hfz_step_noalloc: advances the state held in the float64 device tensors
+    rho, u, v (contiguous, n x n; updated in place) by nsteps steps, with the
+    library's static device scratch as workspace (no device allocation).
+    Returns the step statistics, or (rc, stats) with raise_on_error=False."""
+    lib = load()
+    p = make_params(cfg)
+    for t in (rho, u, v):
+        if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("state tensors must be contiguous float64 device tensors")
+    s = stream if stream is not None else torch.cuda.current_stream(rho.device)
+    torch.cuda.current_stream(rho.device).synchronize()
+    st = Stats()
+    rc = lib.hfz_step_noalloc(ctypes.byref(p), _ptr(rho), _ptr(u), _ptr(v), int(nsteps),
+                              ctypes.c_void_p(s.cuda_stream), ctypes.byref(st))
+    if raise_on_error:
+        check(rc, "hfz_step_noalloc")
+        return st
+    return rc, st
 
 
 class Simulation:
