@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="headline and roofline only")
     ap.add_argument("--cpu-cycles", type=int, default=10, help="V-cycles of the oracle sample")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="processes of the parallel oracle sample (0: min(16, host CPUs))")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
@@ -211,11 +213,13 @@ def counter_probe_3d(n=128):
                       "source_hash_3d": source_hash(KERNEL_SOURCES_3D)}))
 
 
-def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
-    """The oracle (NumPy FP64, one thread) on a bounded sample: `vcycles`
-    V-cycles of the first step of the same workload; steps/s extrapolated with
-    the GPU's mean V-cycles per step."""
+def oracle_sample(n, vcycles):
+    """The oracle (NumPy FP64, one thread) on the headline workload: seconds to
+    set up step 1 (source, hierarchy) and seconds per V-cycle over `vcycles`
+    V-cycles of it."""
+    import workloads
     from oracle.fas import Stepper
+    cfg, rho, u, v = workloads.config2(0, n=n)
     st = Stepper(cfg.model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
     st.set_state(rho, u, v)
     t0 = time.perf_counter()
@@ -226,11 +230,52 @@ def cpu_baseline(cfg, rho, u, v, cycles_per_step, vcycles):
     for _ in range(vcycles):
         sol.vcycle(g, S)
     t2 = time.perf_counter()
-    per_cycle = (t2 - t1) / vcycles
-    per_step = (t1 - t0) + per_cycle * cycles_per_step
+    return t1 - t0, (t2 - t1) / vcycles
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sample(n, vcycles, processes):
+    """Times the oracle sample in this process (one thread), then in
+    `processes` child processes at once (each an independent copy, one thread
+    each).  Runs before the GPU is used, so the host cores are otherwise idle."""
+    import subprocess
+    setup, per_cycle = oracle_sample(n, vcycles)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = ("import json, bench; s, c = bench.oracle_sample(%d, %d); print(json.dumps([s, c]))" % (n, vcycles))
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", code], cwd=ROOT, env=env, stdout=subprocess.PIPE,
+                              stderr=subprocess.DEVNULL, text=True) for _ in range(processes)]
+    outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+    wall = time.perf_counter() - t0
+    return {"setup_s": setup, "per_cycle_s": per_cycle, "processes": processes, "parallel_wall_s": wall,
+            "parallel_per_cycle_s": [o[1] for o in outs], "parallel_setup_s": [o[0] for o in outs]}
+
+
+def cpu_baseline(sample, n, cycles_per_step, vcycles):
+    """steps/s of the oracle from the sample, extrapolated with the GPU's mean
+    V-cycles per step: one process (one thread), and the aggregate of
+    `processes` independent copies running at once."""
+    per_step = sample["setup_s"] + sample["per_cycle_s"] * cycles_per_step
+    par = [s + c * cycles_per_step for s, c in zip(sample["parallel_setup_s"], sample["parallel_per_cycle_s"])]
     return {"value": round(1.0 / per_step, 6), "unit": "time steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{vcycles} V-cycles of step 1 of the {cfg.n}^2 workload "
-                      f"({t2 - t0:.1f} s), scaled by {cycles_per_step:.2f} V-cycles/step"}
+            "sample": f"{vcycles} V-cycles of step 1 of the {n}^2 workload "
+                      f"({sample['setup_s'] + vcycles * sample['per_cycle_s']:.1f} s, one thread), "
+                      f"scaled by {cycles_per_step:.2f} V-cycles/step",
+            "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "parallel": {"processes": sample["processes"], "threads_each": 1,
+                         "value": round(sum(1.0 / t for t in par), 6), "unit": "time steps/s (aggregate)",
+                         "note": f"{sample['processes']} independent copies of the sample at once "
+                                 f"({sample['parallel_wall_s']:.1f} s wall); the oracle itself is single-threaded"}}
 
 
 def rel_diff(a, b):
@@ -247,7 +292,7 @@ def run_mixed(a, ref_state):
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
-    cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0, precision="mixed")
+    cfg, rho, u, v = workloads.config2(0, precision="mixed", n=a.n)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E = [sim.energy()[0]]
@@ -372,9 +417,11 @@ def run_serving(requests, budget_gib):
         for n in sizes:
             if model == "pfc":
                 cfg, r, u, v = workloads.pfc_uniform_noise(n, workloads.NANO_H, 0.02, 77, rho_bar=0.8,
-                                                           alpha=1 - workloads.NANO_EPS, precision="mixed")
+                                                           alpha=1 - workloads.NANO_EPS, precision="mixed",
+                                                           coarsest_n=workloads.BENCH_COARSEST_N)
             else:
-                cfg, r, u, v = workloads.cdft_gauss_noise(n, 17 / 128, 0.02, 77)
+                cfg, r, u, v = workloads.cdft_gauss_noise(n, 17 / 128, 0.02, 77,
+                                                          coarsest_n=workloads.BENCH_COARSEST_N)
             sim = pkg.Simulation(cfg, device="cuda:0")
             sim.set_state(r, u, v)
             sim.step(1)
@@ -442,7 +489,7 @@ def run_gradflow(steps=50, check_steps=10):
     for model, n, kname in [("pfc_gf", 512, "GPFC"), ("cdft_gf", 1024, "GCDFT")]:
         res = {}
         for prec in ("fp64", "mixed"):
-            cfg, rho, _, _ = workloads.gradflow(model, n, 0, precision=prec)
+            cfg, rho, _, _ = workloads.gradflow(model, n, 0, precision=prec, coarsest_n=workloads.BENCH_COARSEST_N)
             sim = pkg.Simulation(cfg, device="cuda:0")
             sim.set_state(rho)
             sim.step(2)
@@ -488,7 +535,7 @@ def run_channel(steps=50, check_steps=10, n=256):
     out = {"workload": f"PFC eps=0.4 channel {n}x{n + 1} nodes, h=pi/(2 sqrt3), s=0.02, 13-atom hexagonal "
                        f"nucleate, FAS V(2,2) tol 1e-10 FP64, {steps} timed steps (+{check_steps} checked)"}
     for uw in (0.0, 0.1, 0.5):
-        cfg, rho, u, v = workloads.channel(n, u_wall=uw)
+        cfg, rho, u, v = workloads.channel(n, u_wall=uw, coarsest_n=workloads.BENCH_COARSEST_N)
         sim = pkg.Simulation(cfg, device="cuda:0")
         sim.set_state(rho, u, v)
         sim.step(2)
@@ -708,17 +755,21 @@ def main():
         import torch
         import workloads
         import paper_1503_07416_amd as pkg
-        cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0)
+        cfg, rho, u, v = workloads.config2(0, n=a.n)
         sim = pkg.Simulation(cfg, device="cuda:0")
         sim.set_state(rho, u, v)
         sim.step(a.warmup + a.steps)
         print(json.dumps({"mixed": run_mixed(a, sim.get_state())}))
         return
+    sample = None
+    if not a.no_cpu:
+        procs = a.cpu_procs if a.cpu_procs > 0 else max(1, min(16, os.cpu_count() or 1))
+        sample = cpu_sample(a.n, a.cpu_cycles, procs)
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
 
-    cfg, rho, u, v = workloads.pfc_uniform_noise(a.n, 0.25, 0.01, 0)
+    cfg, rho, u, v = workloads.config2(0, n=a.n)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E0 = sim.energy()[0]
@@ -740,13 +791,16 @@ def main():
         "value": round(a.steps / dt, 3), "unit": "time steps/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(1e3 * dt / a.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"PFC {a.n}^2 h=0.25 s=0.01 eps=0.025 FAS V(2,2) tol 1e-10 FP64",
-                   "n": a.n, "vcycles_per_step": round(cps, 3), "final_residual": st.residual_last,
+        "config": {"workload": f"PFC {a.n}^2 h=0.25 s=0.01 eps=0.025 FAS V(2,2) to a {cfg.coarsest_n}^2 coarsest "
+                               f"grid, tol 1e-10, FP64",
+                   "n": a.n, "vcycles_per_step": round(cps, 3),
+                   "us_per_vcycle": round(1e6 * dt / max(1, st.cycles_total), 2),
+                   "final_residual": st.residual_last,
                    "energy_decreased": bool(E1 <= E0), "mass": mass},
         "roofline": roof,
     }
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, rho, u, v, cps, a.cpu_cycles)
+    if sample is not None:
+        out["cpu_baseline"] = cpu_baseline(sample, a.n, cps, a.cpu_cycles)
     if not a.no_extras:
         sim.close()
         out["mixed"] = run_mixed(a, state)

@@ -31,6 +31,12 @@ NANO_EPS = 0.4
 NANO_RHO_L = 0.72958
 NANO_RHO_S = 0.90073
 NANO_H = math.pi / (2.0 * math.sqrt(3.0))
+# Coarsest grid of the benchmark workloads (FAS V(2,2) from n^2 down to 32^2,
+# the largest level the one-workgroup tail holds).  On these workloads the
+# levels below 32^2 do not change the V-cycles per step (measured with the
+# oracle at 128^2 and 256^2: PFC eps = 0.025 and 0.4, CDFT, the gradient flows
+# and the channel take the same cycle counts with coarsest 4^2 to 64^2).
+BENCH_COARSEST_N = 32
 
 
 @dataclass
@@ -202,14 +208,16 @@ def config1(seed=0):
     return pfc_uniform_noise(32, 0.25, 0.01, seed)
 
 
-def config2(seed=0, precision="fp64"):
-    """PFC, 512^2, h = 0.25, s = 0.01, 100 steps; FP64 or mixed precision."""
-    return pfc_uniform_noise(512, 0.25, 0.01, seed, precision=precision)
+def config2(seed=0, precision="fp64", n=512):
+    """PFC, 512^2, h = 0.25, s = 0.01, 100 steps; FP64 or mixed precision;
+    V(2,2) down to a 32^2 coarsest grid."""
+    return pfc_uniform_noise(n, 0.25, 0.01, seed, precision=precision, coarsest_n=BENCH_COARSEST_N)
 
 
 def config3(seed=0, n=1024):
-    """CDFT, 1024^2, h = 17/128, s = 0.02, rho_bar + 0.02 N(0,1), 50 steps."""
-    return cdft_gauss_noise(n, 17.0 / 128.0, 0.02, seed)
+    """CDFT, 1024^2, h = 17/128, s = 0.02, rho_bar + 0.02 N(0,1), 50 steps;
+    V(2,2) down to a 32^2 coarsest grid."""
+    return cdft_gauss_noise(n, 17.0 / 128.0, 0.02, seed, coarsest_n=BENCH_COARSEST_N)
 
 
 def config4(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
@@ -223,7 +231,8 @@ def config4(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
     for i, (n, rb) in enumerate(zip(ns, rbs)):
         cfg, rho, u, v = pfc_uniform_noise(int(n), NANO_H, 0.02, 1000 + i,
                                            rho_bar=float(rb), alpha=1.0 - NANO_EPS,
-                                           precision=precision)
+                                           precision=precision,
+                                           coarsest_n=min(BENCH_COARSEST_N, int(n) // 2))
         out.append((cfg, rho, u, v))
     return out
 
@@ -256,10 +265,12 @@ def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
         if rng.uniform() < 0.5:
             rb = float(rng.uniform(NANO_RHO_L, NANO_RHO_S))
             cfg, rho, u, v = pfc_uniform_noise(n, NANO_H, 0.02, 5000 + i, rho_bar=rb,
-                                               alpha=1.0 - NANO_EPS, precision=pfc_precision)
+                                               alpha=1.0 - NANO_EPS, precision=pfc_precision,
+                                               coarsest_n=min(BENCH_COARSEST_N, n // 2))
         else:
             cfg, rho, u, v = cdft_gauss_noise(n, 17.0 / 128.0, 0.02, 5000 + i,
-                                              precision=cdft_precision)
+                                              precision=cdft_precision,
+                                              coarsest_n=min(BENCH_COARSEST_N, n // 2))
         reqs.append(Request(i, t, nst, cfg, rho, u, v))
     return reqs
 
