@@ -15,8 +15,8 @@ Also reported on the same JSON line:
   mixed         the same workload with FP32 smoothing inside FP64 defect
                 correction: steps/s and its distance from the FP64 result;
   batched       256 PFC instances (eps = 0.4, n ~ U{64,128,256}, 20 steps,
-                mixed precision): instance-steps/s against the unbatched FP64
-                path, and the per-step energy check;
+                mixed precision) in one batch: instance-steps/s against the
+                unbatched FP64 path, and the per-step energy check;
   serving       a Poisson stream of PFC and CDFT requests (n ~ U{64..1024},
                 10-200 steps) through the continuous-batching server under a
                 device-memory budget: p50/p99 per-step latency, throughput;
@@ -43,7 +43,6 @@ import json
 import os
 import re
 import sys
-import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -311,56 +310,31 @@ def run_mixed(a, ref_state):
 
 
 def run_batched(steps=20, count=256):
-    """Config 4: one batch per grid size on its own stream, stepped
-    concurrently; then the same instances one at a time through the unbatched
-    FP64 path (a sample of 16), and an untimed rerun of the batches one step at
-    a time reading every instance's energy after each step."""
+    """Config 4: all instances (grid sizes mixed) in one batch, one launch per
+    level depth and phase; then the same instances one at a time through the
+    unbatched FP64 path (a sample of 16), and an untimed rerun one step at a
+    time reading every instance's energy after each step."""
     import numpy as np
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
     inst = workloads.config4(count)
-    groups = {}
-    for c, r, u, v in inst:
-        groups.setdefault(c.n, []).append((c, r, u, v))
+    B = pkg.Batch([c for c, _, _, _ in inst], device="cuda:0")
 
-    def make():
-        out = []
-        for n in sorted(groups):
-            s = torch.cuda.Stream()
-            with torch.cuda.stream(s):
-                out.append((pkg.Batch([c for c, _, _, _ in groups[n]], stream=s), s, n))
-        return out
-
-    def load(batches):
-        for B, s, n in batches:
-            with torch.cuda.stream(s):
-                for k, (c, r, u, v) in enumerate(groups[n]):
-                    B.set_state(k, r, u, v)
+    def load():
+        for k, (c, r, u, v) in enumerate(inst):
+            B.set_state(k, r, u, v)
         torch.cuda.synchronize()
 
-    batches = make()
-    load(batches)
-    for B, s, _ in batches:          # warm-up step (captures each batch's V-cycle graph)
-        with torch.cuda.stream(s):
-            B.step(1)
-    load(batches)
-    res = {}
-
-    def run(k, nsteps):
-        B, s, _ = batches[k]
-        with torch.cuda.stream(s):
-            res[k] = B.step(nsteps)
-
+    load()
+    B.step(1)          # warm-up step (captures the batch's V-cycle graph)
+    load()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    th = [threading.Thread(target=run, args=(k, steps)) for k in range(len(batches))]
-    for x in th:
-        x.start()
-    for x in th:
-        x.join()
+    res = B.step(steps)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    cycles = np.mean([s.cycles_total / steps for k in res for s in res[k]])
+    cycles = np.mean([s.cycles_total / steps for s in res])
     # unbatched FP64 path on a sample
     sub = inst[::count // 16]
     tu = 0.0
@@ -377,21 +351,20 @@ def run_batched(steps=20, count=256):
         sim.close()
     unb = len(sub) * steps / tu
     # energy check, untimed: the same instances again, one step at a time
-    load(batches)
+    load()
     viol = 0
-    for B, s, _ in batches:
-        with torch.cuda.stream(s):
-            E = [B.energy(i)[0] for i in range(B.count)]
-            for _ in range(steps):
-                B.step(1)
-                for i in range(B.count):
-                    e = B.energy(i)[0]
-                    if e > E[i] + 1e-10 * max(1.0, abs(E[i])):
-                        viol += 1
-                    E[i] = e
-    for B, _, _ in batches:
-        B.close()
-    return {"workload": f"{count} PFC instances, eps=0.4, h=pi/(2 sqrt 3), s=0.02, n~U{{64,128,256}}, "
+    E = [B.energy(i)[0] for i in range(B.count)]
+    for _ in range(steps):
+        B.step(1)
+        for i in range(B.count):
+            e = B.energy(i)[0]
+            if e > E[i] + 1e-10 * max(1.0, abs(E[i])):
+                viol += 1
+            E[i] = e
+    B.close()
+    sizes = {n: sum(1 for c, _, _, _ in inst if c.n == n) for n in sorted({c.n for c, _, _, _ in inst})}
+    return {"workload": f"{count} PFC instances, eps=0.4, h=pi/(2 sqrt 3), s=0.02, n~U{{64,128,256}} "
+                        f"({', '.join(f'{v} x {k}^2' for k, v in sizes.items())}), one batch, "
                         f"{steps} steps, mixed precision, tol 1e-10",
             "solves_per_s": round(count * steps / T, 1), "seconds": round(T, 4),
             "unbatched_fp64_solves_per_s": round(unb, 1), "unbatched_sample": len(sub),

@@ -1,7 +1,10 @@
-// Kernels of the batched solve: many equally sized instances per launch,
-// instance = blockIdx.z (or blockIdx.x for one workgroup per instance),
-// descriptors in device arrays, instances whose flag in `active` is 0 skipped.
-// The arithmetic is the single-instance device code.
+// Kernels of the batched solve: many instances per launch, instance =
+// blockIdx.z (or blockIdx.x for one workgroup per instance), descriptors in
+// device arrays, instances whose flag in `active` is 0 skipped.  Instances may
+// differ in grid size: a launch over each instance's finest level is sized
+// for the largest, and every thread outside its own instance's grid returns
+// (or adds nothing to the partial sums).  The arithmetic is the
+// single-instance device code.
 #pragma once
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -110,16 +113,19 @@ __global__ void k_reduce_b(const double* __restrict__ partial, int count, int ps
 }
 
 // The per-instance stop test on the device: for each active instance z,
-// norm2[z] = h_z^2 * (sum of its partials, in k_reduce_b's order); with
+// norm2[z] = h_z^2 * (sum of its partials, in k_reduce_b's order: `count` of
+// them, or counts[z] when counts is not null); with
 // `counted` the cycle that produced it is counted in cyc[z]; the instance
 // leaves the batch with stat[z] = 1 once sqrt(norm2) <= tol[z], 2 if the norm
 // is not finite, 3 if cyc[z] reached maxc[z].  One workgroup per instance.
-__global__ void k_reduce_stop_b(const double* __restrict__ partial, int count, int pstride, const Lvl<double>* Ls,
-                                int* active, double* __restrict__ norm2, int* cyc, int* stat,
-                                const double* __restrict__ tol, const int* __restrict__ maxc, int counted) {
+__global__ void k_reduce_stop_b(const double* __restrict__ partial, int count, const int* __restrict__ counts,
+                                int pstride, const Lvl<double>* Ls, int* active, double* __restrict__ norm2,
+                                int* cyc, int* stat, const double* __restrict__ tol, const int* __restrict__ maxc,
+                                int counted) {
   __shared__ double lds[16];
   const int z = blockIdx.x;
   if (!active[z]) return;
+  if (counts) count = counts[z];
   double acc = 0.0;
   for (int t = threadIdx.x; t < count; t += blockDim.x) acc += partial[(size_t)z * pstride + t];
   const double r = block_sum(acc, lds);

@@ -1153,38 +1153,58 @@ extern "C" int hfz_step_noalloc(const hfz_params* p, double* rho, double* u, dou
 }
 
 // ===========================================================================
-// Batched solve: many independent instances of one model, grid size and
-// precision advance together.  Every instance is an ordinary handle over its
-// own slice of the batch workspace (so set/get state, energy and the per-step
-// kernels are the single-instance ones); the V-cycles of all instances run in
-// shared launches, one per grid level and phase, with the instance in
-// blockIdx.z (the coarse tail: one workgroup per instance).  Each instance
-// keeps its own stop test; converged instances drop out of the launches.
+// Batched solve: many independent instances of one model and precision
+// advance together; their grid sizes may differ.  Every instance is an
+// ordinary handle over its own slice of the batch workspace (so set/get
+// state, energy and the per-step kernels are the single-instance ones).  The
+// instances are kept sorted by grid size, largest first (the slot order), and
+// their multigrid levels are aligned from the coarsest grid, which all share:
+// at depth d (d = 0 the coarsest level) every instance that has a level there
+// has a grid of size coarsest_n * 2^d, and those instances are the first
+// cnt[d] slots.  Each V-cycle phase of one depth is then one launch over those
+// instances (instance in blockIdx.z; the coarse tail one workgroup per
+// instance, one launch per tail size), and each instance's phases run in the
+// order of its own V-cycle, so it gets the result it gets alone.  Each
+// instance keeps its own stop test; converged instances drop out of the
+// launches.
 // ===========================================================================
 
 struct hfz_batch {
   int count = 0;
-  hfz_params p{};  // model, n, precision, nu1, nu2, ... shared by all instances
+  hfz_params p{};  // model, precision, nu1, nu2, coarsest_n, coarse_sweeps, continuity_fix: shared
   int tile_force = -1;  // smoother tile shape forced by HFZ_BATCH_TILE at init (-1: by level size)
   hipStream_t stream = nullptr;
-  std::vector<hfz_handle*> inst;
-  int nlev = 0;
+  std::vector<hfz_handle*> inst;  // by slot
+  std::vector<int> slot_of;       // user index -> slot
+  int nmax = 0;                   // largest grid
+  int depths = 0;                 // levels of the largest instance
+  std::vector<int> cnt;           // [depth] instances with a level there (slots 0 .. cnt - 1)
+  std::vector<int> size_at;       // [depth] grid size there
+  std::vector<int> h_top;         // [slot] depth of the instance's finest level
+  int tail_depth = 0;             // depth of the tail's top level (tail_n) for instances that large
+  std::vector<int> tail_first, tail_count, tail_top;  // tail launches: first slot, slots, top depth
+  int tiled_count = 0;            // slots whose finest level is above the tail (the first ones)
+  std::vector<size_t> doff;       // start of depth d in D64 / D32
   // device arrays
-  Lvl<double>* D64 = nullptr;  // [level][instance]
+  Lvl<double>* D64 = nullptr;  // [depth][slot < cnt[depth]]
   Lvl<float>* D32 = nullptr;
-  Lvl<double>* T64 = nullptr;  // [instance][level] (tail descriptors)
+  Lvl<double>* L064 = nullptr;  // [slot] the finest level
+  Lvl<float>* L032 = nullptr;
+  Lvl<double>* T64 = nullptr;  // [slot][k] the tail's levels from its top down (TAIL_MAX_LEVELS per slot)
   Lvl<float>* T32 = nullptr;
-  Phys<double>* P64 = nullptr;  // [instance]
+  Phys<double>* P64 = nullptr;  // [slot]
   Phys<float>* P32 = nullptr;
   int* active = nullptr;
   double* norm2 = nullptr;
-  StateB* S = nullptr;   // [count] state arrays of each instance
-  int* on = nullptr;      // [count] instances the batched begin / finish kernels treat
+  StateB* S = nullptr;   // [slot] state arrays of each instance
+  int* on = nullptr;     // [slot] instances the batched begin / finish kernels treat
   std::vector<int> h_on;
-  int* cyc = nullptr;     // [count] V-cycles (mixed: outer iterations) of the current step
-  int* stat = nullptr;    // [count] 0 running, 1 converged, 2 not finite, 3 max_cycles reached
-  double* tol = nullptr;  // [count]
-  int* maxc = nullptr;    // [count]
+  int* cyc = nullptr;     // [slot] V-cycles (mixed: outer iterations) of the current step
+  int* stat = nullptr;    // [slot] 0 running, 1 converged, 2 not finite, 3 max_cycles reached
+  double* tol = nullptr;  // [slot]
+  int* maxc = nullptr;    // [slot]
+  int* topd = nullptr;    // [slot] depth of the finest level
+  int* npart = nullptr;   // [slot] stop-test partial sums a V-cycle leaves for the instance
   double* partial = nullptr;
   int pstride = 0;
   int cycle_hint = 4;  // most cycles an instance needed in the previous step
@@ -1199,35 +1219,63 @@ struct hfz_batch {
 namespace {
 
 bool batch_compatible(const hfz_params& a, const hfz_params& b) {
-  return a.model == b.model && a.n == b.n && a.precision == b.precision && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
-         a.coarsest_n == b.coarsest_n && a.coarse_sweeps == b.coarse_sweeps;
+  return a.model == b.model && a.precision == b.precision && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
+         a.coarsest_n == b.coarsest_n && a.coarse_sweeps == b.coarse_sweeps && a.continuity_fix == b.continuity_fix;
 }
 
-struct BatchLayout {
-  size_t inst_bytes = 0, total = 0;
-  size_t off_arrays = 0;
+// Host-side geometry of a batch: slot order, the instances' workspace slices,
+// the per-depth counts and the offsets of the batch arrays.
+struct BatchGeom {
+  std::vector<int> order;  // slot -> user index (grid size descending, stable)
+  std::vector<int> n, nlev;
+  std::vector<size_t> ws_off, ws_bytes;
+  int depths = 0;
+  std::vector<int> cnt;
+  size_t ndesc = 0;
+  int pstride = 0;
+  size_t off_arrays = 0, total = 0;
 };
 
-BatchLayout batch_layout(const hfz_params* ps, int count) {
-  BatchLayout bl;
-  bl.inst_bytes = align_up(layout(ps[0], nullptr, nullptr));
-  bl.off_arrays = bl.inst_bytes * count;
+BatchGeom batch_geom(const hfz_params* ps, int count) {
+  BatchGeom G;
+  G.order.resize(count);
+  for (int i = 0; i < count; ++i) G.order[i] = i;
+  std::stable_sort(G.order.begin(), G.order.end(), [&](int a, int b) { return ps[a].n > ps[b].n; });
+  size_t off = 0;
+  for (int k = 0; k < count; ++k) {
+    const hfz_params& p = ps[G.order[k]];
+    G.n.push_back(p.n);
+    G.nlev.push_back(ilog2(p.n) - ilog2(p.coarsest_n) + 1);
+    const size_t b = align_up(layout(p, nullptr, nullptr));
+    G.ws_off.push_back(off);
+    G.ws_bytes.push_back(b);
+    off += b;
+    G.ndesc += G.nlev.back();
+  }
+  G.depths = G.nlev[0];
+  G.cnt.assign(G.depths, 0);
+  for (int k = 0; k < count; ++k)
+    for (int d = 0; d < G.nlev[k]; ++d) G.cnt[d]++;
+  G.off_arrays = off;
+  G.pstride = (int)((size_t)G.n[0] * G.n[0] / 256 + 64);
   Carver c{nullptr};
-  const int nlev = ilog2(ps[0].n) - ilog2(ps[0].coarsest_n) + 1;
-  const size_t N2 = (size_t)ps[0].n * ps[0].n;
-  c.take<Lvl<double>>((size_t)nlev * count * 2);
-  c.take<Lvl<float>>((size_t)nlev * count * 2);
+  c.take<Lvl<double>>(G.ndesc);
+  c.take<Lvl<float>>(G.ndesc);
+  c.take<Lvl<double>>(count);
+  c.take<Lvl<float>>(count);
+  c.take<Lvl<double>>((size_t)count * TAIL_MAX_LEVELS);
+  c.take<Lvl<float>>((size_t)count * TAIL_MAX_LEVELS);
   c.take<Phys<double>>(count);
   c.take<Phys<float>>(count);
   c.take<int>(count);
   c.take<double>(count);
-  c.take<int>((size_t)count * 3);
+  c.take<int>((size_t)count * 5);
   c.take<double>(count);
   c.take<StateB>(count);
   c.take<int>(count);
-  c.take<double>((N2 / 256 + 64) * count);
-  bl.total = bl.off_arrays + c.off;
-  return bl;
+  c.take<double>((size_t)G.pstride * count);
+  G.total = G.off_arrays + c.off;
+  return G;
 }
 
 // Tile shape of the batched smoother on an n x n level: 64x16 tiles of 512
@@ -1240,30 +1288,41 @@ int batch_tile_shape(int n, int forced) {
   return n >= 128 && fits(2) ? 2 : 0;
 }
 
+// Launch grid over each instance's finest level (sized for the largest; the
+// kernels' threads outside their own instance's grid return).
+void batch_top_grid(const hfz_batch* B, int n, int count, dim3* g, dim3* b) {
+  *b = block2(n, n);
+  const dim3 g2 = grid2(n, n, *b);
+  *g = dim3(g2.x, g2.y, count);
+}
+
+// One batched V-cycle from depth d down: a tiled level launched over the
+// first cnt[d] slots, or, at the tail's depth, the tails of all instances.
 template <int MODEL, typename T, bool CORR>
-void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_max,
-                 const Cycle& K, int l) {
+void bvcycle_depth(hfz_batch* B, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_max, const Cycle& K, int d) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
-  const int nlev = (int)R.size(), count = B->count;
-  int d_from = 0;
-  if (R[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(R[l].n, nlev - l, lds_max, &d_from)) {
-    TailArgs<T> A{};
-    A.Lg = Tl + l;
-    A.nt = nlev - l;
-    A.top_n = R[l].n;
-    A.nu1 = K.nu1;
-    A.nu2 = K.nu2;
-    A.coarse_sweeps = K.coarse_sweeps;
-    A.d_from = d_from;
-    const size_t sh = tail_lds_count<NCm, NB, NR, 0, tail_pm<MODEL>()>(A.top_n, A.nt, A.d_from) * sizeof(T);
-    k_tail_b<MODEL, T, CORR><<<count, TAIL_THREADS, sh, K.stream>>>(A, nlev, Ps, B->active);
+  if (d <= B->tail_depth) {
+    for (size_t t = 0; t < B->tail_first.size(); ++t) {
+      const int first = B->tail_first[t], td = B->tail_top[t];
+      TailArgs<T> A{};
+      A.Lg = Tl + (size_t)first * TAIL_MAX_LEVELS;
+      A.nt = td + 1;
+      A.top_n = B->size_at[td];
+      A.nu1 = K.nu1;
+      A.nu2 = K.nu2;
+      A.coarse_sweeps = K.coarse_sweeps;
+      tail_plan<MODEL, T, CORR>(A.top_n, A.nt, lds_max, &A.d_from);
+      const size_t sh = tail_lds_count<NCm, NB, NR, 0, tail_pm<MODEL>()>(A.top_n, A.nt, A.d_from) * sizeof(T);
+      k_tail_b<MODEL, T, CORR><<<B->tail_count[t], TAIL_THREADS, sh, K.stream>>>(A, TAIL_MAX_LEVELS, Ps + first,
+                                                                                 B->active + first);
+    }
     return;
   }
-  Lvl<T>* Dl = D + (size_t)l * count;
-  Lvl<T>* Dc = D + (size_t)(l + 1) * count;
-  const int n = R[l].n, nc = R[l + 1].n;
+  Lvl<T>* Dl = D + B->doff[d];
+  Lvl<T>* Dc = D + B->doff[d - 1];
+  const int n = B->size_at[d], nc = B->size_at[d - 1], cz = B->cnt[d];
   const int ts = batch_tile_shape(n, B->tile_force);
-  const dim3 grid(n / kTileShapes[ts].tx, n / kTileShapes[ts].ty, count);
+  const dim3 grid(n / kTileShapes[ts].tx, n / kTileShapes[ts].ty, cz);
   int inb = 0;
   auto sweeps = [&](int total, bool pro, int res_last) {
     while (total > 0) {
@@ -1273,10 +1332,10 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
   do {                                                                                                         \
     if (ts == 2)                                                                                               \
       k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR, 2><<<grid, kTileShapes[2].nt, 0, K.stream>>>(             \
-          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride);                                                 \
+          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride, B->topd, d);                                      \
     else                                                                                                       \
       k_sweeps_tile_b<MODEL, T, NSW, PRO, RES, CORR, 0><<<grid, kTileShapes[0].nt, 0, K.stream>>>(             \
-          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride);                                                 \
+          Dl, Dc, Ps, B->active, inb, B->partial, B->pstride, B->topd, d);                                      \
   } while (0)
       if (nsw == 2) {
         if (pro) {
@@ -1298,11 +1357,13 @@ void bvcycle_rec(hfz_batch* B, const std::vector<Lvl<T>>& R, Lvl<T>* D, Lvl<T>* 
     }
   };
   sweeps(K.nu1, false, 1);
-  k_restrict_fas_tile_b<MODEL, T, CORR><<<dim3(nc / RTILE, nc / RTILE, count), RTILE * RTILE, 0, K.stream>>>(
+  k_restrict_fas_tile_b<MODEL, T, CORR><<<dim3(nc / RTILE, nc / RTILE, cz), RTILE * RTILE, 0, K.stream>>>(
       Dl, Dc, Ps, B->active, inb);
-  bvcycle_rec<MODEL, T, CORR>(B, R, D, Tl, Ps, lds_max, K, l + 1);
-  sweeps(K.nu2, true, (l == 0 && !CORR) ? 2 : 0);
-  if (inb) k_swap_back_b<T><<<dim3((n * n + 255) / 256, 1, count), 256, 0, K.stream>>>(Dl, B->active, NCm);
+  bvcycle_depth<MODEL, T, CORR>(B, D, Tl, Ps, lds_max, K, d - 1);
+  // the post-sweeps leave stop-test partial sums for the instances whose
+  // finest level this is (FP64 solve)
+  sweeps(K.nu2, true, CORR ? 0 : 2);
+  if (inb) k_swap_back_b<T><<<dim3((n * n + 255) / 256, 1, cz), 256, 0, K.stream>>>(Dl, B->active, NCm);
 }
 
 // Enqueues one batched V-cycle (mixed: one outer iteration), the
@@ -1312,43 +1373,40 @@ template <int MODEL> void batch_cycle(hfz_batch* B, hipStream_t stream) {
   Cycle K = cycle_ctx(h0);
   K.stream = stream;
   K.partial = B->partial;
-  const int n = B->p.n;
-  const dim3 b = block2(n, n);
-  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, B->count);
+  dim3 g, b;
+  batch_top_grid(B, B->nmax, B->count, &g, &b);
   if (B->p.precision == HFZ_MIXED) {
     for (int i = 0; i < h0->mp_inner; ++i)
-      bvcycle_rec<MODEL, float, true>(B, h0->H32.L, B->D32, B->T32, B->P32, B->lds32, K, 0);
-    k_mp_update_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->D32, B->active);
-    k_mp_prepare_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
-    k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                                   B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
+      bvcycle_depth<MODEL, float, true>(B, B->D32, B->T32, B->P32, B->lds32, K, B->depths - 1);
+    k_mp_update_b<MODEL><<<g, b, 0, stream>>>(B->L064, B->L032, B->active);
+    k_mp_prepare_b<MODEL><<<g, b, 0, stream>>>(B->L064, B->P64, B->L032, B->active, B->partial, B->pstride);
+    k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), nullptr, B->pstride, B->L064,
+                                                   B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
   } else {
-    bvcycle_rec<MODEL, double, false>(B, h0->H.L, B->D64, B->T64, B->P64, B->lds64, K, 0);
-    const bool tiled_top = n > K.tail_n;
-    if (tiled_top) {
-      const int ts = batch_tile_shape(n, B->tile_force);  // the shape of the level-0 launch that wrote the partial sums
-      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (n / kTileShapes[ts].tx) * (n / kTileShapes[ts].ty),
-                                                     B->pstride, B->D64,
-                                                     B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
-    } else {
-      k_residual_partial_b<MODEL><<<g, b, 0, stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
-      k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                                     B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
+    bvcycle_depth<MODEL, double, false>(B, B->D64, B->T64, B->P64, B->lds64, K, B->depths - 1);
+    if (B->tiled_count < B->count) {
+      // instances whose finest level is in the tail: their residual in its own pass
+      const int first = B->tiled_count;
+      dim3 gt, bt;
+      batch_top_grid(B, B->inst[first]->p.n, B->count - first, &gt, &bt);
+      k_residual_partial_b<MODEL><<<gt, bt, 0, stream>>>(B->L064 + first, B->P64 + first, B->active + first,
+                                                         B->partial + (size_t)first * B->pstride, B->pstride);
     }
+    k_reduce_stop_b<<<B->count, 1024, 0, stream>>>(B->partial, 0, B->npart, B->pstride, B->L064, B->active,
+                                                   B->norm2, B->cyc, B->stat, B->tol, B->maxc, 1);
   }
 }
 
 // The first stop test of a step (before any V-cycle).
 template <int MODEL> void batch_first_norm(hfz_batch* B) {
-  const int n = B->p.n;
-  const dim3 b = block2(n, n);
-  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, B->count);
+  dim3 g, b;
+  batch_top_grid(B, B->nmax, B->count, &g, &b);
   if (B->p.precision == HFZ_MIXED)
-    k_mp_prepare_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->D32, B->active, B->partial, B->pstride);
+    k_mp_prepare_b<MODEL><<<g, b, 0, B->stream>>>(B->L064, B->P64, B->L032, B->active, B->partial, B->pstride);
   else
-    k_residual_partial_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->P64, B->active, B->partial, B->pstride);
-  k_reduce_stop_b<<<B->count, 1024, 0, B->stream>>>(B->partial, (int)(g.x * g.y), B->pstride, B->D64, B->active,
-                                                    B->norm2, B->cyc, B->stat, B->tol, B->maxc, 0);
+    k_residual_partial_b<MODEL><<<g, b, 0, B->stream>>>(B->L064, B->P64, B->active, B->partial, B->pstride);
+  k_reduce_stop_b<<<B->count, 1024, 0, B->stream>>>(B->partial, (int)(g.x * g.y), nullptr, B->pstride, B->L064,
+                                                    B->active, B->norm2, B->cyc, B->stat, B->tol, B->maxc, 0);
 }
 
 void batch_cycle_any(hfz_batch* B, hipStream_t s) {
@@ -1379,23 +1437,21 @@ int batch_launch_cycle(hfz_batch* B) {
   return last_error();
 }
 
-// The batched begin of a step for the instances with h_on set: source,
-// iterate, frozen coefficients on every level (and their FP32 copies).
+// The batched begin of a step for the instances with h_on set: source and
+// iterate on each finest level, then the frozen coefficients restricted
+// depth by depth (and their FP32 copies).
 template <int MODEL> int batch_begin(hfz_batch* B) {
   HIPCHK(hipMemcpyAsync(B->on, B->h_on.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
   const bool mixed = B->p.precision == HFZ_MIXED;
-  const int count = B->count;
-  hfz_handle* h0 = B->inst[0];
-  for (int l = 0; l < B->nlev; ++l) {
-    const int n = h0->H.L[l].n;
-    const dim3 b = block2(n, n);
-    const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, count);
-    const Lvl<float>* E = mixed ? B->D32 + (size_t)l * count : nullptr;
-    if (l == 0)
-      k_begin_b<MODEL><<<g, b, 0, B->stream>>>(B->D64, B->S, B->P64, B->on, E);
-    else
-      k_restrict_coef_b<<<g, b, 0, B->stream>>>(B->D64 + (size_t)(l - 1) * count, B->D64 + (size_t)l * count, B->on,
-                                                 E);
+  dim3 g, b;
+  batch_top_grid(B, B->nmax, B->count, &g, &b);
+  k_begin_b<MODEL><<<g, b, 0, B->stream>>>(B->L064, B->S, B->P64, B->on, mixed ? B->L032 : nullptr);
+  for (int d = B->depths - 1; d >= 1; --d) {
+    const int nc = B->size_at[d - 1];
+    const dim3 bc = block2(nc, nc);
+    const dim3 gc(grid2(nc, nc, bc).x, grid2(nc, nc, bc).y, B->cnt[d]);
+    k_restrict_coef_b<<<gc, bc, 0, B->stream>>>(B->D64 + B->doff[d], B->D64 + B->doff[d - 1], B->on,
+                                                 mixed ? B->D32 + B->doff[d - 1] : nullptr);
   }
   return last_error();
 }
@@ -1404,15 +1460,14 @@ template <int MODEL> int batch_begin(hfz_batch* B) {
 // update, state <- g, and for CDFT the next convolution (per instance).
 template <int MODEL> int batch_finish(hfz_batch* B) {
   HIPCHK(hipMemcpyAsync(B->on, B->h_on.data(), B->count * sizeof(int), hipMemcpyHostToDevice, B->stream));
-  const int n = B->p.n, count = B->count;
-  const dim3 b = block2(n, n);
-  const dim3 g(grid2(n, n, b).x, grid2(n, n, b).y, count);
-  if (B->p.continuity_fix) k_continuity_b<<<g, b, 0, B->stream>>>(B->D64, B->P64, B->on);
-  k_state_b<MODEL><<<dim3((unsigned)(((size_t)n * n + 255) / 256), 1, count), 256, 0, B->stream>>>(B->D64, B->S,
-                                                                                                   B->on);
+  dim3 g, b;
+  batch_top_grid(B, B->nmax, B->count, &g, &b);
+  if (B->p.continuity_fix) k_continuity_b<<<g, b, 0, B->stream>>>(B->L064, B->P64, B->on);
+  const size_t nn = (size_t)B->nmax * B->nmax;
+  k_state_b<MODEL><<<dim3((unsigned)((nn + 255) / 256), 1, B->count), 256, 0, B->stream>>>(B->L064, B->S, B->on);
   if constexpr (MODEL == CDFT) {
-    for (int i = 0; i < count; ++i)
-      if (B->h_on[i]) convolve(B->inst[i], B->inst[i]->H.L[0].rk, B->inst[i]->jrho);
+    for (int k = 0; k < B->count; ++k)
+      if (B->h_on[k]) convolve(B->inst[k], B->inst[k]->H.L[0].rk, B->inst[k]->jrho);
   }
   return last_error();
 }
@@ -1438,7 +1493,7 @@ int hfz_batch_workspace_bytes(const hfz_params* params, int count, size_t* bytes
   // the batched V-cycle runs the tiled kernels above the one-workgroup tail,
   // which takes the coarsest level
   if (params[0].nu1 < 1 || params[0].nu2 < 1 || params[0].coarsest_n > kTailNMax) return HFZ_EINVAL;
-  *bytes = batch_layout(params, count).total;
+  *bytes = batch_geom(params, count).total;
   return HFZ_OK;
 }
 
@@ -1453,15 +1508,17 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return HFZ_EINVAL;
   hfz_batch* B = new (std::nothrow) hfz_batch();
   if (!B) return HFZ_ENOMEM;
+  const BatchGeom G = batch_geom(params, count);
   B->count = count;
-  B->p = params[0];
+  B->p = params[G.order[0]];
   if (const char* e = std::getenv("HFZ_BATCH_TILE")) B->tile_force = std::atoi(e);
   B->stream = static_cast<hipStream_t>(hip_stream);
-  const BatchLayout bl = batch_layout(params, count);
   char* base = static_cast<char*>(dev_ws);
-  for (int i = 0; i < count; ++i) {
+  B->slot_of.assign(count, 0);
+  for (int k = 0; k < count; ++k) {
+    const int i = G.order[k];
     hfz_handle* h = nullptr;
-    rc = hfz_init(&params[i], base + bl.inst_bytes * i, bl.inst_bytes, hip_stream, &h);
+    rc = hfz_init(&params[i], base + G.ws_off[k], G.ws_bytes[k], hip_stream, &h);
     if (rc != HFZ_OK) {
       hfz_batch_destroy(B);
       return rc;
@@ -1472,45 +1529,75 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
     h->tail_n = std::max(h->tail_n, params[i].coarsest_n);
     h->use_tiles = true;
     B->inst.push_back(h);
+    B->slot_of[i] = k;
   }
-  B->nlev = B->inst[0]->nlev;
-  Carver c{base + bl.off_arrays};
-  const int nl = B->nlev;
-  B->D64 = c.take<Lvl<double>>((size_t)nl * count);
-  B->T64 = c.take<Lvl<double>>((size_t)nl * count);
-  B->D32 = c.take<Lvl<float>>((size_t)nl * count);
-  B->T32 = c.take<Lvl<float>>((size_t)nl * count);
+  const int cn = B->p.coarsest_n;
+  B->nmax = G.n[0];
+  B->depths = G.depths;
+  B->cnt = G.cnt;
+  B->size_at.resize(B->depths);
+  for (int d = 0; d < B->depths; ++d) B->size_at[d] = cn << d;
+  B->h_top.resize(count);
+  for (int k = 0; k < count; ++k) B->h_top[k] = G.nlev[k] - 1;
+  B->tail_depth = ilog2(B->inst[0]->tail_n) - ilog2(cn);
+  // tail launches: consecutive slots whose tails start at the same depth
+  for (int k = 0; k < count; ++k) {
+    const int td = std::min(B->h_top[k], B->tail_depth);
+    if (B->tail_first.empty() || B->tail_top.back() != td) {
+      B->tail_first.push_back(k);
+      B->tail_count.push_back(0);
+      B->tail_top.push_back(td);
+    }
+    B->tail_count.back()++;
+    if (B->h_top[k] > B->tail_depth) B->tiled_count = k + 1;
+  }
+  Carver c{base + G.off_arrays};
+  B->D64 = c.take<Lvl<double>>(G.ndesc);
+  B->D32 = c.take<Lvl<float>>(G.ndesc);
+  B->L064 = c.take<Lvl<double>>(count);
+  B->L032 = c.take<Lvl<float>>(count);
+  B->T64 = c.take<Lvl<double>>((size_t)count * TAIL_MAX_LEVELS);
+  B->T32 = c.take<Lvl<float>>((size_t)count * TAIL_MAX_LEVELS);
   B->P64 = c.take<Phys<double>>(count);
   B->P32 = c.take<Phys<float>>(count);
   B->active = c.take<int>(count);
   B->norm2 = c.take<double>(count);
-  int* ints = c.take<int>((size_t)count * 3);
+  int* ints = c.take<int>((size_t)count * 5);
   B->cyc = ints;
   B->stat = ints + count;
   B->maxc = ints + 2 * count;
+  B->topd = ints + 3 * count;
+  B->npart = ints + 4 * count;
   B->tol = c.take<double>(count);
   B->S = c.take<StateB>(count);
   B->on = c.take<int>(count);
   B->h_on.assign(count, 0);
-  B->pstride = (int)((size_t)params[0].n * params[0].n / 256 + 64);
+  B->pstride = G.pstride;
   B->partial = c.take<double>((size_t)B->pstride * count);
-  const bool mixed = params[0].precision == HFZ_MIXED;
-  std::vector<Lvl<double>> d64((size_t)nl * count), t64((size_t)nl * count);
-  std::vector<Lvl<float>> d32(mixed ? (size_t)nl * count : 0), t32(mixed ? (size_t)nl * count : 0);
+  const bool mixed = B->p.precision == HFZ_MIXED;
+  std::vector<Lvl<double>> d64(G.ndesc), t64((size_t)count * TAIL_MAX_LEVELS), l064(count);
+  std::vector<Lvl<float>> d32(G.ndesc), t32((size_t)count * TAIL_MAX_LEVELS), l032(count);
   std::vector<Phys<double>> p64(count);
   std::vector<Phys<float>> p32(count);
-  for (int i = 0; i < count; ++i) {
-    hfz_handle* h = B->inst[i];
-    for (int l = 0; l < nl; ++l) {
-      d64[(size_t)l * count + i] = h->H.L[l];
-      t64[(size_t)i * nl + l] = h->H.L[l];
-      if (mixed) {
-        d32[(size_t)l * count + i] = h->H32.L[l];
-        t32[(size_t)i * nl + l] = h->H32.L[l];
-      }
+  B->doff.assign(B->depths, 0);
+  for (int d = 1; d < B->depths; ++d) B->doff[d] = B->doff[d - 1] + B->cnt[d - 1];
+  for (int k = 0; k < count; ++k) {
+    hfz_handle* h = B->inst[k];
+    const int top = B->h_top[k];
+    for (int l = 0; l <= top; ++l) {
+      const int d = top - l;  // level l of this instance sits at depth d
+      d64[B->doff[d] + k] = h->H.L[l];
+      if (mixed) d32[B->doff[d] + k] = h->H32.L[l];
     }
-    p64[i] = h->H.P;
-    p32[i] = h->H32.P;
+    const int td = std::min(top, B->tail_depth);
+    for (int j = 0; j <= td; ++j) {
+      t64[(size_t)k * TAIL_MAX_LEVELS + j] = h->H.L[top - td + j];
+      if (mixed) t32[(size_t)k * TAIL_MAX_LEVELS + j] = h->H32.L[top - td + j];
+    }
+    l064[k] = h->H.L[0];
+    if (mixed) l032[k] = h->H32.L[0];
+    p64[k] = h->H.P;
+    p32[k] = h->H32.P;
   }
   if (B->p.model == HFZ_PFC) {
     B->lds64 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<PFC, double, false>));
@@ -1519,16 +1606,38 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
     B->lds64 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, double, false>));
     B->lds32 = lds_optin(reinterpret_cast<const void*>(&k_tail_b<CDFT, float, true>));
   }
-  {
-    hfz_handle* h0 = B->inst[0];
-    const bool held = B->p.model == HFZ_PFC
-                          ? (mixed ? tail_holds_bottom<PFC, float, true>(h0->H32.L, h0->tail_n, B->lds32)
-                                   : tail_holds_bottom<PFC, double, false>(h0->H.L, h0->tail_n, B->lds64))
-                          : (mixed ? tail_holds_bottom<CDFT, float, true>(h0->H32.L, h0->tail_n, B->lds32)
-                                   : tail_holds_bottom<CDFT, double, false>(h0->H.L, h0->tail_n, B->lds64));
+  // every tail launch must hold its levels in LDS (the tiled path has no
+  // coarsest-level smoother)
+  for (size_t t = 0; t < B->tail_first.size(); ++t) {
+    const int td = B->tail_top[t], nt = td + 1, top_n = B->size_at[td];
+    const bool held =
+        nt <= TAIL_MAX_LEVELS &&
+        (B->p.model == HFZ_PFC
+             ? (mixed ? tail_plan<PFC, float, true>(top_n, nt, B->lds32, nullptr)
+                      : tail_plan<PFC, double, false>(top_n, nt, B->lds64, nullptr))
+             : (mixed ? tail_plan<CDFT, float, true>(top_n, nt, B->lds32, nullptr)
+                      : tail_plan<CDFT, double, false>(top_n, nt, B->lds64, nullptr)));
     if (!held) {
       hfz_batch_destroy(B);
       return HFZ_EINVAL;
+    }
+  }
+  // stop-test partial sums per instance: the tiles of its finest level's
+  // post-sweep launch, or the blocks of the tail-only instances' residual pass
+  std::vector<int> tops(count), nparts(count);
+  {
+    const int first = B->tiled_count;
+    dim3 gt(1, 1, 1), bt;
+    if (first < count) batch_top_grid(B, B->inst[first]->p.n, count - first, &gt, &bt);
+    for (int k = 0; k < count; ++k) {
+      const int n = B->inst[k]->p.n;
+      tops[k] = B->h_top[k];
+      if (k < first) {
+        const int ts = batch_tile_shape(n, B->tile_force);
+        nparts[k] = (n / kTileShapes[ts].tx) * (n / kTileShapes[ts].ty);
+      } else {
+        nparts[k] = (int)(gt.x * gt.y);
+      }
     }
   }
   B->h_active.assign(count, 1);
@@ -1537,10 +1646,14 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
                            B->stream) == hipSuccess;
   ok = ok && hipMemcpyAsync(B->T64, t64.data(), t64.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
                             B->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(B->L064, l064.data(), l064.size() * sizeof(Lvl<double>), hipMemcpyHostToDevice,
+                            B->stream) == hipSuccess;
   if (mixed) {
     ok = ok && hipMemcpyAsync(B->D32, d32.data(), d32.size() * sizeof(Lvl<float>), hipMemcpyHostToDevice,
                               B->stream) == hipSuccess;
     ok = ok && hipMemcpyAsync(B->T32, t32.data(), t32.size() * sizeof(Lvl<float>), hipMemcpyHostToDevice,
+                              B->stream) == hipSuccess;
+    ok = ok && hipMemcpyAsync(B->L032, l032.data(), l032.size() * sizeof(Lvl<float>), hipMemcpyHostToDevice,
                               B->stream) == hipSuccess;
   }
   ok = ok && hipMemcpyAsync(B->P64, p64.data(), count * sizeof(Phys<double>), hipMemcpyHostToDevice, B->stream) ==
@@ -1548,21 +1661,23 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   ok = ok && hipMemcpyAsync(B->P32, p32.data(), count * sizeof(Phys<float>), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
   std::vector<StateB> sts(count);
-  for (int i = 0; i < count; ++i) {
-    hfz_handle* h = B->inst[i];
-    sts[i] = StateB{h->u, h->v, h->mu, h->ka, h->jrho};
+  std::vector<double> tols(count);
+  std::vector<int> maxcs(count);
+  for (int k = 0; k < count; ++k) {
+    hfz_handle* h = B->inst[k];
+    sts[k] = StateB{h->u, h->v, h->mu, h->ka, h->jrho};
+    tols[k] = h->p.tol;
+    maxcs[k] = h->p.max_cycles;
   }
   ok = ok && hipMemcpyAsync(B->S, sts.data(), count * sizeof(StateB), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
-  std::vector<double> tols(count);
-  std::vector<int> maxcs(count);
-  for (int i = 0; i < count; ++i) {
-    tols[i] = params[i].tol;
-    maxcs[i] = params[i].max_cycles;
-  }
   ok = ok && hipMemcpyAsync(B->tol, tols.data(), count * sizeof(double), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
   ok = ok && hipMemcpyAsync(B->maxc, maxcs.data(), count * sizeof(int), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(B->topd, tops.data(), count * sizeof(int), hipMemcpyHostToDevice, B->stream) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(B->npart, nparts.data(), count * sizeof(int), hipMemcpyHostToDevice, B->stream) ==
                  hipSuccess;
   ok = ok && hipStreamSynchronize(B->stream) == hipSuccess;
   if (!ok) {
@@ -1576,44 +1691,44 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
 
 int hfz_batch_set_state(hfz_batch* B, int i, const double* rho, const double* u, const double* v) {
   if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
-  return hfz_set_state(B->inst[i], rho, u, v);
+  return hfz_set_state(B->inst[B->slot_of[i]], rho, u, v);
 }
 
 int hfz_batch_get_state(hfz_batch* B, int i, double* rho, double* u, double* v) {
   if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
-  return hfz_get_state(B->inst[i], rho, u, v);
+  return hfz_get_state(B->inst[B->slot_of[i]], rho, u, v);
 }
 
 int hfz_batch_energy(hfz_batch* B, int i, double* out5) {
   if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
-  return hfz_energy(B->inst[i], out5);
+  return hfz_energy(B->inst[B->slot_of[i]], out5);
 }
 
 int hfz_batch_release(hfz_batch* B, int i) {
   if (!B || i < 0 || i >= B->count) return HFZ_EINVAL;
-  B->inst[i]->has_state = false;
+  B->inst[B->slot_of[i]]->has_state = false;
   return HFZ_OK;
 }
 
 int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
   if (!B || nsteps < 0) return HFZ_EINVAL;
   const int count = B->count;
-  std::vector<char> filled(count);
+  std::vector<char> filled(count);  // by slot
   int nfilled = 0;
-  for (int i = 0; i < count; ++i) nfilled += filled[i] = B->inst[i]->has_state ? 1 : 0;
+  for (int k = 0; k < count; ++k) nfilled += filled[k] = B->inst[k]->has_state ? 1 : 0;
   if (stats)
     for (int i = 0; i < count; ++i) stats[i] = hfz_stats{};
   if (nfilled == 0) return HFZ_OK;
-  std::vector<hfz_stats> st(count);
+  std::vector<hfz_stats> st(count);  // by slot
   std::vector<int> h_cyc(count), h_stat(count);
   int rc = HFZ_OK;
-  for (int k = 0; k < nsteps && rc == HFZ_OK; ++k) {
-    for (int i = 0; i < count; ++i) B->h_on[i] = filled[i];
+  for (int s = 0; s < nsteps && rc == HFZ_OK; ++s) {
+    for (int k = 0; k < count; ++k) B->h_on[k] = filled[k];
     rc = B->p.model == HFZ_PFC ? batch_begin<PFC>(B) : batch_begin<CDFT>(B);
     if (rc != HFZ_OK) break;
     // every instance runs until its own stop test ends it (on the device);
     // the host enqueues cycles in batches and reads the states once a batch
-    for (int i = 0; i < count; ++i) B->h_active[i] = filled[i];
+    for (int k = 0; k < count; ++k) B->h_active[k] = filled[k];
     rc = batch_write_active(B);
     if (rc != HFZ_OK) break;
     k_zero_ints<<<(2 * count + 255) / 256, 256, 0, B->stream>>>(B->cyc, 2 * count);
@@ -1635,36 +1750,36 @@ int hfz_batch_step(hfz_batch* B, int nsteps, hfz_stats* stats) {
         break;
       }
       bool running = false;
-      for (int i = 0; i < count; ++i) running = running || (filled[i] && h_stat[i] == 0);
+      for (int k = 0; k < count; ++k) running = running || (filled[k] && h_stat[k] == 0);
       if (!running) break;
       batch = 2;
     }
     if (rc != HFZ_OK) break;
     int most = 0;
     std::vector<int> failed(count, 0);
-    for (int i = 0; i < count; ++i) {
-      if (!filled[i]) continue;
-      st[i].cycles_last = h_cyc[i];
-      st[i].residual_last = std::sqrt(B->h_norm2[i]);
-      failed[i] = h_stat[i] == 2 ? HFZ_ENAN : h_stat[i] == 3 ? HFZ_ENOCONV : 0;
-      most = std::max(most, h_cyc[i]);
+    for (int k = 0; k < count; ++k) {
+      if (!filled[k]) continue;
+      st[k].cycles_last = h_cyc[k];
+      st[k].residual_last = std::sqrt(B->h_norm2[k]);
+      failed[k] = h_stat[k] == 2 ? HFZ_ENAN : h_stat[k] == 3 ? HFZ_ENOCONV : 0;
+      most = std::max(most, h_cyc[k]);
     }
     B->cycle_hint = most;
     // failed instances are rolled back: their state stays that of the previous step
-    for (int i = 0; i < count; ++i) B->h_on[i] = filled[i] && !failed[i];
+    for (int k = 0; k < count; ++k) B->h_on[k] = filled[k] && !failed[k];
     rc = B->p.model == HFZ_PFC ? batch_finish<PFC>(B) : batch_finish<CDFT>(B);
     if (rc != HFZ_OK) break;
-    for (int i = 0; i < count; ++i) {
-      if (!B->h_on[i]) continue;
-      st[i].steps_done++;
-      st[i].cycles_total += h_cyc[i];
+    for (int k = 0; k < count; ++k) {
+      if (!B->h_on[k]) continue;
+      st[k].steps_done++;
+      st[k].cycles_total += h_cyc[k];
     }
-    for (int i = 0; i < count; ++i)
-      if (failed[i] && rc == HFZ_OK) rc = failed[i];
+    for (int k = 0; k < count; ++k)
+      if (failed[k] && rc == HFZ_OK) rc = failed[k];
   }
   if (rc == HFZ_OK && hipStreamSynchronize(B->stream) != hipSuccess) rc = HFZ_EHIP;
   if (stats)
-    for (int i = 0; i < count; ++i) stats[i] = st[i];
+    for (int i = 0; i < count; ++i) stats[i] = st[B->slot_of[i]];
   return rc;
 }
 

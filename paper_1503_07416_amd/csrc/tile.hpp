@@ -43,9 +43,12 @@ template <typename T> struct Fld {
 // 2 the block's partial sum of |d|^2 written to partial[block] (the stop test).
 // A residual needs the swept values one node beyond the block, hence the
 // extra halo node.
+// res_on false skips the residual (a batched launch whose instance has this
+// level below its finest; uniform over the workgroup).
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
-                                                 const Lvl<T>& C, const Phys<T>& P, double* partial) {
+                                                 const Lvl<T>& C, const Phys<T>& P, double* partial,
+                                                 bool res_on = true) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
@@ -209,14 +212,16 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     __syncthreads();
   }
   if constexpr (PM && RES != 0) {
-    // M on the owned block and its one-node ring, for the residual rows
-    constexpr int BX = TILE_X + 2, BN = BX * (TILE_Y + 2);
-    for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
-      const int r = w / BX, t = w - r * BX;
-      const int lp = (H - 1 + r) * RX + H - 1 + t;
-      sm[lp] = potential_any<MODEL, T, CORR>(gl, bl, lp, P);
+    if (res_on) {
+      // M on the owned block and its one-node ring, for the residual rows
+      constexpr int BX = TILE_X + 2, BN = BX * (TILE_Y + 2);
+      for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
+        const int r = w / BX, t = w - r * BX;
+        const int lp = (H - 1 + r) * RX + H - 1 + t;
+        sm[lp] = potential_any<MODEL, T, CORR>(gl, bl, lp, P);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   double acc = 0.0;
   for (int w = threadIdx.x; w < TILE_X * TILE_Y; w += TILE_THREADS) {
@@ -235,6 +240,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       if (gy == 0) continue;  // the bottom wall row: no equation
     }
     if constexpr (RES != 0) {
+      if (!res_on) continue;
       Nbr q;
       q.p = lp;
       q.e = lp + 1;
@@ -255,9 +261,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
   }
   if constexpr (RES == 2) {
-    __shared__ double red[TILE_THREADS / 64];
-    const double r = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+    if (res_on) {
+      __shared__ double red[TILE_THREADS / 64];
+      const double r = block_sum(acc, red);
+      if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+    }
   }
 }
 
@@ -268,14 +276,17 @@ __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fl
   sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
 }
 
-// Batched form: instance blockIdx.z of equally sized instances, descriptors in
-// device arrays, skipped when not active.  The iterate is read from g (inb =
-// 0) or gb (inb = 1) and written to the other buffer; partial sums go to
-// partial + z * pstride.  TS: tile shape (0 or 2).
+// Batched form: instance blockIdx.z of the instances that have a level of this
+// size (all of the same size), descriptors in device arrays, skipped when not
+// active.  The iterate is read from g (inb = 0) or gb (inb = 1) and written to
+// the other buffer; partial sums go to partial + z * pstride, RES = 2 only for
+// the instances whose finest level is at depth `depth` (topd[z]; the others
+// are inside their V-cycle).  TS: tile shape (0 or 2).
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile_b(const Lvl<T>* Ls, const Lvl<T>* Cs,
                                                                 const Phys<T>* Ps, const int* active, int inb,
-                                                                double* partial, int pstride) {
+                                                                double* partial, int pstride, const int* topd,
+                                                                int depth) {
   const int z = blockIdx.z;
   if (!active[z]) return;
   const Lvl<T> L = lvl_global(Ls[z]);
@@ -287,7 +298,7 @@ __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile_b(const Lvl<
   }
   const Lvl<T> C = PRO ? lvl_global(Cs[z]) : L;
   sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, inb ? b : a, inb ? a : b, C, Ps[z],
-                                                      partial + (size_t)z * pstride);
+                                                      partial + (size_t)z * pstride, RES != 2 || topd[z] == depth);
 }
 
 }  // namespace hfz

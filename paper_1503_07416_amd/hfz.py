@@ -424,14 +424,14 @@ class Simulation3:
 
 
 class Batch:
-    """Many instances of one model, grid size and precision stepped together
-    (hfz_batch_* of the C ABI)."""
+    """Many instances of one model and precision, of any grid sizes, stepped
+    together (hfz_batch_* of the C ABI)."""
 
     def __init__(self, cfgs, device="cuda", stream=None):
         self.lib = load()
         self.count = len(cfgs)
         self.params = (Params * self.count)(*[make_params(c) for c in cfgs])
-        self.n = self.params[0].n
+        self.ns = [p.n for p in self.params]
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nb = ctypes.c_size_t(0)
@@ -451,7 +451,8 @@ class Batch:
         check(self.lib.hfz_batch_set_state(self.h, i, *[_ptr(x) for x in t]), "hfz_batch_set_state")
 
     def get_state(self, i):
-        t = [torch.empty((self.n, self.n), dtype=torch.float64, device=self.device) for _ in range(3)]
+        n = self.ns[i]
+        t = [torch.empty((n, n), dtype=torch.float64, device=self.device) for _ in range(3)]
         check(self.lib.hfz_batch_get_state(self.h, i, *[_ptr(x) for x in t]), "hfz_batch_get_state")
         return t
 

@@ -181,3 +181,31 @@ def test_workspace_too_small_is_enomem():
     assert lib.hfz3_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
     assert lib.hfz3_init(ctypes.byref(p), fake, nb.value - 1, None, ctypes.byref(out)) == -2
     assert not out.value
+
+
+def test_batch_accepts_uneven_sizes():
+    """The batch takes instances of different grid sizes (host-side sizing);
+    it refuses instances that differ in model, precision, cycle shape,
+    coarsest grid or coarse sweeps."""
+    lib = hfz.load()
+
+    def params(**kw):
+        p = hfz.Params()
+        assert lib.hfz_default_params(kw.pop("model", 0), ctypes.byref(p)) == 0
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    nb = ctypes.c_size_t(0)
+    arr = (hfz.Params * 4)(params(n=64), params(n=256), params(n=16), params(n=128))
+    assert lib.hfz_batch_workspace_bytes(arr, 4, ctypes.byref(nb)) == 0
+    single = 0
+    for n in (64, 256, 16, 128):
+        s = ctypes.c_size_t(0)
+        assert lib.hfz_workspace_bytes(ctypes.byref(params(n=n)), ctypes.byref(s)) == 0
+        single += s.value
+    assert nb.value > single
+    for bad in [dict(precision=1), dict(nu1=3), dict(coarsest_n=8), dict(coarse_sweeps=5), dict(model=1),
+                dict(continuity_fix=0)]:
+        arr = (hfz.Params * 2)(params(n=64), params(n=128, **bad))
+        assert lib.hfz_batch_workspace_bytes(arr, 2, ctypes.byref(nb)) == -1, bad
