@@ -19,7 +19,9 @@ Also reported on the same JSON line:
                 unbatched FP64 path, and the per-step energy check;
   serving       a Poisson stream of PFC and CDFT requests (n ~ U{64..1024},
                 10-200 steps) through the continuous-batching server under a
-                device-memory budget: p50/p99 per-step latency, throughput;
+                budget of 80 % of the device memory, the arrival rate from
+                Little's law for that occupancy: p50/p99 per-step latency,
+                throughput, peak reserved memory;
   cdft          CDFT 1024^2 (h = 17/128, s = 0.02), 50 steps with the energy
                 and mass read after every step;
   gradflow      the gradient-flow variant of the scheme (Thm. thm_grad) with the
@@ -74,8 +76,10 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=10, help="V-cycles of the oracle sample")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="processes of the parallel oracle sample (0: min(16, host CPUs))")
-    ap.add_argument("--serve-requests", type=int, default=40)
-    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-hbm-frac", type=float, default=0.8,
+                    help="serving budget as a fraction of the device memory")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving workload")
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
@@ -373,17 +377,20 @@ def run_batched(steps=20, count=256):
             "energy_increases": viol, "energy_checks": count * steps}
 
 
-def run_serving(requests, budget_gib):
-    """Config 5: pilot per class (alone, FP64 CDFT / mixed PFC) for the mean
-    residence time, arrival rate from Little's law for 80% of the budget,
-    then the stream through the server."""
+def run_serving(requests, hbm_frac):
+    """Config 5: the budget is hbm_frac (80 %) of the device's memory; a pilot
+    per class (alone, mixed PFC / FP64 CDFT) gives the mean residence time,
+    and the arrival rate follows Little's law for a mean occupancy of that
+    budget, lambda = budget / (E[bytes per request] E[residence]); then the
+    Poisson stream through the server."""
     import numpy as np
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
     from paper_1503_07416_amd.serve import DeviceBackend, Server
     be = DeviceBackend("cuda:0")
-    budget = int(budget_gib * 2**30)
+    hbm = torch.cuda.get_device_properties(0).total_memory
+    budget = int(hbm_frac * hbm)
     sizes = (64, 128, 256, 512, 1024)
     t_alone, slot = {}, {}
     for model in ("pfc", "cdft"):
@@ -407,14 +414,16 @@ def run_serving(requests, budget_gib):
             sim.close()
     e_bytes = float(np.mean(list(slot.values())))
     e_res = 105.0 * float(np.mean(list(t_alone.values())))
-    lam = 0.8 * budget / (e_bytes * e_res)
+    lam = budget / (e_bytes * e_res)
     reqs = workloads.serving_stream(requests, rate=lam, seed=0)
     alone = sum(t_alone[(r.cfg.model, r.cfg.n)] * r.steps for r in reqs)
     srv = Server(budget, backend=be, check_energy=True)
-    _, rep = srv.run(reqs, realtime=True)
+    _, rep = srv.run(reqs, realtime=True, progress_every=20.0, log=sys.stderr)
     rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
     rep.update({"workload": f"{requests} requests, PFC (mixed, as the batched workload) / CDFT (FP64, h=17/128, "
-                            "s=0.02) 50/50, n~U{64..1024}, steps~U{10..200}, Poisson arrivals, seed 0",
+                            "s=0.02) 50/50, n~U{64..1024}, steps~U{10..200}, Poisson arrivals, seed 0; "
+                            f"budget {hbm_frac:g} of the device memory",
+                "device_memory_bytes": hbm, "peak_reserved_frac_of_device": round(rep["peak_reserved_bytes"] / hbm, 4),
                 "arrival_rate_per_s": round(lam, 3), "mean_slot_bytes": int(e_bytes),
                 "mean_residence_alone_s": round(e_res, 4),
                 "sequential_alone_s": round(alone, 3),
@@ -712,6 +721,9 @@ def main():
     if a.batched_only:
         print(json.dumps({"batched": run_batched()}))
         return
+    if a.serving_only:
+        print(json.dumps({"serving": run_serving(a.serve_requests, a.serve_hbm_frac)}))
+        return
     if a.gradflow_only:
         print(json.dumps({"gradflow": run_gradflow()}))
         return
@@ -783,7 +795,7 @@ def main():
         torch.cuda.empty_cache()
         out["cdft"] = run_cdft()
         torch.cuda.empty_cache()
-        out["serving"] = run_serving(a.serve_requests, a.serve_budget_gib)
+        out["serving"] = run_serving(a.serve_requests, a.serve_hbm_frac)
         torch.cuda.empty_cache()
         out["gradflow"] = run_gradflow()
         torch.cuda.empty_cache()

@@ -251,6 +251,8 @@ class Server:
             for k, job in intake:
                 r = job.req
                 b.set_state(k, r.rho, r.u, r.v)
+                if hasattr(r, "drop_state"):
+                    r.drop_state()   # the host copy of the initial state is no longer needed
                 if self.check_energy:
                     job.energy.append(b.energy(k)[0])
                 pool.running[k] = job
@@ -287,10 +289,12 @@ class Server:
                     self.cv.notify_all()
 
     # ---- driver ---------------------------------------------------------------
-    def run(self, requests, realtime=True, poll=0.02):
+    def run(self, requests, realtime=True, poll=0.02, progress_every=None, log=None):
         """Serves `requests` (objects with arrival [s], steps, cfg, rho, u, v);
         arrivals are honoured in wall time if `realtime`, else all arrive at
-        once.  Returns (jobs in arrival order, report dict)."""
+        once.  With progress_every (seconds), a line of progress goes to `log`
+        (a file object) that often.  Returns (jobs in arrival order, report
+        dict)."""
         jobs = []
         for r in sorted(requests, key=lambda q: q.arrival):
             p = hfz.make_params(r.cfg)
@@ -303,6 +307,7 @@ class Server:
         arrivals = collections.deque(jobs)
         waiting = []
         t0 = time.perf_counter()
+        t_log = t0
         try:
             with self.cv:
                 while self.ndone < len(jobs):
@@ -314,6 +319,11 @@ class Server:
                         j.t_arrive = t0 + (j.req.arrival if realtime else 0.0)
                         waiting.append(j)
                     self._admit(waiting)
+                    if progress_every and log is not None and time.perf_counter() - t_log >= progress_every:
+                        t_log = time.perf_counter()
+                        print(f"serve: {self.ndone}/{len(jobs)} requests done, {len(waiting)} waiting, "
+                              f"{len(self.pools)} pools, {self.reserved / 2**30:.1f} GiB reserved, "
+                              f"{t_log - t0:.1f} s", file=log, flush=True)
                     tmo = poll
                     if arrivals and realtime:
                         tmo = min(tmo, max(0.0, arrivals[0].req.arrival - (time.perf_counter() - t0)))

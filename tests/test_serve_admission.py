@@ -97,7 +97,7 @@ class FakeBackend:
 def stream(count, sizes=(8, 16, 32), steps=(2, 9), seed=3):
     reqs = workloads.serving_stream(count, rate=2000.0, seed=seed, sizes=sizes, steps=steps)
     for r in reqs:
-        r.rho = np.array([float(r.rid), 0.0])   # the fake backend tracks (rid, steps taken)
+        r.fix_state(np.array([float(r.rid), 0.0]), None, None)   # the fake backend tracks (rid, steps taken)
     return reqs
 
 

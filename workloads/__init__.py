@@ -19,7 +19,7 @@ ambiguous, the reading taken and its reason are stated with it:
   the PFC and CDFT freezing runs' constants, grids and initial densities.
 """
 import math
-from dataclasses import dataclass, field, asdict
+from dataclasses import dataclass, asdict
 
 import numpy as np
 
@@ -237,15 +237,44 @@ def config4(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
     return out
 
 
-@dataclass
 class Request:
-    rid: int
-    arrival: float      # seconds after the stream starts
-    steps: int
-    cfg: Config
-    rho: np.ndarray = field(repr=False)
-    u: np.ndarray = field(repr=False)
-    v: np.ndarray = field(repr=False)
+    """One request of a serving stream: arrival time, steps, parameters, and
+    its initial state, drawn from its own seed when first read (so a stream of
+    thousands of requests holds no fields until they are served)."""
+
+    def __init__(self, rid, arrival, steps, cfg, draw):
+        self.rid, self.arrival, self.steps, self.cfg = rid, arrival, steps, cfg
+        self._draw = draw
+        self._state = None
+
+    def state(self):
+        if self._state is None:
+            self._state = self._draw()
+        return self._state
+
+    @property
+    def rho(self):
+        return self.state()[0]
+
+    @property
+    def u(self):
+        return self.state()[1]
+
+    @property
+    def v(self):
+        return self.state()[2]
+
+    def drop_state(self):
+        """Forgets the drawn state (it is drawn again, identically, if read)."""
+        self._state = None
+
+    def fix_state(self, rho, u, v):
+        """Replaces the state the request would draw (simulated backends)."""
+        self._state = (rho, u, v)
+        self._draw = lambda: (rho, u, v)
+
+    def __repr__(self):
+        return f"Request(rid={self.rid}, arrival={self.arrival:.4f}, steps={self.steps}, model={self.cfg.model}, n={self.cfg.n})"
 
 
 def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
@@ -262,16 +291,15 @@ def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
         t += rng.exponential(1.0 / rate)
         n = int(rng.choice(np.asarray(sizes)))
         nst = int(rng.integers(steps[0], steps[1] + 1))
+        cn = min(BENCH_COARSEST_N, n // 2)
         if rng.uniform() < 0.5:
             rb = float(rng.uniform(NANO_RHO_L, NANO_RHO_S))
-            cfg, rho, u, v = pfc_uniform_noise(n, NANO_H, 0.02, 5000 + i, rho_bar=rb,
-                                               alpha=1.0 - NANO_EPS, precision=pfc_precision,
-                                               coarsest_n=min(BENCH_COARSEST_N, n // 2))
+            cfg = Config("pfc", n, NANO_H, 0.02, alpha=1.0 - NANO_EPS, precision=pfc_precision, coarsest_n=cn)
+            draw = (lambda n=n, i=i, rb=rb: pfc_uniform_noise(n, NANO_H, 0.02, 5000 + i, rho_bar=rb)[1:])
         else:
-            cfg, rho, u, v = cdft_gauss_noise(n, 17.0 / 128.0, 0.02, 5000 + i,
-                                              precision=cdft_precision,
-                                              coarsest_n=min(BENCH_COARSEST_N, n // 2))
-        reqs.append(Request(i, t, nst, cfg, rho, u, v))
+            cfg = Config("cdft", n, 17.0 / 128.0, 0.02, precision=cdft_precision, coarsest_n=cn)
+            draw = (lambda n=n, i=i: cdft_gauss_noise(n, 17.0 / 128.0, 0.02, 5000 + i)[1:])
+        reqs.append(Request(i, t, nst, cfg, draw))
     return reqs
 
 
