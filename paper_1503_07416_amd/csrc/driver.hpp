@@ -25,6 +25,8 @@ template <typename T> struct Hier {
   std::vector<int> tile_shape;      // tile shape of the sweep kernel per level (tile.hpp)
   std::vector<int> restrict_shape;  // restriction variant per fine level (restrict.hpp)
   std::vector<int> sweep_fuse;      // sweeps per tiled launch per level (2 fused, or 1)
+  int fuse_tail = -1;  // >= 1: the FP64 V-cycle folds the FAS restriction into the sweep launches and
+                       // the tail starts at this level; -1: separate restriction launches
   Phys<T> P{};
 };
 
@@ -83,7 +85,7 @@ template <int MODEL, typename T, bool CORR> bool tail_plan(int top_n, int nt, si
   return true;
 }
 
-template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l) {
+template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& K, int l, bool fc = false) {
   constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 0, NR = NCoef<MODEL>::value;
   TailArgs<T> A{};
   A.nt = (int)H.L.size() - l;
@@ -92,6 +94,7 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
   A.nu1 = K.nu1;
   A.nu2 = K.nu2;
   A.coarse_sweeps = K.coarse_sweeps;
+  A.fc = fc ? 1 : 0;
   tail_plan<MODEL, T, CORR>(A.top_n, A.nt, H.tail_lds_max, &A.d_from);
   const size_t sh =
       tail_lds_count<NCm, NB, NR, walls(MODEL) ? 1 : 0, tail_pm<MODEL>()>(A.top_n, A.nt, A.d_from) * sizeof(T);
@@ -183,6 +186,71 @@ int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur,
   return blocks;  // workgroups of the last launch
 }
 
+// The pre-sweep launches of the fused restriction: fc completes the level's
+// right-hand side at load (first launch), res 3 restricts (last launch).
+template <int MODEL, typename T, bool CORR, int NSW, int TS, bool FC>
+int tile_launch_fused_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
+                            const Lvl<T>& C, int res) {
+  constexpr TileShape S = kTileShapes[TS];
+  const dim3 grid(L.n / S.tx, L.n / S.ty);
+  if (res == 3)
+    k_sweeps_tile<MODEL, T, NSW, false, 3, CORR, TS, FC><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+  else
+    k_sweeps_tile<MODEL, T, NSW, false, 0, CORR, TS, FC><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+  return (int)(grid.x * grid.y);
+}
+
+template <int MODEL, typename T, bool CORR, int NSW>
+void tile_launch_fused(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
+                       const Lvl<T>& C, int res, int ts, bool fc) {
+  if (!tile_shape_fits(ts, L.n)) ts = 0;
+  if (fc && ts == 2) ts = 1;  // 64x16 tiles with f and omega^k in LDS would exceed a CU's LDS
+  if (fc) {
+    switch (ts) {
+      case 1: tile_launch_fused_shape<MODEL, T, CORR, NSW, 1, true>(H, K, L, in, out, C, res); return;
+      case 3: tile_launch_fused_shape<MODEL, T, CORR, NSW, 3, true>(H, K, L, in, out, C, res); return;
+      default: tile_launch_fused_shape<MODEL, T, CORR, NSW, 0, true>(H, K, L, in, out, C, res); return;
+    }
+  }
+  switch (ts) {
+    case 1: tile_launch_fused_shape<MODEL, T, CORR, NSW, 1, false>(H, K, L, in, out, C, res); return;
+    case 2: tile_launch_fused_shape<MODEL, T, CORR, NSW, 2, false>(H, K, L, in, out, C, res); return;
+    case 3: tile_launch_fused_shape<MODEL, T, CORR, NSW, 3, false>(H, K, L, in, out, C, res); return;
+    default: tile_launch_fused_shape<MODEL, T, CORR, NSW, 0, false>(H, K, L, in, out, C, res); return;
+  }
+}
+
+// The pre-sweeps of level l with the fused restriction (nu1 >= 1): the first
+// launch completes the right-hand side when fc is set, the last forms the
+// coarse level's R g and R d.
+template <int MODEL, typename T, bool CORR>
+void presweeps_fused(Hier<T>& H, Cycle& K, int l, bool fc, Fld<T>& cur, Fld<T>& other) {
+  const Lvl<T>& L = H.L[l];
+  const Lvl<T>& C = H.L[l + 1];
+  const int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
+  const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
+  int sweeps = K.nu1;
+  bool first = true;
+  while (sweeps > 0) {
+    const int nsw = (sweeps >= 2 && fuse >= 2) ? 2 : 1;
+    const int res = (sweeps == nsw) ? 3 : 0;
+    const bool f = first && fc;
+    if (!f && res == 0) {
+      if (nsw == 2)
+        tile_launch<MODEL, T, CORR, 2, false>(H, K, L, cur, other, C, 0, ts);
+      else
+        tile_launch<MODEL, T, CORR, 1, false>(H, K, L, cur, other, C, 0, ts);
+    } else if (nsw == 2) {
+      tile_launch_fused<MODEL, T, CORR, 2>(H, K, L, cur, other, C, res, ts, f);
+    } else {
+      tile_launch_fused<MODEL, T, CORR, 1>(H, K, L, cur, other, C, res, ts, f);
+    }
+    std::swap(cur, other);
+    sweeps -= nsw;
+    first = false;
+  }
+}
+
 template <typename T> void copy_fields(Cycle& K, const Fld<T>& a, const Fld<T>& b, int nc, size_t cnt) {
   for (int c = 0; c < nc; ++c)
     k_copy_t<T><<<(unsigned)((cnt + 255) / 256), 256, 0, K.stream>>>(a.c[c], b.c[c], cnt, K.halt);
@@ -256,9 +324,46 @@ template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K
   }
 }
 
+// A visit to level l of the FP64 V-cycle with the fused restriction: the
+// pre-sweeps (fc: the first completes the level's right-hand side) end with
+// the restriction, the coarser levels (down to the tail, whose top completes
+// its right-hand side too), the prolongation fused into the first post-sweep,
+// post-sweeps.  Every value is the one the separate restriction launches give.
+template <int MODEL, typename T, bool CORR> void vcycle_fused(Hier<T>& H, Cycle& K, int l, bool fc) {
+  if constexpr (!CORR && !walls(MODEL)) {
+    constexpr int NCm = NC<MODEL>::value;
+    const Lvl<T>& L = H.L[l];
+    const Fld<T> home = fld<T>(L.g);
+    Fld<T> cur = home, other = fld<T>(L.gb);
+    presweeps_fused<MODEL, T, CORR>(H, K, l, fc, cur, other);
+    if (l + 1 == H.fuse_tail)
+      tail_launch<MODEL, T, CORR>(H, K, l + 1, true);
+    else
+      vcycle_fused<MODEL, T, CORR>(H, K, l + 1, true);
+    if (K.nu2 > 0) {
+      const bool norm = l == 0;
+      const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
+      if (norm) K.norm_partials = blocks;
+    } else {
+      // no post-sweep to carry the prolongation: the per-level kernel applies it
+      Lvl<T> F = L;
+      for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
+      const dim3 b = block2(F.n, F.n);
+      k_prolong<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.L[l + 1], H.P);
+    }
+    if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.ny);
+  }
+}
+
 // One V-cycle from the finest level.
 template <int MODEL, typename T, bool CORR> void vcycle(Hier<T>& H, Cycle& K) {
   K.norm_partials = 0;
+  if constexpr (!CORR && !walls(MODEL)) {
+    if (H.fuse_tail >= 1) {
+      vcycle_fused<MODEL, T, CORR>(H, K, 0, false);
+      return;
+    }
+  }
   vcycle_rec<MODEL, T, CORR>(H, K, 0);
 }
 

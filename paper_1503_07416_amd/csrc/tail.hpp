@@ -22,6 +22,8 @@ template <typename T> struct TailArgs {
   int top_n;         // size of the tail top
   int nu1, nu2, coarse_sweeps;
   int d_from;        // levels l >= d_from keep the residual scratch d in LDS, the others in global memory
+  int fc;            // 1: the top level's right-hand side is still R d (in its global d); the kernel
+                     // completes f = N(g) + R d after loading g = R g (the fused FP64 restriction)
 };
 
 // T values of LDS per level l of nt (size n): g, f, the NR frozen
@@ -256,6 +258,28 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
   __syncthreads();
 }
 
+// The top level's right-hand side completed in LDS: f (loaded from the
+// global d, R d) += N(g) of the loaded iterate (R g), the coarse right-hand
+// side of tail_restrict formed for the tail's top.
+template <int MODEL, typename T, bool CORR>
+__device__ __forceinline__ void tail_complete_rhs(const Lvl<T> F, const Phys<T>& P, T* sm) {
+  constexpr int NCm = NC<MODEL>::value;
+  constexpr bool PM = tail_pm<MODEL>() > 0;
+  const int cnt = F.n * F.ny;
+  if constexpr (PM) {
+    for (int w = threadIdx.x; w < cnt; w += blockDim.x) sm[w] = potential_any<MODEL, T, CORR>(F.g, F.bg, w, P);
+    __syncthreads();
+  }
+  for (int w = threadIdx.x; w < cnt; w += blockDim.x) {
+    const Nbr q = nbr_of<MODEL>(w & (F.n - 1), w >> F.lg, F.n, F.lg);
+    T nv[NCm];
+    rows_any<MODEL, T, CORR, PM>(F.g, F.bg, F.rk, F.om, q, q.p, F.k, P, nv, sm);
+#pragma unroll
+    for (int c = 0; c < NCm; ++c) F.f[c][w] = F.f[c][w] + nv[c];
+  }
+  __syncthreads();
+}
+
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, const Phys<T>& P) {
   // channel: the interior fine rows take the correction (the coarse wall rows
@@ -327,7 +351,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
 #pragma unroll
         for (int c = 0; c < NCm; ++c) {
           x[2 + c] = g.g[c][w];
-          x[2 + NCm + c] = g.f[c][w];
+          x[2 + NCm + c] = A.fc ? g.d[c][w] : g.f[c][w];
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) x[2 + 2 * NCm + c] = g.bg[c][w];
@@ -348,6 +372,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
     }
   }
   __syncthreads();
+  if constexpr (!walls(MODEL)) {
+    if (A.fc) tail_complete_rhs<MODEL, T, CORR>(tail_view<NCm, NB, NR, false>(S[0]), P, sm);
+  }
   const int last = A.nt - 1;
   for (int l = 0; l < last; ++l) {
     const Lvl<T> F = tail_view<NCm, NB, NR, false>(S[l]);

@@ -14,8 +14,15 @@
 // CORR = true runs the same kernel on the correction form of the
 // mixed-precision inner solve (stencil.hpp); the base state is then staged
 // in LDS beside the iterate.
+//
+// The FP64 V-cycle folds the FAS restriction into these launches (FC and
+// RES = 3 below): the last pre-smoothing launch of a level also forms R g and
+// R d on the coarse nodes under its block, and the first launch on the coarse
+// level completes the coarse right-hand side f_c = N_c(R g) + R d in LDS as it
+// loads its tile.  The arithmetic is the restriction kernels' (restrict.hpp).
 #pragma once
 #include "kernels.hpp"
+#include "restrict.hpp"
 #include "stencil.hpp"
 
 namespace hfz {
@@ -40,12 +47,19 @@ template <typename T> struct Fld {
 
 // RES selects what follows the sweeps on the owned block: 0 nothing, 1 the
 // residual d = f - N(g) written to L.d (the input of the FAS restriction),
-// 2 the block's partial sum of |d|^2 written to partial[block] (the stop test).
-// A residual needs the swept values one node beyond the block, hence the
-// extra halo node.
+// 2 the block's partial sum of |d|^2 written to partial[block] (the stop test),
+// 3 the FAS restriction of the block: R g into the coarse C.g and C.g0 and
+// R d into C.d (the coarse level's first launch adds N_c(R g) to it).  A
+// residual needs the swept values one node beyond the block, hence the
+// extra halo node; R d needs d one node below and left of the block as well,
+// hence two for RES = 3.
+// FC: the level's right-hand side is still R d (in L.d, from the restriction
+// of the finer level); the launch loads it with the tile, adds N(g) of the
+// loaded iterate (which is R g) to complete f = N(R g) + R d in LDS, sweeps
+// with it, and writes f of the owned block to L.f.
 // res_on false skips the residual (a batched launch whose instance has this
 // level below its finest; uniform over the workgroup).
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0, bool FC = false>
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
                                                  const Lvl<T>& C, const Phys<T>& P, double* partial,
                                                  bool res_on = true) {
@@ -53,7 +67,8 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
   constexpr int TILE_X = kTileShapes[TS].tx, TILE_Y = kTileShapes[TS].ty, TILE_THREADS = kTileShapes[TS].nt;
-  constexpr int H = 2 * NSW + (RES ? 1 : 0);
+  static_assert(!((FC || RES == 3) && (CORR || walls(MODEL) || PRO)), "fused restriction: FP64 periodic pre-sweeps");
+  constexpr int H = 2 * NSW + (RES == 3 ? 2 : (RES ? 1 : 0));
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2, CRN = CRX * CRY;
@@ -71,6 +86,12 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
+  // FC: the right-hand side and omega^k of the region; RES = 3: d on the
+  // block and one node below and left of it
+  __shared__ T sf[NCm][FC ? RN : 1];
+  __shared__ T som[FC && RK ? RN : 1];
+  constexpr int DX = TILE_X + 1, DN = DX * (TILE_Y + 1);
+  __shared__ T sd[NCm][RES == 3 ? DN : 1];
   // se (the coarse correction, read only while loading) and sm (the
   // potential, written only after the load) share one LDS array
   constexpr int SE = PRO ? NCm * CRN : 0, SM = PM ? RN : 0;
@@ -108,6 +129,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
     const int gp = (gj << lg) + gi;
     if constexpr (RK) srk[w] = L.rk[gp];
+    if constexpr (FC) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) sf[c][w] = L.d[c][gp];
+      if constexpr (RK) som[w] = L.om[gp];
+    }
     if constexpr (CORR) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) sb[c][w] = L.bg[c][gp];
@@ -163,6 +189,35 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   const T* bl[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
+  // the right-hand side and omega^k the rows read: from LDS (FC, index in the
+  // region) or global memory (index in the grid)
+  const T* fl[NCm];
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) fl[c] = FC ? sf[c] : L.f[c];
+  const T* oml = (FC && RK) ? som : L.om;
+  if constexpr (FC) {
+    // f = R d + N(R g) on the region without its outer ring (the nodes the
+    // first half sweep may update); the loaded iterate is R g
+    if constexpr (PM) {
+      for (int w = threadIdx.x; w < RN; w += TILE_THREADS) sm[w] = potential_any<MODEL, T, CORR>(gl, bl, w, P);
+      __syncthreads();
+    }
+    constexpr int IX = RX - 2, IN = IX * (RY - 2);
+    for (int w = threadIdx.x; w < IN; w += TILE_THREADS) {
+      const int r = w / IX, t = w - r * IX;
+      Nbr q;
+      q.p = (r + 1) * RX + t + 1;
+      q.e = q.p + 1;
+      q.w = q.p - 1;
+      q.n = q.p + RX;
+      q.s = q.p - RX;
+      T nv[NCm];
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, q.p, L.k, P, nv, sm);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) sf[c][q.p] = sf[c][q.p] + nv[c];
+    }
+    __syncthreads();
+  }
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
     if constexpr (PM) {
@@ -192,9 +247,9 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.w = q.p - 1;
       q.n = q.p + RX;
       q.s = q.p - RX;
-      const int pf = ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
+      const int pf = FC ? q.p : ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
       T out[NCm];
-      update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
+      update_any<MODEL, T, CORR, PM>(gl, fl, bl, srk, oml, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
       if constexpr (WL) {
@@ -213,11 +268,12 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   }
   if constexpr (PM && RES != 0) {
     if (res_on) {
-      // M on the owned block and its one-node ring, for the residual rows
-      constexpr int BX = TILE_X + 2, BN = BX * (TILE_Y + 2);
+      // M on the nodes the residual rows read: the owned block and its
+      // one-node ring (RES = 3: the block of d and its ring)
+      constexpr int E0 = RES == 3 ? 2 : 1, BX = TILE_X + E0 + 1, BN = BX * (TILE_Y + E0 + 1);
       for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
         const int r = w / BX, t = w - r * BX;
-        const int lp = (H - 1 + r) * RX + H - 1 + t;
+        const int lp = (H - E0 + r) * RX + H - E0 + t;
         sm[lp] = potential_any<MODEL, T, CORR>(gl, bl, lp, P);
       }
       __syncthreads();
@@ -231,6 +287,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     const int gp = (gy << lg) + ((x0 + H + tx) & m);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) gout.c[c][gp] = sg[c][lp];
+    if constexpr (FC) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) L.f[c][gp] = sf[c][lp];
+    }
     if constexpr (WL) {
       // the top wall row n belongs to no block: the block owning row n - 1 writes it
       if (gy == nn - 1) {
@@ -239,7 +299,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       }
       if (gy == 0) continue;  // the bottom wall row: no equation
     }
-    if constexpr (RES != 0) {
+    if constexpr (RES == 1 || RES == 2) {
       if (!res_on) continue;
       Nbr q;
       q.p = lp;
@@ -247,11 +307,12 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.w = lp - 1;
       q.n = lp + RX;
       q.s = lp - RX;
+      const int fi = FC ? lp : gp;
       T nv[NCm];
-      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, fi, L.k, P, nv, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) {
-        const T d = L.f[c][gp] - nv[c];
+        const T d = fl[c][fi] - nv[c];
         if constexpr (RES == 1) {
           L.d[c][gp] = d;
         } else {
@@ -267,13 +328,50 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
     }
   }
+  if constexpr (RES == 3) {
+    // d = f - N(g) on the block and one node below and left of it (the fine
+    // nodes under the 9-point stencils of the block's coarse nodes)
+    for (int w = threadIdx.x; w < DN; w += TILE_THREADS) {
+      const int r = w / DX, t = w - r * DX;
+      const int lp = (H - 1 + r) * RX + H - 1 + t;
+      const int gp = (((y0 + H - 1 + r) & m) << lg) + ((x0 + H - 1 + t) & m);
+      Nbr q;
+      q.p = lp;
+      q.e = lp + 1;
+      q.w = lp - 1;
+      q.n = lp + RX;
+      q.s = lp - RX;
+      const int fi = FC ? lp : gp;
+      T nv[NCm];
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, fi, L.k, P, nv, sm);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) sd[c][w] = fl[c][fi] - nv[c];
+    }
+    __syncthreads();
+    // the block's coarse nodes: R g into C.g and C.g0, R d into C.d
+    constexpr int CX = TILE_X / 2, CN = CX * (TILE_Y / 2);
+    const int I0 = (int)blockIdx.x * CX, J0 = (int)blockIdx.y * (TILE_Y / 2);
+    for (int w = threadIdx.x; w < CN; w += TILE_THREADS) {
+      const int cy = w / CX, cx = w - cy * CX;
+      const int pc = ((J0 + cy) << C.lg) + I0 + cx;
+      const int lg2 = (H + 2 * cy) * RX + H + 2 * cx;
+      const int ld2 = (2 * cy + 1) * DX + 2 * cx + 1;
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) {
+        const T gr = fw9l(sg[c], lg2, RX);
+        C.g[c][pc] = gr;
+        C.g0[c][pc] = gr;
+        C.d[c][pc] = fw9l(sd[c], ld2, DX);
+      }
+    }
+  }
 }
 
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0, bool FC = false>
 __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
                                                                     Phys<T> P, double* partial) {
   if (halted(P.halt)) return;
-  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS, FC>(L, gin, gout, C, P, partial);
 }
 
 // Batched form: instance blockIdx.z of the instances that have a level of this
