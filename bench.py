@@ -14,6 +14,8 @@ Also reported on the same JSON line:
   cpu_baseline  the CPU oracle (NumPy FP64) on a bounded sample;
   mixed         the same workload with FP32 smoothing inside FP64 defect
                 correction: steps/s and its distance from the FP64 result;
+  precision_sweep  FP64 against mixed precision on the same law at 512^2,
+                1024^2 and 2048^2 (steps/s, V-cycles, time per V-cycle);
   batched       256 PFC instances (eps = 0.4, n ~ U{64,128,256}, 20 steps,
                 mixed precision) in one batch: instance-steps/s against the
                 unbatched FP64 path, and the per-step energy check;
@@ -80,6 +82,8 @@ def parse():
     ap.add_argument("--serve-hbm-frac", type=float, default=0.8,
                     help="serving budget as a fraction of the device memory")
     ap.add_argument("--serving-only", action="store_true", help="only the serving workload")
+    ap.add_argument("--precision-sweep-only", action="store_true",
+                    help="only FP64 against mixed precision at 512^2, 1024^2, 2048^2")
     ap.add_argument("--cdft-only", action="store_true", help="only the CDFT 1024^2 workload (for profiles)")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision PFC workload (for profiles)")
     ap.add_argument("--batched-only", action="store_true", help="only the batched workload (for profiles)")
@@ -311,6 +315,38 @@ def run_mixed(a, ref_state):
             "outer_cycles_per_step": round(st.cycles_total / max(1, st.steps_done), 3),
             "max_rel_diff_vs_fp64": rel_diff(sim.get_state(), ref_state),
             "energy_decreased": bool(E[1] <= E[0]), "tol": 1e-10}
+
+
+def run_precision_sweep(sizes=(512, 1024, 2048), steps=5, warmup=2):
+    """The headline law (PFC, h = 0.25, s = 0.01, coarsest 32^2, tol 1e-10) at
+    growing grid sizes in FP64 and in mixed precision: where the V-cycle is
+    bound by latency (the coarse levels) the FP32 inner solve gains little,
+    where it is bound by bandwidth it moves half the bytes."""
+    import torch
+    import workloads
+    import paper_1503_07416_amd as pkg
+    out = {}
+    for n in sizes:
+        row = {}
+        for prec in ("fp64", "mixed"):
+            cfg, rho, u, v = workloads.config2(0, precision=prec, n=n)
+            sim = pkg.Simulation(cfg, device="cuda:0")
+            sim.set_state(rho, u, v)
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[prec] = {"steps_per_s": round(steps / dt, 3),
+                         "cycles_per_step": round(st.cycles_total / steps, 3),
+                         "us_per_cycle": round(1e6 * dt / max(1, st.cycles_total), 2)}
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        row["mixed_over_fp64"] = round(row["mixed"]["steps_per_s"] / row["fp64"]["steps_per_s"], 3)
+        out[str(n)] = row
+    return out
 
 
 def run_batched(steps=20, count=256):
@@ -721,6 +757,9 @@ def main():
     if a.batched_only:
         print(json.dumps({"batched": run_batched()}))
         return
+    if a.precision_sweep_only:
+        print(json.dumps({"precision_sweep": run_precision_sweep()}))
+        return
     if a.serving_only:
         print(json.dumps({"serving": run_serving(a.serve_requests, a.serve_hbm_frac)}))
         return
@@ -790,6 +829,8 @@ def main():
         sim.close()
         out["mixed"] = run_mixed(a, state)
         del state
+        torch.cuda.empty_cache()
+        out["precision_sweep"] = run_precision_sweep()
         torch.cuda.empty_cache()
         out["batched"] = run_batched()
         torch.cuda.empty_cache()

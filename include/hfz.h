@@ -74,8 +74,9 @@
  *                         channel always use the tiled kernels)
  *    HFZ_TAIL_N=<n>       largest level of the one-workgroup tail (0: none)
  *    HFZ_GRAPH=0          no HIP graph capture of the V-cycle
- *    HFZ_FUSE=0           FP64 V-cycle: separate FAS restriction launches instead
- *                         of the restriction folded into the sweep launches
+ *    HFZ_FUSE=<0|1>       FAS restriction as a launch of its own (0) or folded
+ *                         into the last pre-sweep launch of a level (1) on every
+ *                         level where it can be (default: timed per level)
  *    HFZ_MP_INNER=<1..8>  FP32 V-cycles per outer FP64 iteration (mixed)
  *    HFZ_BATCH_TILE=<0|2> tile shape of the batched smoother
  *    HFZ3_TILES=<n>       smallest 3D level swept by the tiled kernel (0: none)

@@ -25,8 +25,7 @@ template <typename T> struct Hier {
   std::vector<int> tile_shape;      // tile shape of the sweep kernel per level (tile.hpp)
   std::vector<int> restrict_shape;  // restriction variant per fine level (restrict.hpp)
   std::vector<int> sweep_fuse;      // sweeps per tiled launch per level (2 fused, or 1)
-  int fuse_tail = -1;  // >= 1: the FP64 V-cycle folds the FAS restriction into the sweep launches and
-                       // the tail starts at this level; -1: separate restriction launches
+  std::vector<char> fused;          // per level: the FAS restriction folded into the pre-sweep launch
   Phys<T> P{};
 };
 
@@ -102,12 +101,19 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
 }
 
 // Launches the tiled sweep kernel of shape ts on level L; returns its
-// number of workgroups (= stop-test partial sums when res == 2).
+// number of workgroups (= stop-test partial sums when res == 2).  res 3 (the
+// restriction into C folded in) only without PRO and walls.
 template <int MODEL, typename T, bool CORR, int NSW, bool PRO, int TS>
 int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
                       const Lvl<T>& C, int res) {
   constexpr TileShape S = kTileShapes[TS];
   const dim3 grid(L.n / S.tx, L.n / S.ty);
+  if constexpr (!PRO && !walls(MODEL)) {
+    if (res == 3) {
+      k_sweeps_tile<MODEL, T, NSW, false, 3, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+      return (int)(grid.x * grid.y);
+    }
+  }
   if (res == 1)
     k_sweeps_tile<MODEL, T, NSW, PRO, 1, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
   else if (res == 2)
@@ -186,77 +192,30 @@ int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur,
   return blocks;  // workgroups of the last launch
 }
 
-// The pre-sweep launches of the fused restriction: fc completes the level's
-// right-hand side at load (first launch), res 3 restricts (last launch).
-template <int MODEL, typename T, bool CORR, int NSW, int TS, bool FC>
-int tile_launch_fused_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
-                            const Lvl<T>& C, int res) {
-  constexpr TileShape S = kTileShapes[TS];
-  const dim3 grid(L.n / S.tx, L.n / S.ty);
-  if (res == 3)
-    k_sweeps_tile<MODEL, T, NSW, false, 3, CORR, TS, FC><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
-  else
-    k_sweeps_tile<MODEL, T, NSW, false, 0, CORR, TS, FC><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
-  return (int)(grid.x * grid.y);
-}
-
-template <int MODEL, typename T, bool CORR, int NSW>
-void tile_launch_fused(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
-                       const Lvl<T>& C, int res, int ts, bool fc) {
-  if (!tile_shape_fits(ts, L.n)) ts = 0;
-  if (fc && ts == 2) ts = 1;  // 64x16 tiles with f and omega^k in LDS would exceed a CU's LDS
-  if (fc) {
-    switch (ts) {
-      case 1: tile_launch_fused_shape<MODEL, T, CORR, NSW, 1, true>(H, K, L, in, out, C, res); return;
-      case 3: tile_launch_fused_shape<MODEL, T, CORR, NSW, 3, true>(H, K, L, in, out, C, res); return;
-      default: tile_launch_fused_shape<MODEL, T, CORR, NSW, 0, true>(H, K, L, in, out, C, res); return;
-    }
-  }
-  switch (ts) {
-    case 1: tile_launch_fused_shape<MODEL, T, CORR, NSW, 1, false>(H, K, L, in, out, C, res); return;
-    case 2: tile_launch_fused_shape<MODEL, T, CORR, NSW, 2, false>(H, K, L, in, out, C, res); return;
-    case 3: tile_launch_fused_shape<MODEL, T, CORR, NSW, 3, false>(H, K, L, in, out, C, res); return;
-    default: tile_launch_fused_shape<MODEL, T, CORR, NSW, 0, false>(H, K, L, in, out, C, res); return;
-  }
-}
-
-// The pre-sweeps of level l with the fused restriction (nu1 >= 1): the first
-// launch completes the right-hand side when fc is set, the last forms the
-// coarse level's R g and R d.
-template <int MODEL, typename T, bool CORR>
-void presweeps_fused(Hier<T>& H, Cycle& K, int l, bool fc, Fld<T>& cur, Fld<T>& other) {
-  const Lvl<T>& L = H.L[l];
-  const Lvl<T>& C = H.L[l + 1];
-  const int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
-  const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
-  int sweeps = K.nu1;
-  bool first = true;
-  while (sweeps > 0) {
-    const int nsw = (sweeps >= 2 && fuse >= 2) ? 2 : 1;
-    const int res = (sweeps == nsw) ? 3 : 0;
-    const bool f = first && fc;
-    if (!f && res == 0) {
-      if (nsw == 2)
-        tile_launch<MODEL, T, CORR, 2, false>(H, K, L, cur, other, C, 0, ts);
-      else
-        tile_launch<MODEL, T, CORR, 1, false>(H, K, L, cur, other, C, 0, ts);
-    } else if (nsw == 2) {
-      tile_launch_fused<MODEL, T, CORR, 2>(H, K, L, cur, other, C, res, ts, f);
-    } else {
-      tile_launch_fused<MODEL, T, CORR, 1>(H, K, L, cur, other, C, res, ts, f);
-    }
-    std::swap(cur, other);
-    sweeps -= nsw;
-    first = false;
-  }
-}
-
 template <typename T> void copy_fields(Cycle& K, const Fld<T>& a, const Fld<T>& b, int nc, size_t cnt) {
   for (int c = 0; c < nc; ++c)
     k_copy_t<T><<<(unsigned)((cnt + 255) / 256), 256, 0, K.stream>>>(a.c[c], b.c[c], cnt, K.halt);
 }
 
-template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l);
+template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l, bool fc = false);
+
+// Whether level l folds its FAS restriction into its last pre-sweep launch.
+template <typename T> bool level_fused(const Hier<T>& H, const Cycle& K, int l) {
+  return K.nu1 >= 1 && l < (int)H.fused.size() && H.fused[l];
+}
+
+// After a folded restriction from level l: f_c = R d + N_c(R g) on level
+// l + 1, by the tail kernel as it loads (returns true: the caller passes fc)
+// or by k_fas_rhs.
+template <int MODEL, typename T, bool CORR> bool complete_coarse_rhs(Hier<T>& H, Cycle& K, int l) {
+  const int c = l + 1;
+  if (H.L[c].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[c].n, (int)H.L.size() - c, H.tail_lds_max, nullptr))
+    return true;
+  const Lvl<T>& C = H.L[c];
+  const dim3 b = block2(C.n, C.n);
+  k_fas_rhs<MODEL, T, CORR><<<grid2(C.n, C.n, b), b, 0, K.stream>>>(C, H.P);
+  return false;
+}
 
 // One visit to a large level with the tiled kernels: pre-sweeps (the last also
 // writes d = f - N(g)), the fused FAS restriction, the coarser levels, the
@@ -268,17 +227,24 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
   const Lvl<T>& C = H.L[l + 1];
   const Fld<T> home = fld<T>(L.g);
   Fld<T> cur = home, other = fld<T>(L.gb);
-  tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 1);
-  Lvl<T> F = L;  // descriptor of the buffer holding the iterate
-  for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
-  if (K.nu1 == 0) {
-    if constexpr (!CORR && !walls(MODEL)) {
-      const dim3 b = block2(F.n, F.n);
-      k_residual_field<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.P);
+  bool fc = false;
+  if (level_fused(H, K, l)) {
+    // the last pre-sweep launch restricts g and d into the coarse level
+    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 3);
+    fc = complete_coarse_rhs<MODEL, T, CORR>(H, K, l);
+  } else {
+    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 1);
+    Lvl<T> F = L;  // descriptor of the buffer holding the iterate
+    for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
+    if (K.nu1 == 0) {
+      if constexpr (!CORR && !walls(MODEL)) {
+        const dim3 b = block2(F.n, F.n);
+        k_residual_field<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.P);
+      }
     }
+    restrict_launch<MODEL, T, CORR>(H, K, F, C, l < (int)H.restrict_shape.size() ? H.restrict_shape[l] : 0);
   }
-  restrict_launch<MODEL, T, CORR>(H, K, F, C, l < (int)H.restrict_shape.size() ? H.restrict_shape[l] : 0);
-  vcycle_rec<MODEL, T, CORR>(H, K, l + 1);
+  vcycle_rec<MODEL, T, CORR>(H, K, l + 1, fc);
   if (K.nu2 > 0) {
     // post-sweeps; on the finest level of the FP64 solve the last one also
     // leaves the partial sums of the stop-test residual
@@ -287,6 +253,8 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
     if (norm) K.norm_partials = blocks;
   } else {
     if constexpr (!CORR && !walls(MODEL)) {
+      Lvl<T> F = L;  // descriptor of the buffer holding the iterate
+      for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
       const dim3 b = block2(F.n, F.n);
       k_prolong<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, C, H.P);
     }
@@ -294,10 +262,10 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
   if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.ny);
 }
 
-template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l) {
+template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l, bool fc) {
   const int nlev = (int)H.L.size(), last = nlev - 1;
   if (H.L[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[l].n, nlev - l, H.tail_lds_max, nullptr)) {
-    tail_launch<MODEL, T, CORR>(H, K, l);
+    tail_launch<MODEL, T, CORR>(H, K, l, fc);
     return;
   }
   if (K.use_tiles && l < last && H.L[l].n >= TILE_X && H.L[l + 1].n >= RTILE) {
@@ -324,46 +292,9 @@ template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K
   }
 }
 
-// A visit to level l of the FP64 V-cycle with the fused restriction: the
-// pre-sweeps (fc: the first completes the level's right-hand side) end with
-// the restriction, the coarser levels (down to the tail, whose top completes
-// its right-hand side too), the prolongation fused into the first post-sweep,
-// post-sweeps.  Every value is the one the separate restriction launches give.
-template <int MODEL, typename T, bool CORR> void vcycle_fused(Hier<T>& H, Cycle& K, int l, bool fc) {
-  if constexpr (!CORR && !walls(MODEL)) {
-    constexpr int NCm = NC<MODEL>::value;
-    const Lvl<T>& L = H.L[l];
-    const Fld<T> home = fld<T>(L.g);
-    Fld<T> cur = home, other = fld<T>(L.gb);
-    presweeps_fused<MODEL, T, CORR>(H, K, l, fc, cur, other);
-    if (l + 1 == H.fuse_tail)
-      tail_launch<MODEL, T, CORR>(H, K, l + 1, true);
-    else
-      vcycle_fused<MODEL, T, CORR>(H, K, l + 1, true);
-    if (K.nu2 > 0) {
-      const bool norm = l == 0;
-      const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
-      if (norm) K.norm_partials = blocks;
-    } else {
-      // no post-sweep to carry the prolongation: the per-level kernel applies it
-      Lvl<T> F = L;
-      for (int c = 0; c < 5; ++c) F.g[c] = cur.c[c];
-      const dim3 b = block2(F.n, F.n);
-      k_prolong<MODEL, T><<<grid2(F.n, F.n, b), b, 0, K.stream>>>(F, H.L[l + 1], H.P);
-    }
-    if (cur.c[0] != home.c[0]) copy_fields<T>(K, cur, home, NCm, (size_t)L.n * L.ny);
-  }
-}
-
 // One V-cycle from the finest level.
 template <int MODEL, typename T, bool CORR> void vcycle(Hier<T>& H, Cycle& K) {
   K.norm_partials = 0;
-  if constexpr (!CORR && !walls(MODEL)) {
-    if (H.fuse_tail >= 1) {
-      vcycle_fused<MODEL, T, CORR>(H, K, 0, false);
-      return;
-    }
-  }
   vcycle_rec<MODEL, T, CORR>(H, K, 0);
 }
 

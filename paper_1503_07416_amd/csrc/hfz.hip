@@ -248,7 +248,7 @@ size_t layout(const hfz_params& p, void* ws, hfz_handle* hd) {
       for (int k = 0; k < nc; ++k) l.g[k] = c.take<float>(cnt);
       for (int k = 0; k < nc; ++k) l.f[k] = c.take<float>(cnt);
       for (int k = 0; k < nc; ++k) l.g0[k] = c.take<float>(cnt);
-      if (m > p.coarsest_n)
+      if (m > p.coarsest_n || m != n)
         for (int k = 0; k < nc; ++k) l.d[k] = c.take<float>(cnt);
       if (m >= TILE_X && m > p.coarsest_n)
         for (int k = 0; k < nc; ++k) l.gb[k] = c.take<float>(cnt);
@@ -781,35 +781,17 @@ int init_handle(hfz_handle* hd, const hfz_params& p, void* dev_ws, void* hip_str
       if (p.precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K, !by_kernel);
     });
   }
-  // the FP64 V-cycle folds the FAS restriction into the sweep launches where
-  // every level above the tail is tiled and the tail holds the rest
-  // (HFZ_FUSE=0: separate restriction launches)
-  hd->H.fuse_tail = -1;
-  {
-    bool want = hd->use_tiles && !p.walls && p.nu1 >= 1;
-    if (const char* e = std::getenv("HFZ_FUSE")) want = want && std::atoi(e) != 0;
-    int t = -1;
-    for (int l = 0; l < hd->nlev && want; ++l)
-      if (hd->H.L[l].n <= hd->tail_n) {
-        t = l;
-        break;
-      }
-    bool ok = want && t >= 1 && by_model(hd->km, [&](auto m) {
-      return tail_plan<decltype(m)::value, double, false>(hd->H.L[t].n, hd->nlev - t, hd->H.tail_lds_max, nullptr);
-    });
-    for (int l = 0; ok && l < t; ++l)
-      ok = hd->H.L[l].n >= TILE_X && hd->H.L[l + 1].n >= RTILE && hd->H.L[l].gb[0] && hd->H.L[l + 1].d[0];
-    if (ok) hd->H.fuse_tail = t;
-  }
   if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));
   if (std::getenv("HFZ_VERBOSE")) {
-    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d fused restriction to level %d, tile shapes:",
-                 p.n, hd->nlev, hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph, hd->H.fuse_tail);
+    std::fprintf(stderr, "hfz: n=%d levels=%d tail_n=%d tail_lds_max=%zu graph=%d tile shapes:", p.n, hd->nlev,
+                 hd->tail_n, hd->H.tail_lds_max, (int)hd->use_graph);
     for (size_t l = 0; l < hd->H.tile_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.tile_shape[l]);
     std::fprintf(stderr, " restriction:");
     for (size_t l = 0; l < hd->H.restrict_shape.size(); ++l) std::fprintf(stderr, " %d", hd->H.restrict_shape[l]);
     std::fprintf(stderr, " sweeps/launch:");
     for (size_t l = 0; l < hd->H.sweep_fuse.size(); ++l) std::fprintf(stderr, " %d", hd->H.sweep_fuse[l]);
+    std::fprintf(stderr, " restriction folded:");
+    for (size_t l = 0; l < hd->H.fused.size(); ++l) std::fprintf(stderr, " %d", (int)hd->H.fused[l]);
     for (size_t l = 0; l < hd->H32.tile_shape.size(); ++l) std::fprintf(stderr, "%s%d", l ? " " : " | ", hd->H32.tile_shape[l]);
     std::fprintf(stderr, "\n");
   }

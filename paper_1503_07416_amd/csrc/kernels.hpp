@@ -174,8 +174,9 @@ __global__ void k_restrict_gd(Lvl<T> F, Lvl<T> C, const int* halt) {
   }
 }
 
-// K6b: f_c += N_c(R g), the FAS coarse right-hand side.
-template <int MODEL, typename T>
+// K6b: f_c += N_c(R g), the FAS coarse right-hand side (C.f holds R d; the
+// correction form evaluates N_d about the restricted base C.bg).
+template <int MODEL, typename T, bool CORR = false>
 __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
   if (halted(P.halt)) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,7 +185,7 @@ __global__ void k_fas_rhs(Lvl<T> C, Phys<T> P) {
   constexpr int NCm = NC<MODEL>::value;
   const Nbr q = nbr(I, J, C.n, C.lg);
   T nv[NCm];
-  rows_N<MODEL, T>(C.g0, C.rk, C.om, q, q.p, C.k, P, nv);
+  rows_any<MODEL, T, CORR>(C.g0, C.bg, C.rk, C.om, q, q.p, C.k, P, nv);
 #pragma unroll
   for (int c = 0; c < NCm; ++c) C.f[c][q.p] += nv[c];
 }

@@ -22,8 +22,8 @@ template <typename T> struct TailArgs {
   int top_n;         // size of the tail top
   int nu1, nu2, coarse_sweeps;
   int d_from;        // levels l >= d_from keep the residual scratch d in LDS, the others in global memory
-  int fc;            // 1: the top level's right-hand side is still R d (in its global d); the kernel
-                     // completes f = N(g) + R d after loading g = R g (the fused FP64 restriction)
+  int fc;            // 1: the top level's right-hand side is still R d; the kernel completes
+                     // f = R d + N(g) after loading g = R g (the restriction folded into the sweeps)
 };
 
 // T values of LDS per level l of nt (size n): g, f, the NR frozen
@@ -258,9 +258,9 @@ __device__ __forceinline__ void tail_restrict(const Lvl<T> F, const Lvl<T> C, co
   __syncthreads();
 }
 
-// The top level's right-hand side completed in LDS: f (loaded from the
-// global d, R d) += N(g) of the loaded iterate (R g), the coarse right-hand
-// side of tail_restrict formed for the tail's top.
+// The top level's right-hand side completed in LDS: f (loaded: R d) +=
+// N(g) of the loaded iterate (R g), the coarse right-hand side of
+// tail_restrict formed for the tail's top.
 template <int MODEL, typename T, bool CORR>
 __device__ __forceinline__ void tail_complete_rhs(const Lvl<T> F, const Phys<T>& P, T* sm) {
   constexpr int NCm = NC<MODEL>::value;
@@ -351,7 +351,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
 #pragma unroll
         for (int c = 0; c < NCm; ++c) {
           x[2 + c] = g.g[c][w];
-          x[2 + NCm + c] = A.fc ? g.d[c][w] : g.f[c][w];
+          x[2 + NCm + c] = g.f[c][w];
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) x[2 + 2 * NCm + c] = g.bg[c][w];

@@ -15,11 +15,11 @@
 // mixed-precision inner solve (stencil.hpp); the base state is then staged
 // in LDS beside the iterate.
 //
-// The FP64 V-cycle folds the FAS restriction into these launches (FC and
-// RES = 3 below): the last pre-smoothing launch of a level also forms R g and
-// R d on the coarse nodes under its block, and the first launch on the coarse
-// level completes the coarse right-hand side f_c = N_c(R g) + R d in LDS as it
-// loads its tile.  The arithmetic is the restriction kernels' (restrict.hpp).
+// The V-cycle can fold the FAS restriction into these launches (RES = 3
+// below): the last pre-smoothing launch of a level also forms R g and R d on
+// the coarse nodes under its block; f_c = R d + N_c(R g) is then completed
+// on the coarse grid (k_fas_rhs, or the tail kernel as it loads).  The
+// arithmetic is the restriction kernels' (restrict.hpp).
 #pragma once
 #include "kernels.hpp"
 #include "restrict.hpp"
@@ -49,17 +49,14 @@ template <typename T> struct Fld {
 // residual d = f - N(g) written to L.d (the input of the FAS restriction),
 // 2 the block's partial sum of |d|^2 written to partial[block] (the stop test),
 // 3 the FAS restriction of the block: R g into the coarse C.g and C.g0 and
-// R d into C.d (the coarse level's first launch adds N_c(R g) to it).  A
-// residual needs the swept values one node beyond the block, hence the
-// extra halo node; R d needs d one node below and left of the block as well,
-// hence two for RES = 3.
-// FC: the level's right-hand side is still R d (in L.d, from the restriction
-// of the finer level); the launch loads it with the tile, adds N(g) of the
-// loaded iterate (which is R g) to complete f = N(R g) + R d in LDS, sweeps
-// with it, and writes f of the owned block to L.f.
+// R d into C.f (to which N_c(R g) is added on the coarse grid afterwards; the
+// correction form also restricts its base state into C.bg).  A residual
+// needs the swept values one node beyond the block, hence the extra halo
+// node; R d needs d one node below and left of the block as well, hence two
+// for RES = 3.
 // res_on false skips the residual (a batched launch whose instance has this
 // level below its finest; uniform over the workgroup).
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0, bool FC = false>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
                                                  const Lvl<T>& C, const Phys<T>& P, double* partial,
                                                  bool res_on = true) {
@@ -67,7 +64,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
   constexpr int TILE_X = kTileShapes[TS].tx, TILE_Y = kTileShapes[TS].ty, TILE_THREADS = kTileShapes[TS].nt;
-  static_assert(!((FC || RES == 3) && (CORR || walls(MODEL) || PRO)), "fused restriction: FP64 periodic pre-sweeps");
+  static_assert(!(RES == 3 && (walls(MODEL) || PRO)), "fused restriction: periodic pre-sweeps");
   constexpr int H = 2 * NSW + (RES == 3 ? 2 : (RES ? 1 : 0));
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
@@ -86,10 +83,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   __shared__ T sg[NCm][RN];
   __shared__ T srk[RK ? RN : 1];
   __shared__ T sb[NB][CORR ? RN : 1];
-  // FC: the right-hand side and omega^k of the region; RES = 3: d on the
-  // block and one node below and left of it
-  __shared__ T sf[NCm][FC ? RN : 1];
-  __shared__ T som[FC && RK ? RN : 1];
+  // RES = 3: d on the block and one node below and left of it
   constexpr int DX = TILE_X + 1, DN = DX * (TILE_Y + 1);
   __shared__ T sd[NCm][RES == 3 ? DN : 1];
   // se (the coarse correction, read only while loading) and sm (the
@@ -129,11 +123,6 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
     const int gp = (gj << lg) + gi;
     if constexpr (RK) srk[w] = L.rk[gp];
-    if constexpr (FC) {
-#pragma unroll
-      for (int c = 0; c < NCm; ++c) sf[c][w] = L.d[c][gp];
-      if constexpr (RK) som[w] = L.om[gp];
-    }
     if constexpr (CORR) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) sb[c][w] = L.bg[c][gp];
@@ -189,35 +178,6 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   const T* bl[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
-  // the right-hand side and omega^k the rows read: from LDS (FC, index in the
-  // region) or global memory (index in the grid)
-  const T* fl[NCm];
-#pragma unroll
-  for (int c = 0; c < NCm; ++c) fl[c] = FC ? sf[c] : L.f[c];
-  const T* oml = (FC && RK) ? som : L.om;
-  if constexpr (FC) {
-    // f = R d + N(R g) on the region without its outer ring (the nodes the
-    // first half sweep may update); the loaded iterate is R g
-    if constexpr (PM) {
-      for (int w = threadIdx.x; w < RN; w += TILE_THREADS) sm[w] = potential_any<MODEL, T, CORR>(gl, bl, w, P);
-      __syncthreads();
-    }
-    constexpr int IX = RX - 2, IN = IX * (RY - 2);
-    for (int w = threadIdx.x; w < IN; w += TILE_THREADS) {
-      const int r = w / IX, t = w - r * IX;
-      Nbr q;
-      q.p = (r + 1) * RX + t + 1;
-      q.e = q.p + 1;
-      q.w = q.p - 1;
-      q.n = q.p + RX;
-      q.s = q.p - RX;
-      T nv[NCm];
-      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, q.p, L.k, P, nv, sm);
-#pragma unroll
-      for (int c = 0; c < NCm; ++c) sf[c][q.p] = sf[c][q.p] + nv[c];
-    }
-    __syncthreads();
-  }
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
     if constexpr (PM) {
@@ -247,9 +207,9 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.w = q.p - 1;
       q.n = q.p + RX;
       q.s = q.p - RX;
-      const int pf = FC ? q.p : ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
+      const int pf = ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
       T out[NCm];
-      update_any<MODEL, T, CORR, PM>(gl, fl, bl, srk, oml, q, pf, L.k, P, out, sm);
+      update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
       if constexpr (WL) {
@@ -287,10 +247,6 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     const int gp = (gy << lg) + ((x0 + H + tx) & m);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) gout.c[c][gp] = sg[c][lp];
-    if constexpr (FC) {
-#pragma unroll
-      for (int c = 0; c < NCm; ++c) L.f[c][gp] = sf[c][lp];
-    }
     if constexpr (WL) {
       // the top wall row n belongs to no block: the block owning row n - 1 writes it
       if (gy == nn - 1) {
@@ -307,12 +263,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.w = lp - 1;
       q.n = lp + RX;
       q.s = lp - RX;
-      const int fi = FC ? lp : gp;
       T nv[NCm];
-      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, fi, L.k, P, nv, sm);
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) {
-        const T d = fl[c][fi] - nv[c];
+        const T d = L.f[c][gp] - nv[c];
         if constexpr (RES == 1) {
           L.d[c][gp] = d;
         } else {
@@ -341,14 +296,13 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.w = lp - 1;
       q.n = lp + RX;
       q.s = lp - RX;
-      const int fi = FC ? lp : gp;
       T nv[NCm];
-      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, oml, q, fi, L.k, P, nv, sm);
+      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
 #pragma unroll
-      for (int c = 0; c < NCm; ++c) sd[c][w] = fl[c][fi] - nv[c];
+      for (int c = 0; c < NCm; ++c) sd[c][w] = L.f[c][gp] - nv[c];
     }
     __syncthreads();
-    // the block's coarse nodes: R g into C.g and C.g0, R d into C.d
+    // the block's coarse nodes: R g into C.g and C.g0, R d into C.f
     constexpr int CX = TILE_X / 2, CN = CX * (TILE_Y / 2);
     const int I0 = (int)blockIdx.x * CX, J0 = (int)blockIdx.y * (TILE_Y / 2);
     for (int w = threadIdx.x; w < CN; w += TILE_THREADS) {
@@ -361,17 +315,22 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
         const T gr = fw9l(sg[c], lg2, RX);
         C.g[c][pc] = gr;
         C.g0[c][pc] = gr;
-        C.d[c][pc] = fw9l(sd[c], ld2, DX);
+        C.f[c][pc] = fw9l(sd[c], ld2, DX);
+      }
+      if constexpr (CORR) {
+        // the correction form's base state restricted with the iterate
+#pragma unroll
+        for (int c = 0; c < NB; ++c) C.bg[c][pc] = fw9l(sb[c], lg2, RX);
       }
     }
   }
 }
 
-template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0, bool FC = false>
+template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
                                                                     Phys<T> P, double* partial) {
   if (halted(P.halt)) return;
-  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS, FC>(L, gin, gout, C, P, partial);
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
 }
 
 // Batched form: instance blockIdx.z of the instances that have a level of this

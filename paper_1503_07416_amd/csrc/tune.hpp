@@ -33,8 +33,8 @@ inline std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
 }
-inline std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>>& tune_cache() {
-  static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>> c;
+inline std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int, int>>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int, int>> c;
   return c;
 }
 
@@ -119,6 +119,51 @@ float time_schedule(Hier<T>& H, Cycle& K, int l, int fuse, int reps) {
   return ms;
 }
 
+// Average time (ms) of `reps` pre-smoothing passes of level l (two sweeps)
+// with the FAS restriction to level l + 1 after them: folded into the sweep
+// launch (fused, with f_c completed by k_fas_rhs unless the next level is the
+// tail, whose completion costs a phase of the tail kernel) or as the
+// restriction launch of variant rs.
+template <int MODEL, typename T, bool CORR>
+float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int reps) {
+  const Lvl<T>& L = H.L[l];
+  const Lvl<T>& C = H.L[l + 1];
+  const Fld<T> a = fld<T>(L.g), b = fld<T>(L.gb);
+  const int ts = H.tile_shape[l];
+  const bool tail_next = C.n <= K.tail_n;
+  auto pass = [&]() {
+    if (fused) {
+      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 3, ts);
+      if (!tail_next) {
+        const dim3 bl = block2(C.n, C.n);
+        k_fas_rhs<MODEL, T, CORR><<<grid2(C.n, C.n, bl), bl, 0, K.stream>>>(C, H.P);
+      }
+    } else {
+      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+      Lvl<T> F = L;
+      for (int c = 0; c < 5; ++c) F.g[c] = b.c[c];
+      restrict_launch<MODEL, T, CORR>(H, K, F, C, rs);
+    }
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+    pass();
+    bool ok = hipEventRecord(e0, K.stream) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) pass();
+    ok = ok && hipEventRecord(e1, K.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipGetLastError() == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.0f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  return ms;
+}
+
 // Index of the fastest of `count` candidates timed by `time(k)` (best of
 // three rounds; a later candidate must win by 2%, so near-ties resolve the
 // same way every run); 0 if none could be timed.
@@ -141,17 +186,23 @@ template <typename F> int pick_fastest(int count, F&& time, const char* what = n
   return best;
 }
 
-// Fills H.tile_shape and H.restrict_shape for the levels the tiled V-cycle
-// visits (size >= 32 with a coarser level of >= 16, above the tail).
-// HFZ_RESTRICT=<variant> forces a restriction variant where it fits.  With
-// time_them false nothing is launched: a level takes the choices cached for
-// its size in this process, else shape 0, variant 0 and fused sweeps.
+// Fills H.tile_shape, H.restrict_shape, H.sweep_fuse and H.fused for the
+// levels the tiled V-cycle visits (size >= 32 with a coarser level of >= 16,
+// above the tail).  HFZ_RESTRICT=<variant> forces a restriction variant where
+// it fits; HFZ_FUSE=0 / 1 keeps the restriction launches separate / folds
+// them into the sweeps wherever it can (default: whichever times faster).
+// With time_them false nothing is launched: a level takes the choices cached
+// for its size in this process, else shape 0, variant 0, fused sweeps and a
+// separate restriction.
 template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cycle K, bool time_them = true) {
   const int nlev = (int)H.L.size();
   H.tile_shape.assign(nlev, 0);
   H.restrict_shape.assign(nlev, 0);
   H.sweep_fuse.assign(nlev, 2);
-  int forced_r = -1, forced_f = -1;
+  H.fused.assign(nlev, 0);
+  int forced_r = -1, forced_f = -1, forced_x = -1;
+  if (const char* e = std::getenv("HFZ_FUSE")) forced_x = std::atoi(e) != 0 ? 1 : 0;
+  if constexpr (walls(MODEL)) forced_x = 0;  // the channel's wall rows: the direct restriction kernel
   if (const char* e = std::getenv("HFZ_RESTRICT")) forced_r = std::atoi(e);
   if (const char* e = std::getenv("HFZ_SWEEPS")) forced_f = std::atoi(e) == 1 ? 1 : 2;
   int forced = -1;
@@ -165,7 +216,8 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     if (forced_r >= 0)
       H.restrict_shape[l] = (forced_r < NUM_RESTRICT_SHAPES && nc % kRestrictTile[forced_r] == 0) ? forced_r : 0;
     if (forced_f > 0) H.sweep_fuse[l] = forced_f;
-    if (!tune || n <= K.tail_n || (forced >= 0 && forced_r >= 0 && forced_f > 0)) continue;
+    if (forced_x >= 0) H.fused[l] = (char)forced_x;
+    if (!tune || n <= K.tail_n || (forced >= 0 && forced_r >= 0 && forced_f > 0 && forced_x >= 0)) continue;
     const auto key = std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, n);
     {
       std::lock_guard<std::mutex> g(tune_mutex());
@@ -174,6 +226,7 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
         if (forced < 0) H.tile_shape[l] = std::get<0>(it->second);
         if (forced_r < 0) H.restrict_shape[l] = std::get<1>(it->second);
         if (forced_f < 0) H.sweep_fuse[l] = std::get<2>(it->second);
+        if (forced_x < 0) H.fused[l] = (char)std::get<3>(it->second);
         continue;
       }
     }
@@ -191,8 +244,17 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     const int fs = pick_fastest(
         2, [&](int k) { return time_schedule<MODEL, T, CORR>(H, K, l, k == 0 ? 2 : 1, 8); }, "sweeps", n);
     if (forced_f < 0) H.sweep_fuse[l] = fs == 0 ? 2 : 1;
+    // the restriction: a launch of its own, or folded into the last pre-sweep
+    // launch (candidate 1; never for the channel)
+    int fx = 0;
+    if constexpr (!walls(MODEL)) {
+      fx = pick_fastest(
+          2, [&](int k) { return time_restriction_mode<MODEL, T, CORR>(H, K, l, k == 1, H.restrict_shape[l], 8); },
+          "restriction folded", n);
+    }
+    if (forced_x < 0) H.fused[l] = (char)fx;
     std::lock_guard<std::mutex> g(tune_mutex());
-    tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1);
+    tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1, fx);
   }
 }
 

@@ -1,10 +1,10 @@
-"""GPU: the FP64 V-cycle with the FAS restriction folded into the sweep
-launches (the last pre-smoothing launch of a level forms R g and R d; the
-coarse level's first launch, or the tail, completes f_c = N_c(R g) + R d)
-against the same V-cycle with separate restriction launches (HFZ_FUSE=0) and
-against the oracle, for every model, cycle shapes, coarsest grids, sweep
-schedules and tile shapes; and the separate restriction kernels (each
-variant) against the oracle, since the fused cycle no longer runs them."""
+"""GPU: the V-cycle with the FAS restriction folded into the sweep launches
+(HFZ_FUSE=1: the last pre-smoothing launch of every level forms R g and R d;
+f_c = R d + N_c(R g) is completed on the coarse grid by k_fas_rhs, or by the
+tail kernel as it loads) against the same V-cycle with separate restriction
+launches (HFZ_FUSE=0) and against the oracle, for every model, cycle shapes,
+coarsest grids, sweep schedules and tile shapes; and each separate
+restriction variant against the oracle."""
 import numpy as np
 import pytest
 
@@ -84,7 +84,7 @@ ENVS = [{}, {"HFZ_SWEEPS": "1"}, {"HFZ_TILE": "2"}, {"HFZ_TILE": "3"}]
 def test_fused_equals_separate_and_oracle(model, n, kw, env, monkeypatch):
     cfg, rho, u, v = case(model, n, **kw)
     print(f"fused {model} {n} {kw} {env}", flush=True)
-    fused = cycles(cfg, rho, u, v, 3, dict(env), monkeypatch)
+    fused = cycles(cfg, rho, u, v, 3, dict(env, HFZ_FUSE="1"), monkeypatch)
     sep = cycles(cfg, rho, u, v, 3, dict(env, HFZ_FUSE="0"), monkeypatch)
     for k, (a, b) in enumerate(zip(fused, sep)):
         for c, (x, y) in enumerate(zip(a, b)):
@@ -125,3 +125,28 @@ def test_fused_steps_equal_separate(model, monkeypatch):
     assert out[0][0] == out[1][0]
     for x, y in zip(out[0][1], out[1][1]):
         assert rel_err(x, y) < 1e-12
+
+
+@pytest.mark.parametrize("model", ["pfc", "cdft", "pfc_gf", "cdft_gf"])
+def test_fused_mixed_precision_steps(model, monkeypatch):
+    """Mixed precision: the FP32 correction-form inner V-cycles with the fused
+    restriction (the base state restricted along) against the separate
+    restriction launches: the same outer iteration counts (within one) and
+    final states within 1e-9, each meeting the FP64 tolerance."""
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v = case(model, 128, seed=6, precision="mixed", coarsest_n=16)
+    out = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("HFZ_FUSE", fuse)
+        sim = pkg.Simulation(cfg)
+        if cfg.gradflow:
+            sim.set_state(rho)
+        else:
+            sim.set_state(rho, u, v)
+        st = sim.step(3)
+        assert st.residual_last <= cfg.tol
+        out.append((st.cycles_total, [np_(x) for x in sim.get_state()]))
+    assert abs(out[0][0] - out[1][0]) <= 3
+    for x, y in zip(out[0][1], out[1][1]):
+        if np.abs(y).max() > 0:
+            assert rel_err(x, y) < 1e-9
