@@ -69,6 +69,8 @@
  *    HFZ_RESTRICT=<0..3>  FAS restriction variant where it fits
  *    HFZ_SWEEPS=1         one sweep per smoother launch (default: two fused)
  *    HFZ_TUNE=0           no timing: shape 0, variant 0, fused sweeps
+ *    HFZ_TUNE_CACHE=<f>   the tuner's choices read from file f when it exists and
+ *                         written to it after timing (profiled runs reuse them)
  *    HFZ_TILES=0          per-colour smoother kernels instead of the tiled one
  *                         (FP64 periodic only; mixed precision and the
  *                         channel always use the tiled kernels)

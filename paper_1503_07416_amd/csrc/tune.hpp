@@ -38,6 +38,37 @@ inline std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int, int>>&
   return c;
 }
 
+// HFZ_TUNE_CACHE=<file>: the choices are read from the file when it exists
+// (one line per level size: model, bytes per value, form, n, shape, variant,
+// sweeps per launch, restriction folded) and written to it after timing, so
+// that another process (a profiled run, whose timings the profiler distorts)
+// takes the same kernels.  Call with tune_mutex held.
+inline void tune_cache_load() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* path = std::getenv("HFZ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int k[8];
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7]) == 8)
+    tune_cache()[std::make_tuple(k[0], k[1], k[2], k[3])] = std::make_tuple(k[4], k[5], k[6], k[7]);
+  std::fclose(f);
+}
+
+inline void tune_cache_save() {
+  const char* path = std::getenv("HFZ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (const auto& kv : tune_cache())
+    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                 std::get<3>(kv.first), std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second),
+                 std::get<3>(kv.second));
+  std::fclose(f);
+}
+
 // Average time (ms) of `reps` pre-smoothing launches of shape ts on level l,
 // after one untimed launch; negative on a HIP error.
 template <int MODEL, typename T, bool CORR>
@@ -221,6 +252,7 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     const auto key = std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, n);
     {
       std::lock_guard<std::mutex> g(tune_mutex());
+      tune_cache_load();
       auto it = tune_cache().find(key);
       if (it != tune_cache().end()) {
         if (forced < 0) H.tile_shape[l] = std::get<0>(it->second);
@@ -255,6 +287,7 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     if (forced_x < 0) H.fused[l] = (char)fx;
     std::lock_guard<std::mutex> g(tune_mutex());
     tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1, fx);
+    tune_cache_save();
   }
 }
 
