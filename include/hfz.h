@@ -65,7 +65,7 @@
  * hfz_init (cached per process).  Environment variables, read at init
  * (hfz_init, hfz_batch_init, hfz3_init), override the choices for testing
  * and measurement:
- *    HFZ_TILE=<0..3>      tile shape of the 2D smoother where it fits
+ *    HFZ_TILE=<0..9>      tile shape of the 2D smoother where it fits
  *    HFZ_RESTRICT=<0..3>  FAS restriction variant where it fits
  *    HFZ_SWEEPS=1         one sweep per smoother launch (default: two fused)
  *    HFZ_TUNE=0           no timing: shape 0, variant 0, fused sweeps
@@ -228,7 +228,7 @@ int hfz_info(hfz_handle* hd, int* levels, double* ce);
 
 /* Tile shape of the LDS-tiled sweep kernel on an FP64 level: tx x ty owned
  * nodes per workgroup of `threads` threads, picked at hfz_init by timing the
- * shapes that cover the level (environment: HFZ_TILE=<0..3> forces a shape,
+ * shapes that cover the level (environment: HFZ_TILE=<0..9> forces a shape,
  * HFZ_TUNE=0 keeps shape 0).  The swept values do not depend on the shape.
  * HFZ_EINVAL for a level the tiled kernel does not sweep (the coarse tail). */
 int hfz_tile_shape(hfz_handle* hd, int level, int* tx, int* ty, int* threads);

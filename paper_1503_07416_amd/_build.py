@@ -17,12 +17,29 @@ FLAGS = [
 
 
 def build(verbose=False):
+    """Compiles each source to an object in its own hipcc process (in
+    parallel), then links the shared library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
+    objs = [os.path.join(HERE, os.path.basename(src) + ".o") for src in SOURCES]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    for src, obj in zip(SOURCES, objs):
+        cmd = [hipcc] + compile_flags + ["-c", "-I", os.path.join(ROOT, "include"), "-o", obj, src]
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+    errs, failed = [], False
+    for p in procs:
+        _, err = p.communicate()
+        errs.append("\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l))
+        failed |= p.returncode != 0
+    err = "\n".join(e for e in errs if e.strip())
+    if failed:
         raise RuntimeError("hipcc failed:\n" + err)
+    res = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs,
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed:\n" + res.stderr)
+    for obj in objs:
+        os.remove(obj)
     if verbose and err.strip():
         print(err)
     os.replace(LIB + ".tmp", LIB)

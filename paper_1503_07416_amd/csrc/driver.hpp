@@ -154,6 +154,12 @@ int tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const F
     case 1: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 1>(H, K, L, in, out, C, res);
     case 2: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 2>(H, K, L, in, out, C, res);
     case 3: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 3>(H, K, L, in, out, C, res);
+    case 4: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 4>(H, K, L, in, out, C, res);
+    case 5: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 5>(H, K, L, in, out, C, res);
+    case 6: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 6>(H, K, L, in, out, C, res);
+    case 7: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 7>(H, K, L, in, out, C, res);
+    case 8: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 8>(H, K, L, in, out, C, res);
+    case 9: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 9>(H, K, L, in, out, C, res);
     default: return tile_launch_shape<MODEL, T, CORR, NSW, PRO, 0>(H, K, L, in, out, C, res);
   }
 }

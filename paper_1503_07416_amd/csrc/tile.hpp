@@ -28,15 +28,22 @@
 namespace hfz {
 
 // Tile shapes of the sweep kernel: TX x TY owned nodes per workgroup of NT
-// threads.  Shape 0 is the default (and the only one the batched kernels use);
-// the tuner (tune.hpp) picks a shape per level by timing.  The swept values
-// do not depend on the shape; only the grouping of the stop-test partial sums
-// does.
+// threads.  Shape 0 is the default (the batched kernels use shapes 0 and 2);
+// the tuner (tune.hpp) picks a shape per level by timing.  The small shapes
+// (4-6) are for the latency-bound levels, where a 16 x 16 tiling leaves most
+// compute units idle (64^2: 16 workgroups): more, smaller workgroups split
+// each half sweep's updates over more units at the price of more recomputed
+// halo.  The large ones (7-9) are for the large levels: a square tile
+// recomputes less halo per owned node than a 64 x 16 one, and 1024 threads
+// give each node of a half sweep its own thread.  The swept values do not
+// depend on the shape; only the grouping of the stop-test partial sums does.
 struct TileShape {
   int tx, ty, nt;
 };
-constexpr int NUM_TILE_SHAPES = 4;
-constexpr TileShape kTileShapes[NUM_TILE_SHAPES] = {{32, 16, 256}, {32, 16, 512}, {64, 16, 512}, {16, 16, 256}};
+constexpr int NUM_TILE_SHAPES = 10;
+constexpr TileShape kTileShapes[NUM_TILE_SHAPES] = {{32, 16, 256}, {32, 16, 512}, {64, 16, 512}, {16, 16, 256},
+                                                    {16, 16, 512}, {16, 8, 256},  {8, 8, 256},   {32, 32, 512},
+                                                    {32, 32, 1024}, {64, 16, 1024}};
 constexpr int TILE_X = kTileShapes[0].tx;
 constexpr int TILE_Y = kTileShapes[0].ty;
 constexpr int TILE_THREADS = kTileShapes[0].nt;

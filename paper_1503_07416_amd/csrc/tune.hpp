@@ -24,6 +24,7 @@
 #include <mutex>
 #include <tuple>
 #include <utility>
+#include <vector>
 
 #include "driver.hpp"
 
@@ -199,8 +200,7 @@ float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int
 // three rounds; a later candidate must win by 2%, so near-ties resolve the
 // same way every run); 0 if none could be timed.
 template <typename F> int pick_fastest(int count, F&& time, const char* what = nullptr, int n = 0) {
-  float ms[8];
-  for (int k = 0; k < count; ++k) ms[k] = -1.0f;
+  std::vector<float> ms((size_t)count, -1.0f);
   for (int round = 0; round < 3; ++round)
     for (int k = 0; k < count; ++k) {
       const float t = time(k);

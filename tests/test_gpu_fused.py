@@ -75,12 +75,12 @@ def oracle_cycles(cfg, rho, u, v, count):
 CASES = [("pfc", 128, {}), ("pfc", 256, dict(coarsest_n=32)), ("cdft", 128, {}), ("cdft", 64, dict(nu1=1, nu2=1)),
          ("pfc", 128, dict(nu1=3, nu2=1)), ("pfc", 64, dict(nu1=1, nu2=0)), ("pfc_gf", 128, {}),
          ("cdft_gf", 128, dict(coarsest_n=16))]
-ENVS = [{}, {"HFZ_SWEEPS": "1"}, {"HFZ_TILE": "2"}, {"HFZ_TILE": "3"}]
+ENVS = [{}, {"HFZ_SWEEPS": "1"}, {"HFZ_TILE": "2"}, {"HFZ_TILE": "3"}, {"HFZ_TILE": "6"}, {"HFZ_TILE": "9"}]
 
 
 @pytest.mark.parametrize("model,n,kw", CASES, ids=[f"{m}-{n}-{'-'.join(f'{k}{v}' for k, v in kw.items())}"
                                                    for m, n, kw in CASES])
-@pytest.mark.parametrize("env", ENVS, ids=["default", "one-sweep", "tile2", "tile3"])
+@pytest.mark.parametrize("env", ENVS, ids=["default", "one-sweep", "tile2", "tile3", "tile6", "tile9"])
 def test_fused_equals_separate_and_oracle(model, n, kw, env, monkeypatch):
     cfg, rho, u, v = case(model, n, **kw)
     print(f"fused {model} {n} {kw} {env}", flush=True)

@@ -203,7 +203,7 @@ def test_full_size_step(model, n):
 
 
 # the tuner picks among these by timing at init; each is forced here once
-VARIANTS = ([("HFZ_TILE", str(t)) for t in range(4)] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
+VARIANTS = ([("HFZ_TILE", str(t)) for t in range(10)] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
             + [("HFZ_SWEEPS", "1")])
 
 

@@ -230,7 +230,8 @@ def test_mixed_precision_steps(model, n, steps):
 
 
 # the tuner picks among these by timing at init; each is forced here once
-SHAPES = [(32, 16, 256), (32, 16, 512), (64, 16, 512), (16, 16, 256)]
+SHAPES = [(32, 16, 256), (32, 16, 512), (64, 16, 512), (16, 16, 256), (16, 16, 512), (16, 8, 256), (8, 8, 256),
+          (32, 32, 512), (32, 32, 1024), (64, 16, 1024)]
 VARIANTS = ([("HFZ_TILE", str(t)) for t in range(len(SHAPES))] + [("HFZ_RESTRICT", str(r)) for r in range(4)]
             + [("HFZ_SWEEPS", "1")])
 
