@@ -98,7 +98,7 @@ def parse():
                     help="the paper's convergence study instead of the benchmark (minutes of GPU time)")
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
     ap.add_argument("--conv-tf", type=float, default=10.0)
-    ap.add_argument("--probe-tile-shape", type=int, default=2,
+    ap.add_argument("--probe-tile-shape", type=int, default=9,
                     help="tile shape of the counter probe (the one the tuner picks at 512^2)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="only launch the smoother and a reference copy kernel (for counter runs)")

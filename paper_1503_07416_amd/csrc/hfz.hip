@@ -1283,13 +1283,15 @@ BatchGeom batch_geom(const hfz_params* ps, int count) {
 }
 
 // Tile shape of the batched smoother on an n x n level: 64x16 tiles of 512
-// threads (shape 2) from 128^2 up, else 32x16 of 256 (shape 0); forced (0 or
-// 2, from the environment variable HFZ_BATCH_TILE at hfz_batch_init)
-// overrides it where the shape divides n.
+// threads (shape 2) where they divide n, else 32x16 of 256 (shape 0); forced
+// (0 or 2, from the environment variable HFZ_BATCH_TILE at hfz_batch_init)
+// overrides it where the shape divides n.  (With many instances per launch
+// the workgroups fill the device at any level size, and the wider tile
+// recomputes less halo; the 1024-thread shapes time slower here.)
 int batch_tile_shape(int n, int forced) {
   const auto fits = [n](int ts) { return n % kTileShapes[ts].tx == 0 && n % kTileShapes[ts].ty == 0; };
   if ((forced == 0 || forced == 2) && fits(forced)) return forced;
-  return n >= 128 && fits(2) ? 2 : 0;
+  return fits(2) ? 2 : 0;
 }
 
 // Launch grid over each instance's finest level (sized for the largest; the

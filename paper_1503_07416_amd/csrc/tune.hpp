@@ -5,8 +5,10 @@
 // wide tiles (less recomputed halo per owned node) and more threads per
 // workgroup.  For every level the V-cycle sweeps with the tiled kernel, the
 // tuner times the level's pre-smoothing launch (two sweeps and the residual
-// field) in every tile shape that covers the level, with HIP events on the
-// handle's stream, and keeps the fastest.  The kernels' speed does not depend
+// field) and post-smoothing launch (the prolongation and two sweeps) in every
+// tile shape that covers the level, with HIP events on the handle's stream,
+// and keeps the fastest pair (the two can favour different shapes: with the
+// CDFT potential the prolongation launch is slower in 1024-thread tiles).  The kernels' speed does not depend
 // on the values they sweep, so the tuner runs on the workspace as it is; it
 // writes only the second iterate buffer and the residual scratch of the level.
 // The restriction variants (restrict.hpp) are timed the same way per level,
@@ -70,19 +72,29 @@ inline void tune_cache_save() {
   std::fclose(f);
 }
 
-// Average time (ms) of `reps` pre-smoothing launches of shape ts on level l,
-// after one untimed launch; negative on a HIP error.
+// Average time (ms) of `reps` pairs of a pre-smoothing launch (two sweeps and
+// the residual field) and a post-smoothing launch (the prolongation from
+// level l + 1, two sweeps, on the finest level of the FP64 solve the
+// stop-test partial sums) of shape ts on level l, after one untimed pair;
+// negative on a HIP error.  The pre-sweep writes the second iterate buffer,
+// the post-sweep reads it and writes the first: the tuner runs before any
+// state is set.
 template <int MODEL, typename T, bool CORR>
 float time_shape(Hier<T>& H, Cycle& K, int l, int ts, int reps) {
   const Lvl<T>& L = H.L[l];
   const Lvl<T>& C = H.L[l + 1];
   const Fld<T> a = fld<T>(L.g), b = fld<T>(L.gb);
+  const int res_post = (l == 0 && !CORR) ? 2 : 0;
+  auto pass = [&]() {
+    tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+    tile_launch<MODEL, T, CORR, 2, true>(H, K, L, b, a, C, res_post, ts);
+  };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   float ms = -1.0f;
   if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-    tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+    pass();
     bool ok = hipEventRecord(e0, K.stream) == hipSuccess;
-    for (int r = 0; r < reps && ok; ++r) tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
+    for (int r = 0; r < reps && ok; ++r) pass();
     ok = ok && hipEventRecord(e1, K.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipGetLastError() == hipSuccess;
     if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)

@@ -73,7 +73,7 @@ def test_batch_matches_oracle():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_tile_shapes_agree(precision, monkeypatch):
-    """From 128^2 up the batched smoother runs 64x16 tiles of 512 threads;
+    """From 64^2 up the batched smoother runs 64x16 tiles of 512 threads;
     HFZ_BATCH_TILE=0 (read at batch init) forces the 32x16 tiles of 256.
     The swept values do not depend on the tile: three steps of a 128^2 batch
     agree to rounding, with the same V-cycle counts."""
