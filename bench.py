@@ -598,24 +598,46 @@ def run_channel(steps=50, check_steps=10, n=256):
     return out
 
 
-def run_size_sweep(sizes=(1024, 2048, 4096)):
-    """The headline smoother (PFC, FP64, two fused sweeps per launch, the
-    tuner's tile shape) on grids past the 256 MB Infinity Cache: at 2048^2 one
-    launch moves 2.3 GB of algorithmic bytes, at 4096^2 9.1 GB."""
+def run_size_sweep(sizes=(1024, 2048, 4096), shapes=(0, 1, 2, 7, 8, 9)):
+    """The headline smoother (PFC, FP64, two fused sweeps per launch) on grids
+    past the 256 MB Infinity Cache: at 2048^2 one launch moves 2.3 GB of
+    algorithmic bytes, at 4096^2 9.1 GB.  In the tuner's tile shape (chosen
+    for the V-cycle's pre- and post-smoothing launches together), and in each
+    of the large shapes forced (HFZ_TILE, no tuning), with the best of them."""
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
-    out = {}
-    for m in sizes:
+
+    def one(m):
         cfg, rho, u, v = workloads.pfc_uniform_noise(m, 0.25, 0.01, 0)
         sim = pkg.Simulation(cfg, device="cuda:0")
         sim.set_state(rho, u, v)
         rl = smoother_roofline(sim, m, launches=10)
-        out[str(m)] = {"launch_us": rl["launch_us"], "achieved": rl["achieved"], "frac": rl["frac"],
-                       "kernel": rl["kernel"]}
         sim.close()
         del sim
         torch.cuda.empty_cache()
+        return rl
+
+    out = {}
+    for m in sizes:
+        rl = one(m)
+        out[str(m)] = {"launch_us": rl["launch_us"], "achieved": rl["achieved"], "frac": rl["frac"],
+                       "kernel": rl["kernel"], "by_shape_GBs": {}}
+        saved = {k: os.environ.get(k) for k in ("HFZ_TILE", "HFZ_TUNE")}
+        try:
+            os.environ["HFZ_TUNE"] = "0"
+            for ts in shapes:
+                os.environ["HFZ_TILE"] = str(ts)
+                r = one(m)
+                out[str(m)]["by_shape_GBs"][r["kernel"]] = r["achieved"]
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        best = max(out[str(m)]["by_shape_GBs"].items(), key=lambda kv: kv[1])
+        out[str(m)]["best"] = {"kernel": best[0], "achieved": best[1], "frac": round(best[1] / HBM_PEAK_GBS, 4)}
     return out
 
 
