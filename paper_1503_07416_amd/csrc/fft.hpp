@@ -3,6 +3,16 @@
 // row DFTs, a transpose, row DFTs; every row transform runs in LDS as a
 // radix-2 Stockham autosort FFT (n = 2^p, p <= 12; a 4096-point complex FP64
 // row and its ping-pong buffer take 128 KiB of the 160 KiB LDS).
+//
+// rho and the result are real, so the convolution keeps only the x
+// frequencies 0..n/2 of each row (the others are their complex conjugates):
+// two real rows are transformed as one complex row x_a + i x_b, whose
+// spectrum Z gives X_a(k) = (Z(k) + conj Z(n-k)) / 2 and
+// X_b(k) = (Z(k) - conj Z(n-k)) / (2i); the columns of the n/2 + 1 kept
+// frequencies are transformed, multiplied and transformed back; and two real
+// output rows come out of one inverse complex transform of
+// X_a(k) + i X_b(k), rebuilt over all k from the kept half.  Half the row
+// transforms and half the column transforms of a complex convolution.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -79,17 +89,72 @@ __global__ void k_fft_rows_fwd(double2* __restrict__ io, int n) {
   for (int t = threadIdx.x; t < n; t += blockDim.x) io[row + t] = r[t];
 }
 
-// Inverse row DFT, real part times scale into a real grid.
-__global__ void k_fft_rows_real_inv(const double2* __restrict__ in, double* __restrict__ out, int n,
-                                    double scale) {
+// Forward DFT of two real rows per workgroup (rows 2 blockIdx.x and
+// 2 blockIdx.x + 1 of the n x n grid in): frequencies 0..n/2 of each into the
+// rows of out (row stride n/2 + 1).
+__global__ void k_fft_rows_r2c(const double* __restrict__ in, double2* __restrict__ out, int n) {
   extern __shared__ double2 sh[];
   double2* a = sh;
   double2* b = sh + n;
-  const size_t row = (size_t)blockIdx.x * n;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) a[t] = in[row + t];
+  const int hx = n / 2 + 1;
+  const size_t ra = (size_t)(2 * blockIdx.x) * n, rb = ra + n;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) a[t] = make_double2(in[ra + t], in[rb + t]);
   __syncthreads();
-  double2* r = fft_lds(a, b, n, true);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) out[row + t] = r[t].x * scale;
+  const double2* z = fft_lds(a, b, n, false);
+  const size_t oa = (size_t)(2 * blockIdx.x) * hx, ob = oa + hx;
+  for (int k = threadIdx.x; k < hx; k += blockDim.x) {
+    const double2 zk = z[k], zn = z[(n - k) & (n - 1)];
+    // X_a = (zk + conj zn) / 2, X_b = (zk - conj zn) / (2i)
+    out[oa + k] = make_double2(0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y));
+    out[ob + k] = make_double2(0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x));
+  }
+}
+
+// Inverse DFT to two real rows per workgroup: in holds frequencies 0..n/2 of
+// rows 2 blockIdx.x and 2 blockIdx.x + 1 (row stride n/2 + 1); the complex
+// row X_a + i X_b over all k (X(n - k) = conj X(k)) is transformed back, its
+// real and imaginary parts times scale are the two rows of out.
+__global__ void k_fft_rows_c2r(const double2* __restrict__ in, double* __restrict__ out, int n, double scale) {
+  extern __shared__ double2 sh[];
+  double2* a = sh;
+  double2* b = sh + n;
+  const int hx = n / 2 + 1;
+  const size_t ia = (size_t)(2 * blockIdx.x) * hx, ib = ia + hx;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    double2 xa, xb;
+    if (k < hx) {
+      xa = in[ia + k];
+      xb = in[ib + k];
+    } else {
+      const double2 ca = in[ia + n - k], cb = in[ib + n - k];
+      xa = make_double2(ca.x, -ca.y);
+      xb = make_double2(cb.x, -cb.y);
+    }
+    a[k] = make_double2(xa.x - xb.y, xa.y + xb.x);  // X_a + i X_b
+  }
+  __syncthreads();
+  const double2* r = fft_lds(a, b, n, true);
+  const size_t ra = (size_t)(2 * blockIdx.x) * n, rb = ra + n;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    out[ra + t] = r[t].x * scale;
+    out[rb + t] = r[t].y * scale;
+  }
+}
+
+// out = in^T for a rows x cols complex grid (row strides cols and rows),
+// 32 x 32 tiles through LDS.
+__global__ void k_transpose_rect(const double2* __restrict__ in, double2* __restrict__ out, int rows, int cols) {
+  __shared__ double2 tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // column, row of the tile in `in`
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int x = bx + threadIdx.x, y = by + k;
+    if (x < cols && y < rows) tile[k][threadIdx.x] = in[(size_t)y * cols + x];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int x = by + threadIdx.x, y = bx + k;
+    if (x < rows && y < cols) out[(size_t)y * rows + x] = tile[threadIdx.x][k];
+  }
 }
 
 // out = in^T for an n x n complex grid, 32 x 32 tiles through LDS.

@@ -554,15 +554,18 @@ int solve_step(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
 
 // (J * rho) of Eq. discrete_convolution: jrho = IDFT(mult . DFT(rho)) / n^2.
 void convolve(hfz_handle* hd, const double* rho, double* out) {
-  const int n = hd->p.n;
+  const int n = hd->p.n, hx = n / 2 + 1;
   const int thr = std::min(256, n / 2);
   const size_t sh = 2 * (size_t)n * sizeof(double2);
-  const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
-  k_fft_rows_real_fwd<<<n, thr, sh, hd->stream>>>(rho, hd->fa, n);
-  k_transpose<<<tg, tb, 0, hd->stream>>>(hd->fa, hd->fb, n);
-  k_fft_rows_conv<<<n, thr, sh, hd->stream>>>(hd->fb, hd->mult, n);
-  k_transpose<<<tg, tb, 0, hd->stream>>>(hd->fb, hd->fa, n);
-  k_fft_rows_real_inv<<<n, thr, sh, hd->stream>>>(hd->fa, out, n, 1.0 / ((double)n * n));
+  const dim3 tb(32, 8);
+  // rows (two real rows per transform) -> n x hx; columns of the hx kept x
+  // frequencies (rows of the transposed hx x n grid; mult's first hx rows are
+  // those frequencies) -> back
+  k_fft_rows_r2c<<<n / 2, thr, sh, hd->stream>>>(rho, hd->fa, n);
+  k_transpose_rect<<<dim3((hx + 31) / 32, (n + 31) / 32), tb, 0, hd->stream>>>(hd->fa, hd->fb, n, hx);
+  k_fft_rows_conv<<<hx, thr, sh, hd->stream>>>(hd->fb, hd->mult, n);
+  k_transpose_rect<<<dim3((n + 31) / 32, (hx + 31) / 32), tb, 0, hd->stream>>>(hd->fb, hd->fa, hx, n);
+  k_fft_rows_c2r<<<n / 2, thr, sh, hd->stream>>>(hd->fa, out, n, 1.0 / ((double)n * n));
 }
 
 // CDFT set-up: J on the grid, c_e = h^2 sum J_e, mult = h^2 Re DFT(J) in the
