@@ -226,7 +226,7 @@ def oracle_sample(n, vcycles):
     V-cycles of it."""
     import workloads
     from oracle.fas import Stepper
-    cfg, rho, u, v = workloads.config2(0, n=n)
+    cfg, rho, u, v = workloads.pfc_freezing_512(0, n=n)
     st = Stepper(cfg.model, cfg.n, cfg.h, cfg.s, **cfg.oracle_kwargs())
     st.set_state(rho, u, v)
     t0 = time.perf_counter()
@@ -294,12 +294,12 @@ def rel_diff(a, b):
 
 
 def run_mixed(a, ref_state):
-    """Config 2 in mixed precision: steps/s and max relative distance of the
+    """The PFC 512^2 workload in mixed precision: steps/s and max relative distance of the
     final state from the FP64 run's."""
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
-    cfg, rho, u, v = workloads.config2(0, precision="mixed", n=a.n)
+    cfg, rho, u, v = workloads.pfc_freezing_512(0, precision="mixed", n=a.n)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E = [sim.energy()[0]]
@@ -329,7 +329,7 @@ def run_precision_sweep(sizes=(512, 1024, 2048), steps=5, warmup=2):
     for n in sizes:
         row = {}
         for prec in ("fp64", "mixed"):
-            cfg, rho, u, v = workloads.config2(0, precision=prec, n=n)
+            cfg, rho, u, v = workloads.pfc_freezing_512(0, precision=prec, n=n)
             sim = pkg.Simulation(cfg, device="cuda:0")
             sim.set_state(rho, u, v)
             sim.step(warmup)
@@ -350,7 +350,7 @@ def run_precision_sweep(sizes=(512, 1024, 2048), steps=5, warmup=2):
 
 
 def run_batched(steps=20, count=256):
-    """Config 4: all instances (grid sizes mixed) in one batch, one launch per
+    """The batched workload: all instances (grid sizes mixed) in one batch, one launch per
     level depth and phase; then the same instances one at a time through the
     unbatched FP64 path (a sample of 16), and an untimed rerun one step at a
     time reading every instance's energy after each step."""
@@ -358,7 +358,7 @@ def run_batched(steps=20, count=256):
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
-    inst = workloads.config4(count)
+    inst = workloads.pfc_nanocrystal_batch(count)
     B = pkg.Batch([c for c, _, _, _ in inst], device="cuda:0")
 
     def load():
@@ -414,7 +414,7 @@ def run_batched(steps=20, count=256):
 
 
 def run_serving(requests, hbm_frac):
-    """Config 5: the budget is hbm_frac (80 %) of the device's memory; a pilot
+    """The serving workload: the budget is hbm_frac (80 %) of the device's memory; a pilot
     per class (alone, mixed PFC / FP64 CDFT) gives the mean residence time,
     and the arrival rate follows Little's law for a mean occupancy of that
     budget, lambda = budget / (E[bytes per request] E[residence]); then the
@@ -468,12 +468,12 @@ def run_serving(requests, hbm_frac):
 
 
 def run_cdft(steps=50, n=1024):
-    """Config 3: CDFT 1024^2 FP64, energy and mass read after every step
+    """The CDFT workload: 1024^2 FP64, energy and mass read after every step
     (inside the timed region: they are part of this workload)."""
     import torch
     import workloads
     import paper_1503_07416_amd as pkg
-    cfg, rho, u, v = workloads.config3(0, n=n)
+    cfg, rho, u, v = workloads.cdft_freezing_1024(0, n=n)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E = [sim.energy()]
@@ -801,7 +801,7 @@ def main():
         import torch
         import workloads
         import paper_1503_07416_amd as pkg
-        cfg, rho, u, v = workloads.config2(0, n=a.n)
+        cfg, rho, u, v = workloads.pfc_freezing_512(0, n=a.n)
         sim = pkg.Simulation(cfg, device="cuda:0")
         sim.set_state(rho, u, v)
         sim.step(a.warmup + a.steps)
@@ -815,7 +815,7 @@ def main():
     import workloads
     import paper_1503_07416_amd as pkg
 
-    cfg, rho, u, v = workloads.config2(0, n=a.n)
+    cfg, rho, u, v = workloads.pfc_freezing_512(0, n=a.n)
     sim = pkg.Simulation(cfg, device="cuda:0")
     sim.set_state(rho, u, v)
     E0 = sim.energy()[0]

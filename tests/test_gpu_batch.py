@@ -145,7 +145,7 @@ def test_uneven_batch_benchmark_mix_matches_oracle():
     32^2, mixed precision) on a dozen instances, two steps against the FP64
     oracle (1e-6), and against each instance alone (same V-cycles)."""
     import paper_1503_07416_amd as pkg
-    inst = workloads.config4(count=12, seed=3)
+    inst = workloads.pfc_nanocrystal_batch(count=12, seed=3)
     assert len({c.n for c, _, _, _ in inst}) == 3
     B = pkg.Batch([c for c, _, _, _ in inst])
     for i, (c, r, u, v) in enumerate(inst):

@@ -24,10 +24,10 @@ from tests.helpers import oracle_stepper, rel_err
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "pfc512": lambda: workloads.config2(0),
-    "pfc512_mixed": lambda: workloads.config2(0, precision="mixed"),
-    "cdft1024": lambda: workloads.config3(0),
-    "cdft2048": lambda: workloads.config3(1, n=2048),   # the largest CDFT grid the ABI accepts
+    "pfc512": lambda: workloads.pfc_freezing_512(0),
+    "pfc512_mixed": lambda: workloads.pfc_freezing_512(0, precision="mixed"),
+    "cdft1024": lambda: workloads.cdft_freezing_1024(0),
+    "cdft2048": lambda: workloads.cdft_freezing_1024(1, n=2048),   # the largest CDFT grid the ABI accepts
 }
 
 

@@ -109,7 +109,7 @@ def test_vcycles(model, n):
 def test_config1_steps(seed):
     """PFC 32^2, h = 0.25, s = 0.01, V(2,2), tol 1e-10: ten steps, every step
     within 1e-10 relative of the oracle, same V-cycle counts."""
-    cfg, rho, u, v = workloads.config1(seed)
+    cfg, rho, u, v = workloads.pfc_freezing_32(seed)
     sim = sim_for(cfg, rho, u, v)
     ora = oracle_stepper(cfg)
     ora.set_state(rho, u, v)
@@ -164,7 +164,7 @@ def test_ragged_tiles_and_sizes(model):
 
 def test_failure_paths_leave_state():
     import paper_1503_07416_amd as pkg
-    cfg, rho, u, v = workloads.config1(0)
+    cfg, rho, u, v = workloads.pfc_freezing_32(0)
     cfg.max_cycles = 1
     sim = sim_for(cfg, rho, u, v)
     before = [np_(x) for x in sim.get_state()]
@@ -182,7 +182,7 @@ def test_failure_paths_leave_state():
 
 
 def test_uniform_fixed_point_zero_cycles():
-    cfg, rho, u, v = workloads.config1(0)
+    cfg, rho, u, v = workloads.pfc_freezing_32(0)
     rho[:] = 1.3
     u[:] = 0.2
     v[:] = -0.1
@@ -194,7 +194,7 @@ def test_uniform_fixed_point_zero_cycles():
 
 
 def test_determinism_bitwise():
-    cfg, rho, u, v = workloads.config1(1)
+    cfg, rho, u, v = workloads.pfc_freezing_32(1)
     outs = []
     for _ in range(2):
         sim = sim_for(cfg, rho, u, v)

@@ -201,26 +201,26 @@ def random_velocity(n, seed, amp):
     return amp * rng.uniform(-1.0, 1.0, (n, n)), amp * rng.uniform(-1.0, 1.0, (n, n))
 
 
-# ---- the five workloads of the benchmark / parity suite -------------------
+# ---- the workloads of the benchmark and parity suite ----------------------
 
-def config1(seed=0):
+def pfc_freezing_32(seed=0):
     """PFC, 32^2, h = 0.25, s = 0.01, 10 steps, FP64, V(2,2), tol 1e-10."""
     return pfc_uniform_noise(32, 0.25, 0.01, seed)
 
 
-def config2(seed=0, precision="fp64", n=512):
+def pfc_freezing_512(seed=0, precision="fp64", n=512):
     """PFC, 512^2, h = 0.25, s = 0.01, 100 steps; FP64 or mixed precision;
     V(2,2) down to a 32^2 coarsest grid."""
     return pfc_uniform_noise(n, 0.25, 0.01, seed, precision=precision, coarsest_n=BENCH_COARSEST_N)
 
 
-def config3(seed=0, n=1024):
+def cdft_freezing_1024(seed=0, n=1024):
     """CDFT, 1024^2, h = 17/128, s = 0.02, rho_bar + 0.02 N(0,1), 50 steps;
     V(2,2) down to a 32^2 coarsest grid."""
     return cdft_gauss_noise(n, 17.0 / 128.0, 0.02, seed, coarsest_n=BENCH_COARSEST_N)
 
 
-def config4(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
+def pfc_nanocrystal_batch(count=256, seed=0, sizes=(64, 128, 256), precision="mixed"):
     """Batch of independent PFC instances (eps = 0.4, h = pi/(2 sqrt 3), s = 0.02),
     n ~ U{sizes}, rho_bar ~ U(rho_l, rho_s), rho = rho_bar + 0.05 U(-1,1);
     instance i draws its field from seed 1000 + i."""
@@ -281,8 +281,8 @@ def serving_stream(count, rate, seed=0, sizes=(64, 128, 256, 512, 1024),
                    steps=(10, 200), pfc_precision="mixed", cdft_precision="fp64"):
     """Poisson request stream: exponential inter-arrival times of mean 1/rate,
     model PFC or CDFT with probability 1/2 each, n ~ U{sizes},
-    steps ~ U{steps[0]..steps[1]}.  PFC requests are drawn as in ``config4``
-    (mixed precision by default), CDFT requests as in ``config3`` at their own
+    steps ~ U{steps[0]..steps[1]}.  PFC requests are drawn as in ``pfc_nanocrystal_batch``
+    (mixed precision by default), CDFT requests as in ``cdft_freezing_1024`` at their own
     size (FP64 by default)."""
     rng = np.random.default_rng(seed)
     t = 0.0
