@@ -117,6 +117,8 @@ Dims dims2(int nx, int ny) {
 
 }  // namespace
 
+constexpr int kGraphSizes = 4;  // graphs of 1, 2, 4, 8 V-cycles
+
 struct hfz_handle {
   hfz_params p{};
   int km = 0;  // the kernels' model (kernel_model)
@@ -150,10 +152,12 @@ struct hfz_handle {
   int mp_inner = 3;  // FP32 V-cycles per outer defect-correction iteration
   bool use_tiles = true;  // LDS-tiled kernels on levels >= 32
   int norm_partials = 0;  // > 0: the last V-cycle's post-sweep left this many residual partials
-  int graph_state = 0;  // 0: not built, 1: built, -1: unavailable
-  hipGraphExec_t cycle_exec = nullptr;
-  int mp_graph_state = 0;  // the same for the mixed-precision outer iteration
-  hipGraphExec_t mp_exec = nullptr;
+  // HIP graphs of 1, 2, 4 and 8 V-cycles (each with its stop test): state 0
+  // not built, 1 built, -1 unavailable
+  int graph_state[kGraphSizes] = {};
+  hipGraphExec_t cycle_exec[kGraphSizes] = {};
+  int mp_graph_state[kGraphSizes] = {};  // the same for the mixed-precision outer iteration
+  hipGraphExec_t mp_exec[kGraphSizes] = {};
 };
 
 namespace {
@@ -382,14 +386,18 @@ void vcycle_and_norm(hfz_handle* hd, bool stop) {
     residual_launch(hd, stop);
 }
 
-// One V-cycle followed by the residual norm and the device stop test,
+// 2^k V-cycles, each followed by the residual norm and the device stop test,
 // captured once into a HIP graph (on a private stream: capture records, it
-// does not execute) and replayed on the caller's stream.  Returns false when
-// graphs are unavailable; callers then launch the kernels one by one and test
-// on the host.
-bool cycle_graph(hfz_handle* hd) {
-  if (hd->graph_state == 1) return true;
-  if (hd->graph_state < 0) return false;
+// does not execute) and replayed on the caller's stream.  A batch of cycles
+// is launched as graphs of 8, 4, 2 and 1 cycles: the device idles for some
+// microseconds between two graph launches, against under one between two
+// kernels of a graph.  `body` enqueues one cycle.  Returns false when graphs
+// are unavailable; callers then launch the kernels one by one and test on the
+// host.
+template <typename F>
+bool capture_graph(hfz_handle* hd, int* state, hipGraphExec_t* exec, int k, F&& body) {
+  if (state[k] == 1) return true;
+  if (state[k] < 0) return false;
   hipStream_t cap = nullptr;
   hipGraph_t g = nullptr;
   bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
@@ -398,17 +406,21 @@ bool cycle_graph(hfz_handle* hd) {
     hd->stream = cap;
     ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      vcycle_and_norm(hd, true);
+      for (int i = 0; i < (1 << k); ++i) body();
       ok = hipStreamEndCapture(cap, &g) == hipSuccess;
     }
     hd->stream = user;
   }
-  if (ok) ok = hipGraphInstantiate(&hd->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphInstantiate(&exec[k], g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   if (cap) (void)hipStreamDestroy(cap);
   (void)hipGetLastError();
-  hd->graph_state = ok ? 1 : -1;
+  state[k] = ok ? 1 : -1;
   return ok;
+}
+
+bool cycle_graph(hfz_handle* hd, int k = 0) {
+  return capture_graph(hd, hd->graph_state, hd->cycle_exec, k, [&]() { vcycle_and_norm(hd, true); });
 }
 
 // One V-cycle and the residual norm that follows it, launched kernel by
@@ -447,28 +459,8 @@ void mp_cycle(hfz_handle* hd, bool stop) {
   mp_prepare_launch(hd, stop);
 }
 
-bool mp_graph(hfz_handle* hd) {
-  if (hd->mp_graph_state == 1) return true;
-  if (hd->mp_graph_state < 0) return false;
-  hipStream_t cap = nullptr;
-  hipGraph_t g = nullptr;
-  bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
-  if (ok) {
-    hipStream_t user = hd->stream;
-    hd->stream = cap;
-    ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
-    if (ok) {
-      mp_cycle(hd, true);
-      ok = hipStreamEndCapture(cap, &g) == hipSuccess;
-    }
-    hd->stream = user;
-  }
-  if (ok) ok = hipGraphInstantiate(&hd->mp_exec, g, nullptr, nullptr, 0) == hipSuccess;
-  if (g) (void)hipGraphDestroy(g);
-  if (cap) (void)hipStreamDestroy(cap);
-  (void)hipGetLastError();
-  hd->mp_graph_state = ok ? 1 : -1;
-  return ok;
+bool mp_graph(hfz_handle* hd, int k = 0) {
+  return capture_graph(hd, hd->mp_graph_state, hd->mp_exec, k, [&]() { mp_cycle(hd, true); });
 }
 
 int mp_cycle_and_residual(hfz_handle* hd, double* norm) {
@@ -511,7 +503,18 @@ int solve_step(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
     *cycles_out = cycles;
     return rc;
   }
-  hipGraphExec_t exec = mixed ? hd->mp_exec : hd->cycle_exec;
+  // `count` cycles as graphs of 8, 4, 2 and 1 (a size whose graph cannot be
+  // built is covered by smaller ones)
+  auto launch_cycles = [&](int count) -> bool {
+    for (int k = kGraphSizes - 1; k >= 0; --k) {
+      const bool have = k == 0 || (mixed ? mp_graph(hd, k) : cycle_graph(hd, k));
+      if (!have) continue;
+      hipGraphExec_t exec = mixed ? hd->mp_exec[k] : hd->cycle_exec[k];
+      for (; count >= (1 << k); count -= 1 << k)
+        if (hipGraphLaunch(exec, hd->stream) != hipSuccess) return false;
+    }
+    return true;
+  };
   k_ctl_reset<<<1, 64, 0, hd->stream>>>(hd->ctl);
   if (mixed)
     mp_prepare_launch(hd, true, false);
@@ -522,9 +525,10 @@ int solve_step(hfz_handle* hd, bool mixed, double* r, int* cycles_out) {
   for (;;) {
     const int remaining = hd->p.max_cycles - cycles;
     const int nb = std::min(batch, remaining);
-    for (int i = 0; i < nb && rc == HFZ_OK; ++i)
-      if (hipGraphLaunch(exec, hd->stream) != hipSuccess) rc = HFZ_EHIP;
-    if (rc != HFZ_OK) break;
+    if (!launch_cycles(nb)) {
+      rc = HFZ_EHIP;
+      break;
+    }
     double h[10];
     if (hipMemcpyAsync(h, hd->result, sizeof(h), hipMemcpyDeviceToHost, hd->stream) != hipSuccess ||
         hipStreamSynchronize(hd->stream) != hipSuccess) {
@@ -1071,8 +1075,10 @@ int hfz_tile_shape(hfz_handle* hd, int level, int* tx, int* ty, int* threads) {
 
 int hfz_destroy(hfz_handle* hd) {
   if (!hd) return HFZ_EINVAL;
-  if (hd->cycle_exec) (void)hipGraphExecDestroy(hd->cycle_exec);
-  if (hd->mp_exec) (void)hipGraphExecDestroy(hd->mp_exec);
+  for (int k = 0; k < kGraphSizes; ++k) {
+    if (hd->cycle_exec[k]) (void)hipGraphExecDestroy(hd->cycle_exec[k]);
+    if (hd->mp_exec[k]) (void)hipGraphExecDestroy(hd->mp_exec[k]);
+  }
   delete hd;
   return HFZ_OK;
 }
