@@ -81,6 +81,8 @@
  *                         level where it can be (default: timed per level)
  *    HFZ_MP_INNER=<1..8>  FP32 V-cycles per outer FP64 iteration (mixed)
  *    HFZ_BATCH_TILE=<0|2> tile shape of the batched smoother
+ *    HFZ_BATCH_RESTRICT=0 batched FAS restriction by the direct kernel (default:
+ *                         the staged one)
  *    HFZ3_TILES=<n>       smallest 3D level swept by the tiled kernel (0: none)
  *    HFZ3_TAIL=0          no one-workgroup tail in 3D
  *    HFZ_VERBOSE=1        the choices made, on stderr

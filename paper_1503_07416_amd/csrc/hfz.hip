@@ -1186,6 +1186,7 @@ struct hfz_batch {
   int count = 0;
   hfz_params p{};  // model, precision, nu1, nu2, coarsest_n, coarse_sweeps, continuity_fix: shared
   int tile_force = -1;  // smoother tile shape forced by HFZ_BATCH_TILE at init (-1: by level size)
+  bool restrict_staged = true;  // staged FAS restriction (HFZ_BATCH_RESTRICT=0: the direct kernel)
   hipStream_t stream = nullptr;
   std::vector<hfz_handle*> inst;  // by slot
   std::vector<int> slot_of;       // user index -> slot
@@ -1372,8 +1373,14 @@ void bvcycle_depth(hfz_batch* B, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_
     }
   };
   sweeps(K.nu1, false, 1);
-  k_restrict_fas_tile_b<MODEL, T, CORR><<<dim3(nc / RTILE, nc / RTILE, cz), RTILE * RTILE, 0, K.stream>>>(
-      Dl, Dc, Ps, B->active, inb);
+  // the FAS restriction: the staged kernel (coarse tiles of 8 through LDS), or
+  // the direct one (HFZ_BATCH_RESTRICT=0)
+  if (B->restrict_staged && nc % 8 == 0)
+    k_restrict_fas_staged_b<MODEL, T, CORR, 8, 256><<<dim3(nc / 8, nc / 8, cz), 256, 0, K.stream>>>(
+        Dl, Dc, Ps, B->active, inb);
+  else
+    k_restrict_fas_tile_b<MODEL, T, CORR><<<dim3(nc / RTILE, nc / RTILE, cz), RTILE * RTILE, 0, K.stream>>>(
+        Dl, Dc, Ps, B->active, inb);
   bvcycle_depth<MODEL, T, CORR>(B, D, Tl, Ps, lds_max, K, d - 1);
   // the post-sweeps leave stop-test partial sums for the instances whose
   // finest level this is (FP64 solve)
@@ -1527,6 +1534,7 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   B->count = count;
   B->p = params[G.order[0]];
   if (const char* e = std::getenv("HFZ_BATCH_TILE")) B->tile_force = std::atoi(e);
+  if (const char* e = std::getenv("HFZ_BATCH_RESTRICT")) B->restrict_staged = std::atoi(e) != 0;
   B->stream = static_cast<hipStream_t>(hip_stream);
   char* base = static_cast<char*>(dev_ws);
   B->slot_of.assign(count, 0);

@@ -248,6 +248,21 @@ __global__ __launch_bounds__(NT) void k_restrict_fas_staged(Lvl<T> F, Lvl<T> C, 
   restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, C, P);
 }
 
+// Batched staged form (instance blockIdx.z; the fine iterate in g, inb = 0,
+// or gb).
+template <int MODEL, typename T, bool CORR, int RT, int NT>
+__global__ __launch_bounds__(NT) void k_restrict_fas_staged_b(const Lvl<T>* Fs, const Lvl<T>* Cs,
+                                                             const Phys<T>* Ps, const int* active, int inb) {
+  const int z = blockIdx.z;
+  if (!active[z]) return;
+  Lvl<T> F = lvl_global(Fs[z]);
+  if (inb) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F.g[c] = F.gb[c];
+  }
+  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, lvl_global(Cs[z]), Ps[z]);
+}
+
 // Restriction variants the tuner chooses from: 0 the direct kernel (coarse
 // tile 16), 1 the staged kernel with coarse tile 8, 2 with coarse tile 16,
 // 3 with coarse tile 16 and 512 threads.
