@@ -1023,8 +1023,8 @@ struct hfz3_handle {
   int* ctl = nullptr;
   bool has_state = false;
   int cycle_hint = 4;
-  int graph_state = 0;
-  hipGraphExec_t cycle_exec = nullptr;
+  int graph_state[4] = {};  // graphs of 1, 2, 4, 8 V-cycles: 0 not built, 1 built, -1 unavailable
+  hipGraphExec_t cycle_exec[4] = {};
   // smallest level swept by the z-marching tiled kernel (below: the two
   // per-colour kernels, which fill the device better on small grids); the
   // environment variable HFZ3_TILES overrides it (0: never)
@@ -1187,9 +1187,12 @@ int residual(hfz3_handle* hd, double* norm) {
 
 // One V-cycle and its stop-test norm, captured once into a HIP graph on a
 // private stream and replayed on the caller's; false when unavailable.
-bool cycle_graph(hfz3_handle* hd) {
-  if (hd->graph_state == 1) return true;
-  if (hd->graph_state < 0) return false;
+// 2^k V-cycles, each with its stop-test norm, in one HIP graph (k < 4): a
+// batch of cycles is launched as graphs of 8, 4, 2 and 1, since the device
+// idles some microseconds between two graph launches.
+bool cycle_graph(hfz3_handle* hd, int k = 0) {
+  if (hd->graph_state[k] == 1) return true;
+  if (hd->graph_state[k] < 0) return false;
   hipStream_t cap = nullptr;
   hipGraph_t g = nullptr;
   bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
@@ -1198,17 +1201,19 @@ bool cycle_graph(hfz3_handle* hd) {
     hd->stream = cap;
     ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      vcycle_rec(hd, 0);
-      residual_launch(hd, true, true);
+      for (int i = 0; i < (1 << k); ++i) {
+        vcycle_rec(hd, 0);
+        residual_launch(hd, true, true);
+      }
       ok = hipStreamEndCapture(cap, &g) == hipSuccess;
     }
     hd->stream = user;
   }
-  if (ok) ok = hipGraphInstantiate(&hd->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphInstantiate(&hd->cycle_exec[k], g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   if (cap) (void)hipStreamDestroy(cap);
   (void)hipGetLastError();
-  hd->graph_state = ok ? 1 : -1;
+  hd->graph_state[k] = ok ? 1 : -1;
   return ok;
 }
 
@@ -1256,9 +1261,12 @@ int solve_step(hfz3_handle* hd, double* r, int* cycles_out) {
   int rc = HFZ_OK;
   int batch = std::max(1, hd->cycle_hint);
   for (;;) {
-    const int nb = std::min(batch, hd->p.max_cycles - cycles);
-    for (int i = 0; i < nb && rc == HFZ_OK; ++i)
-      if (hipGraphLaunch(hd->cycle_exec, hd->stream) != hipSuccess) rc = HFZ_EHIP;
+    int nb = std::min(batch, hd->p.max_cycles - cycles);
+    for (int k = 3; k >= 0 && rc == HFZ_OK; --k) {
+      if (k > 0 && !cycle_graph(hd, k)) continue;
+      for (; nb >= (1 << k) && rc == HFZ_OK; nb -= 1 << k)
+        if (hipGraphLaunch(hd->cycle_exec[k], hd->stream) != hipSuccess) rc = HFZ_EHIP;
+    }
     if (rc != HFZ_OK) break;
     double hst[10];
     if ((rc = read_result(hd, hst, 10)) != HFZ_OK) break;
@@ -1481,7 +1489,8 @@ int hfz3_levels(hfz3_handle* hd, int* levels) {
 
 int hfz3_destroy(hfz3_handle* hd) {
   if (!hd) return HFZ_EINVAL;
-  if (hd->cycle_exec) (void)hipGraphExecDestroy(hd->cycle_exec);
+  for (int k = 0; k < 4; ++k)
+    if (hd->cycle_exec[k]) (void)hipGraphExecDestroy(hd->cycle_exec[k]);
   delete hd;
   return HFZ_OK;
 }
