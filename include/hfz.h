@@ -79,6 +79,10 @@
  *    HFZ_FUSE=<0|1>       FAS restriction as a launch of its own (0) or folded
  *                         into the last pre-sweep launch of a level (1) on every
  *                         level where it can be (default: timed per level)
+ *    HFZ_FOLD_RHS=0       a coarse level whose right-hand side a folded
+ *                         restriction left as R d has it completed by a launch
+ *                         of its own (default: by its own pre-sweep launch where
+ *                         that folds its restriction too and its tiles fit LDS)
  *    HFZ_MP_INNER=<1..8>  FP32 V-cycles per outer FP64 iteration (mixed)
  *    HFZ_BATCH_TILE=<0|2> tile shape of the batched smoother
  *    HFZ_BATCH_RESTRICT=0 batched FAS restriction by the direct kernel (default:

@@ -26,6 +26,7 @@ template <typename T> struct Hier {
   std::vector<int> restrict_shape;  // restriction variant per fine level (restrict.hpp)
   std::vector<int> sweep_fuse;      // sweeps per tiled launch per level (2 fused, or 1)
   std::vector<char> fused;          // per level: the FAS restriction folded into the pre-sweep launch
+  bool fold_rhs = true;             // a folded level completes its own coarse right-hand side (RES = 4)
   Phys<T> P{};
 };
 
@@ -102,7 +103,10 @@ template <int MODEL, typename T, bool CORR> void tail_launch(Hier<T>& H, Cycle& 
 
 // Launches the tiled sweep kernel of shape ts on level L; returns its
 // number of workgroups (= stop-test partial sums when res == 2).  res 3 (the
-// restriction into C folded in) only without PRO and walls.
+// restriction into C folded in) only without PRO and walls; res 4 (the same
+// after completing L's own right-hand side) also only with two sweeps in a
+// shape whose arrays fit the LDS (fold_rhs_fits; returns 0 and launches
+// nothing otherwise).
 template <int MODEL, typename T, bool CORR, int NSW, bool PRO, int TS>
 int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const Fld<T>& out,
                       const Lvl<T>& C, int res) {
@@ -112,6 +116,13 @@ int tile_launch_shape(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, c
     if (res == 3) {
       k_sweeps_tile<MODEL, T, NSW, false, 3, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
       return (int)(grid.x * grid.y);
+    }
+    if (res == 4) {
+      if constexpr (NSW == 2 && fold_rhs_fits<MODEL, T, CORR, TS>()) {
+        k_sweeps_tile<MODEL, T, 2, false, 4, CORR, TS><<<grid, S.nt, 0, K.stream>>>(L, in, out, C, H.P, K.partial);
+        return (int)(grid.x * grid.y);
+      }
+      return 0;
     }
   }
   if (res == 1)
@@ -167,12 +178,16 @@ int tile_launch(Hier<T>& H, Cycle& K, const Lvl<T>& L, const Fld<T>& in, const F
 // `sweeps` tiled sweeps of level l from cur into the other buffer and back
 // (two per launch, or one where the level's sweep schedule says so).  The first launch applies the coarse-grid correction from
 // level l+1 when pro is set; the last launch also computes the residual
-// (res_last: 1 the field d, 2 stop-test partial sums).  On return cur names
-// the buffer holding the iterate.
+// (res_last: 1 the field d, 2 stop-test partial sums, 3 and 4 the folded
+// restriction).  f_in_d: the level's right-hand side is in L.d (left there by
+// its RES = 4 pre-sweep launch).  On return cur names the buffer holding the
+// iterate.
 template <int MODEL, typename T, bool CORR>
 int tiled_sweeps(Hier<T>& H, Cycle& K, int l, int sweeps, bool pro, Fld<T>& cur, Fld<T>& other,
-                 int res_last = 0) {
-  const Lvl<T>& L = H.L[l];
+                 int res_last = 0, bool f_in_d = false) {
+  Lvl<T> L = H.L[l];
+  if (f_in_d)
+    for (int c = 0; c < 5; ++c) L.f[c] = L.d[c];
   const Lvl<T>& C = H.L[std::min<size_t>(l + 1, H.L.size() - 1)];
   const int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
   const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
@@ -210,13 +225,38 @@ template <typename T> bool level_fused(const Hier<T>& H, const Cycle& K, int l) 
   return K.nu1 >= 1 && l < (int)H.fused.size() && H.fused[l];
 }
 
+// Whether the V-cycle visits level l with the tail kernel, or with the tiled
+// kernels (vcycle_tiled).
+template <int MODEL, typename T, bool CORR> bool level_in_tail(const Hier<T>& H, const Cycle& K, int l) {
+  return H.L[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[l].n, (int)H.L.size() - l, H.tail_lds_max, nullptr);
+}
+template <int MODEL, typename T, bool CORR> bool level_tiled(const Hier<T>& H, const Cycle& K, int l) {
+  return !level_in_tail<MODEL, T, CORR>(H, K, l) && K.use_tiles && l + 1 < (int)H.L.size() &&
+         H.L[l].n >= TILE_X && H.L[l + 1].n >= RTILE;
+}
+
+// Whether tiled level l, its right-hand side left as R d by a restriction
+// folded into level l - 1, can complete it in its own pre-sweep launch when
+// that launch folds its restriction too: one launch of two sweeps (nu1 = 2)
+// in a tile shape whose RES = 4 arrays fit the LDS.
+template <int MODEL, typename T, bool CORR> bool fold_rhs_possible(const Hier<T>& H, const Cycle& K, int l) {
+  if constexpr (walls(MODEL)) return false;
+  if (!H.fold_rhs || l < 1 || !level_fused(H, K, l - 1) || !level_tiled<MODEL, T, CORR>(H, K, l)) return false;
+  const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
+  int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
+  if (!tile_shape_fits(ts, H.L[l].n)) ts = 0;
+  return K.nu1 == 2 && fuse >= 2 && fold_rhs_fits_shape<MODEL, T, CORR>(ts);
+}
+template <int MODEL, typename T, bool CORR> bool level_fold_rhs(const Hier<T>& H, const Cycle& K, int l) {
+  return level_fused(H, K, l) && fold_rhs_possible<MODEL, T, CORR>(H, K, l);
+}
+
 // After a folded restriction from level l: f_c = R d + N_c(R g) on level
-// l + 1, by the tail kernel as it loads (returns true: the caller passes fc)
-// or by k_fas_rhs.
+// l + 1, by the tail kernel as it loads or by the coarse level's own
+// pre-sweep launch (returns true: the caller passes fc), or by k_fas_rhs.
 template <int MODEL, typename T, bool CORR> bool complete_coarse_rhs(Hier<T>& H, Cycle& K, int l) {
   const int c = l + 1;
-  if (H.L[c].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[c].n, (int)H.L.size() - c, H.tail_lds_max, nullptr))
-    return true;
+  if (level_in_tail<MODEL, T, CORR>(H, K, c) || level_fold_rhs<MODEL, T, CORR>(H, K, c)) return true;
   const Lvl<T>& C = H.L[c];
   const dim3 b = block2(C.n, C.n);
   k_fas_rhs<MODEL, T, CORR><<<grid2(C.n, C.n, b), b, 0, K.stream>>>(C, H.P);
@@ -226,8 +266,9 @@ template <int MODEL, typename T, bool CORR> bool complete_coarse_rhs(Hier<T>& H,
 // One visit to a large level with the tiled kernels: pre-sweeps (the last also
 // writes d = f - N(g)), the fused FAS restriction, the coarser levels, the
 // prolongation fused into the first post-sweep, post-sweeps.  The iterate
-// starts and ends in L.g.
-template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle& K, int l) {
+// starts and ends in L.g.  fc: f still holds R d (level_fold_rhs), completed
+// by the pre-sweep launch into L.d, where the post-sweeps read it.
+template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle& K, int l, bool fc_here = false) {
   constexpr int NCm = NC<MODEL>::value;
   const Lvl<T>& L = H.L[l];
   const Lvl<T>& C = H.L[l + 1];
@@ -236,7 +277,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
   bool fc = false;
   if (level_fused(H, K, l)) {
     // the last pre-sweep launch restricts g and d into the coarse level
-    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 3);
+    tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, fc_here ? 4 : 3);
     fc = complete_coarse_rhs<MODEL, T, CORR>(H, K, l);
   } else {
     tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu1, false, cur, other, 1);
@@ -255,7 +296,7 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
     // post-sweeps; on the finest level of the FP64 solve the last one also
     // leaves the partial sums of the stop-test residual
     const bool norm = (l == 0 && !CORR);
-    const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0);
+    const int blocks = tiled_sweeps<MODEL, T, CORR>(H, K, l, K.nu2, true, cur, other, norm ? 2 : 0, fc_here);
     if (norm) K.norm_partials = blocks;
   } else {
     if constexpr (!CORR && !walls(MODEL)) {
@@ -270,12 +311,12 @@ template <int MODEL, typename T, bool CORR> void vcycle_tiled(Hier<T>& H, Cycle&
 
 template <int MODEL, typename T, bool CORR> void vcycle_rec(Hier<T>& H, Cycle& K, int l, bool fc) {
   const int nlev = (int)H.L.size(), last = nlev - 1;
-  if (H.L[l].n <= K.tail_n && tail_plan<MODEL, T, CORR>(H.L[l].n, nlev - l, H.tail_lds_max, nullptr)) {
+  if (level_in_tail<MODEL, T, CORR>(H, K, l)) {
     tail_launch<MODEL, T, CORR>(H, K, l, fc);
     return;
   }
-  if (K.use_tiles && l < last && H.L[l].n >= TILE_X && H.L[l + 1].n >= RTILE) {
-    vcycle_tiled<MODEL, T, CORR>(H, K, l);
+  if (level_tiled<MODEL, T, CORR>(H, K, l)) {
+    vcycle_tiled<MODEL, T, CORR>(H, K, l, fc);
     return;
   }
   // (a channel always runs the tiled kernels and the tail: its hierarchy is

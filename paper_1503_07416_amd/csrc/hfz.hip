@@ -786,6 +786,12 @@ int init_handle(hfz_handle* hd, const hfz_params& p, void* dev_ws, void* hip_str
       constexpr int M = decltype(m)::value;
       tune_tile_shapes<M, double, false>(hd->H, K, !by_kernel);
       if (p.precision == HFZ_MIXED) tune_tile_shapes<M, float, true>(hd->H32, K, !by_kernel);
+      if (std::getenv("HFZ_VERBOSE")) {
+        std::fprintf(stderr, "hfz: right-hand side completed by the pre-sweep launch:");
+        for (int l = 0; l < (int)hd->H.L.size(); ++l)
+          std::fprintf(stderr, " %d", (int)level_fold_rhs<M, double, false>(hd->H, K, l));
+        std::fprintf(stderr, "\n");
+      }
     });
   }
   if (const char* e = std::getenv("HFZ_MP_INNER")) hd->mp_inner = std::max(1, std::min(8, std::atoi(e)));

@@ -18,8 +18,10 @@
 // The V-cycle can fold the FAS restriction into these launches (RES = 3
 // below): the last pre-smoothing launch of a level also forms R g and R d on
 // the coarse nodes under its block; f_c = R d + N_c(R g) is then completed
-// on the coarse grid (k_fas_rhs, or the tail kernel as it loads).  The
-// arithmetic is the restriction kernels' (restrict.hpp).
+// on the coarse grid (k_fas_rhs, or the tail kernel as it loads), or by the
+// coarse level's own pre-smoothing launch (RES = 4) when that launch folds
+// its restriction too.  The arithmetic is the restriction kernels'
+// (restrict.hpp) and k_fas_rhs's.
 #pragma once
 #include "kernels.hpp"
 #include "restrict.hpp"
@@ -60,7 +62,13 @@ template <typename T> struct Fld {
 // correction form also restricts its base state into C.bg).  A residual
 // needs the swept values one node beyond the block, hence the extra halo
 // node; R d needs d one node below and left of the block as well, hence two
-// for RES = 3.
+// for RES = 3.  RES = 4 is RES = 3 on a level whose right-hand side still holds
+// R d from the restriction into it: the launch first completes f = R d + N(g)
+// (g is R g before the first half sweep, so this is k_fas_rhs's value) in LDS
+// over the nodes it updates, sweeps and restricts with that f, and writes the
+// completed f of its block to L.d, from which the level's post-smoothing
+// launch reads it (L.f itself stays R d: the neighbouring workgroups read their
+// halo of it in the same launch).
 // res_on false skips the residual (a batched launch whose instance has this
 // level below its finest; uniform over the workgroup).
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
@@ -71,8 +79,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
   constexpr int TILE_X = kTileShapes[TS].tx, TILE_Y = kTileShapes[TS].ty, TILE_THREADS = kTileShapes[TS].nt;
-  static_assert(!(RES == 3 && (walls(MODEL) || PRO)), "fused restriction: periodic pre-sweeps");
-  constexpr int H = 2 * NSW + (RES == 3 ? 2 : (RES ? 1 : 0));
+  constexpr bool FR = RES == 3 || RES == 4;  // the FAS restriction folded in
+  constexpr bool FC = RES == 4;              // and this level's f completed first
+  static_assert(!(FR && (walls(MODEL) || PRO)), "fused restriction: periodic pre-sweeps");
+  constexpr int H = 2 * NSW + (FR ? 2 : (RES ? 1 : 0));
   constexpr int RX = TILE_X + 2 * H, RY = TILE_Y + 2 * H, RN = RX * RY;
   // coarse patch under the region (prolongation staging)
   constexpr int CRX = RX / 2 + 2, CRY = RY / 2 + 2, CRN = CRX * CRY;
@@ -92,7 +102,11 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   __shared__ T sb[NB][CORR ? RN : 1];
   // RES = 3: d on the block and one node below and left of it
   constexpr int DX = TILE_X + 1, DN = DX * (TILE_Y + 1);
-  __shared__ T sd[NCm][RES == 3 ? DN : 1];
+  __shared__ T sd[NCm][FR ? DN : 1];
+  // RES = 4: the completed f and omega^k over the region (the sweeps read
+  // them from LDS, indexed like g)
+  __shared__ T sf[NCm][FC ? RN : 1];
+  __shared__ T som[(FC && RK) ? RN : 1];
   // se (the coarse correction, read only while loading) and sm (the
   // potential, written only after the load) share one LDS array
   constexpr int SE = PRO ? NCm * CRN : 0, SM = PM ? RN : 0;
@@ -130,6 +144,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
     const int gp = (gj << lg) + gi;
     if constexpr (RK) srk[w] = L.rk[gp];
+    if constexpr (FC && RK) som[w] = L.om[gp];
     if constexpr (CORR) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) sb[c][w] = L.bg[c][gp];
@@ -185,6 +200,30 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   const T* bl[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) bl[c] = sb[(CORR && c < NB) ? c : 0];
+  const T* fl[NCm];
+#pragma unroll
+  for (int c = 0; c < NCm; ++c) fl[c] = sf[c];
+  if constexpr (FC) {
+    // f = R d + N(R g) on the region less its outer ring (the nodes the first
+    // half sweep may update), with k_fas_rhs's rows and operand order
+    constexpr int BX = RX - 2, BN = BX * (RY - 2);
+    for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
+      const int r = w / BX, t = w - r * BX;
+      const int lp = (1 + r) * RX + 1 + t;
+      const int gp = (((y0 + 1 + r) & m) << lg) + ((x0 + 1 + t) & m);
+      Nbr q;
+      q.p = lp;
+      q.e = lp + 1;
+      q.w = lp - 1;
+      q.n = lp + RX;
+      q.s = lp - RX;
+      T nv[NCm];
+      rows_any<MODEL, T, CORR>(gl, bl, srk, som, q, lp, L.k, P, nv);
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) sf[c][lp] = L.f[c][gp] + nv[c];
+    }
+    __syncthreads();
+  }
   for (int k = 1; k <= 2 * NSW; ++k) {
     const int colour = (k - 1) & 1;
     if constexpr (PM) {
@@ -216,7 +255,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.s = q.p - RX;
       const int pf = ((WL ? (y0 + ly) : ((y0 + ly) & m)) << lg) + ((x0 + lx) & m);
       T out[NCm];
-      update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
+      if constexpr (FC)
+        update_any<MODEL, T, CORR, PM>(gl, fl, bl, srk, som, q, q.p, L.k, P, out, sm);
+      else
+        update_any<MODEL, T, CORR, PM>(gl, L.f, bl, srk, L.om, q, pf, L.k, P, out, sm);
 #pragma unroll
       for (int c = 0; c < NCm; ++c) sg[c][q.p] = out[c];
       if constexpr (WL) {
@@ -236,8 +278,8 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   if constexpr (PM && RES != 0) {
     if (res_on) {
       // M on the nodes the residual rows read: the owned block and its
-      // one-node ring (RES = 3: the block of d and its ring)
-      constexpr int E0 = RES == 3 ? 2 : 1, BX = TILE_X + E0 + 1, BN = BX * (TILE_Y + E0 + 1);
+      // one-node ring (RES = 3, 4: the block of d and its ring)
+      constexpr int E0 = FR ? 2 : 1, BX = TILE_X + E0 + 1, BN = BX * (TILE_Y + E0 + 1);
       for (int w = threadIdx.x; w < BN; w += TILE_THREADS) {
         const int r = w / BX, t = w - r * BX;
         const int lp = (H - E0 + r) * RX + H - E0 + t;
@@ -254,6 +296,10 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     const int gp = (gy << lg) + ((x0 + H + tx) & m);
 #pragma unroll
     for (int c = 0; c < NCm; ++c) gout.c[c][gp] = sg[c][lp];
+    if constexpr (FC) {
+#pragma unroll
+      for (int c = 0; c < NCm; ++c) L.d[c][gp] = sf[c][lp];
+    }
     if constexpr (WL) {
       // the top wall row n belongs to no block: the block owning row n - 1 writes it
       if (gy == nn - 1) {
@@ -290,7 +336,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
     }
   }
-  if constexpr (RES == 3) {
+  if constexpr (FR) {
     // d = f - N(g) on the block and one node below and left of it (the fine
     // nodes under the 9-point stencils of the block's coarse nodes)
     for (int w = threadIdx.x; w < DN; w += TILE_THREADS) {
@@ -304,9 +350,15 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       q.n = lp + RX;
       q.s = lp - RX;
       T nv[NCm];
-      rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
+      if constexpr (FC) {
+        rows_any<MODEL, T, CORR, PM>(gl, bl, srk, som, q, lp, L.k, P, nv, sm);
 #pragma unroll
-      for (int c = 0; c < NCm; ++c) sd[c][w] = L.f[c][gp] - nv[c];
+        for (int c = 0; c < NCm; ++c) sd[c][w] = sf[c][lp] - nv[c];
+      } else {
+        rows_any<MODEL, T, CORR, PM>(gl, bl, srk, L.om, q, gp, L.k, P, nv, sm);
+#pragma unroll
+        for (int c = 0; c < NCm; ++c) sd[c][w] = L.f[c][gp] - nv[c];
+      }
     }
     __syncthreads();
     // the block's coarse nodes: R g into C.g and C.g0, R d into C.f
@@ -331,6 +383,28 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
       }
     }
   }
+}
+
+// Whether the RES = 4 form of two fused sweeps in tile shape TS fits the LDS
+// of a compute unit (160 KiB): the kernel body's arrays for NSW = 2, PRO =
+// false, RES = 4 (large tiles do not fit; there k_fas_rhs completes f).
+template <int MODEL, typename T, bool CORR, int TS> constexpr bool fold_rhs_fits() {
+  constexpr int NCm = NC<MODEL>::value, NB = CORR ? NBase<MODEL>::value : 1;
+  constexpr bool RK = NCoef<MODEL>::value > 0, PM = MODEL == CDFT;
+  constexpr int H = 2 * 2 + 2, TX = kTileShapes[TS].tx, TY = kTileShapes[TS].ty;
+  constexpr size_t RN = (size_t)(TX + 2 * H) * (TY + 2 * H), DN = (size_t)(TX + 1) * (TY + 1);
+  constexpr size_t vals = NCm * RN + (RK ? RN : 1) + NB * (CORR ? RN : 1) + NCm * DN + NCm * RN +
+                          (RK ? RN : 1) + (PM ? RN : 1);
+  return vals * sizeof(T) <= 160 * 1024;
+}
+
+template <int MODEL, typename T, bool CORR> bool fold_rhs_fits_shape(int ts) {
+  constexpr bool fits[NUM_TILE_SHAPES] = {
+      fold_rhs_fits<MODEL, T, CORR, 0>(), fold_rhs_fits<MODEL, T, CORR, 1>(), fold_rhs_fits<MODEL, T, CORR, 2>(),
+      fold_rhs_fits<MODEL, T, CORR, 3>(), fold_rhs_fits<MODEL, T, CORR, 4>(), fold_rhs_fits<MODEL, T, CORR, 5>(),
+      fold_rhs_fits<MODEL, T, CORR, 6>(), fold_rhs_fits<MODEL, T, CORR, 7>(), fold_rhs_fits<MODEL, T, CORR, 8>(),
+      fold_rhs_fits<MODEL, T, CORR, 9>()};
+  return ts >= 0 && ts < NUM_TILE_SHAPES && fits[ts];
 }
 
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>

@@ -167,7 +167,10 @@ float time_schedule(Hier<T>& H, Cycle& K, int l, int fuse, int reps) {
 // with the FAS restriction to level l + 1 after them: folded into the sweep
 // launch (fused, with f_c completed by k_fas_rhs unless the next level is the
 // tail, whose completion costs a phase of the tail kernel) or as the
-// restriction launch of variant rs.
+// restriction launch of variant rs.  Where level l's own right-hand side
+// arrives as R d and the folded launch could complete it (RES = 4), the two
+// candidates are a RES = 4 launch against k_fas_rhs on level l followed by
+// the separate pre-sweep and restriction launches.
 template <int MODEL, typename T, bool CORR>
 float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int reps) {
   const Lvl<T>& L = H.L[l];
@@ -175,14 +178,19 @@ float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int
   const Fld<T> a = fld<T>(L.g), b = fld<T>(L.gb);
   const int ts = H.tile_shape[l];
   const bool tail_next = C.n <= K.tail_n;
+  const bool rhs_here = fold_rhs_possible<MODEL, T, CORR>(H, K, l);
   auto pass = [&]() {
     if (fused) {
-      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 3, ts);
+      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, rhs_here ? 4 : 3, ts);
       if (!tail_next) {
         const dim3 bl = block2(C.n, C.n);
         k_fas_rhs<MODEL, T, CORR><<<grid2(C.n, C.n, bl), bl, 0, K.stream>>>(C, H.P);
       }
     } else {
+      if (rhs_here) {
+        const dim3 bl = block2(L.n, L.n);
+        k_fas_rhs<MODEL, T, CORR><<<grid2(L.n, L.n, bl), bl, 0, K.stream>>>(L, H.P);
+      }
       tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
       Lvl<T> F = L;
       for (int c = 0; c < 5; ++c) F.g[c] = b.c[c];
@@ -234,6 +242,9 @@ template <typename F> int pick_fastest(int count, F&& time, const char* what = n
 // above the tail).  HFZ_RESTRICT=<variant> forces a restriction variant where
 // it fits; HFZ_FUSE=0 / 1 keeps the restriction launches separate / folds
 // them into the sweeps wherever it can (default: whichever times faster).
+// HFZ_FOLD_RHS=0 leaves the completion of a folded level's coarse right-hand
+// side to k_fas_rhs everywhere (default: the coarse level's RES = 4 launch
+// where level_fold_rhs allows it).
 // With time_them false nothing is launched: a level takes the choices cached
 // for its size in this process, else shape 0, variant 0, fused sweeps and a
 // separate restriction.
@@ -243,6 +254,8 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
   H.restrict_shape.assign(nlev, 0);
   H.sweep_fuse.assign(nlev, 2);
   H.fused.assign(nlev, 0);
+  H.fold_rhs = true;
+  if (const char* e = std::getenv("HFZ_FOLD_RHS")) H.fold_rhs = std::atoi(e) != 0;
   int forced_r = -1, forced_f = -1, forced_x = -1;
   if (const char* e = std::getenv("HFZ_FUSE")) forced_x = std::atoi(e) != 0 ? 1 : 0;
   if constexpr (walls(MODEL)) forced_x = 0;  // the channel's wall rows: the direct restriction kernel

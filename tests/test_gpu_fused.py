@@ -3,8 +3,9 @@
 f_c = R d + N_c(R g) is completed on the coarse grid by k_fas_rhs, or by the
 tail kernel as it loads) against the same V-cycle with separate restriction
 launches (HFZ_FUSE=0) and against the oracle, for every model, cycle shapes,
-coarsest grids, sweep schedules and tile shapes; and each separate
-restriction variant against the oracle."""
+coarsest grids, sweep schedules and tile shapes; each separate restriction
+variant against the oracle; and a coarse level's right-hand side completed by
+its own pre-sweep launch (RES = 4) against k_fas_rhs (HFZ_FOLD_RHS=0)."""
 import numpy as np
 import pytest
 
@@ -150,3 +151,63 @@ def test_fused_mixed_precision_steps(model, monkeypatch):
     for x, y in zip(out[0][1], out[1][1]):
         if np.abs(y).max() > 0:
             assert rel_err(x, y) < 1e-9
+
+
+FOLD_CASES = [("pfc", 256, {}), ("cdft", 256, {}), ("pfc_gf", 256, {}), ("cdft_gf", 128, {}),
+              ("pfc", 128, dict(coarsest_n=16)), ("cdft", 128, dict(nu1=2, nu2=1))]
+
+
+@pytest.mark.parametrize("model,n,kw", FOLD_CASES, ids=[f"{m}-{n}-{'-'.join(f'{k}{v}' for k, v in kw.items())}"
+                                                        for m, n, kw in FOLD_CASES])
+@pytest.mark.parametrize("tile", ["3", "6"])
+def test_fold_rhs_equals_fas_rhs_launch(model, n, kw, tile, monkeypatch, capfd):
+    """With every restriction folded (HFZ_FUSE=1) the coarse tiled levels
+    complete f_c = R d + N_c(R g) in their own pre-sweep launch (RES = 4, the
+    completed f read back by their post-sweep launch); HFZ_FOLD_RHS=0 leaves
+    it to k_fas_rhs.  The same rows in the same order: three V-cycles agree
+    to rounding, and both agree with the oracle's."""
+    cfg, rho, u, v = case(model, n, seed=9, **kw)
+    print(f"fold-rhs {model} {n} {kw} tile {tile}", flush=True)
+    env = {"HFZ_FUSE": "1", "HFZ_TILE": tile, "HFZ_VERBOSE": "1"}
+    capfd.readouterr()
+    folded = cycles(cfg, rho, u, v, 3, env, monkeypatch)
+    err = capfd.readouterr().err
+    line = [x for x in err.splitlines() if "completed by the pre-sweep launch" in x]
+    assert line and " 1" in line[-1].split(":")[-1], err
+    launch = cycles(cfg, rho, u, v, 3, dict(env, HFZ_FOLD_RHS="0"), monkeypatch)
+    for k, (a, b) in enumerate(zip(folded, launch)):
+        for c, (x, y) in enumerate(zip(a, b)):
+            assert rel_err(x, y) < 1e-13, (k, c, rel_err(x, y))
+    ora = oracle_cycles(cfg, rho, u, v, 3)
+    for k, (a, b) in enumerate(zip(folded, ora)):
+        errs = [rel_err(x, y) for x, y in zip(a, b)]
+        assert max(errs) < 1e-11, (k, errs)
+
+
+@pytest.mark.parametrize("model,precision", [("pfc", "fp64"), ("cdft", "fp64"), ("pfc", "mixed"),
+                                             ("cdft", "mixed")])
+def test_fold_rhs_steps(model, precision, monkeypatch):
+    """Whole steps (graphs, device stop test; mixed: the FP32 correction form)
+    with the coarse right-hand sides completed in the pre-sweep launches
+    against k_fas_rhs: the same V-cycle counts, states within 1e-12 (FP64) or
+    1e-9 (mixed)."""
+    import paper_1503_07416_amd as pkg
+    cfg, rho, u, v = case(model, 256, seed=12, precision=precision, coarsest_n=16)
+    out = []
+    for fold in ("1", "0"):
+        monkeypatch.setenv("HFZ_FUSE", "1")
+        monkeypatch.setenv("HFZ_TILE", "4")
+        monkeypatch.setenv("HFZ_FOLD_RHS", fold)
+        sim = pkg.Simulation(cfg)
+        sim.set_state(rho, u, v)
+        st = sim.step(3)
+        assert st.residual_last <= cfg.tol
+        out.append((st.cycles_total, [np_(x) for x in sim.get_state()]))
+    tol = 1e-12 if precision == "fp64" else 1e-9
+    if precision == "fp64":
+        assert out[0][0] == out[1][0]
+    else:
+        assert abs(out[0][0] - out[1][0]) <= 3
+    for x, y in zip(out[0][1], out[1][1]):
+        if np.abs(y).max() > 0:
+            assert rel_err(x, y) < tol
