@@ -288,10 +288,12 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int count, in
 __global__ void k_reduce_stop(const double* __restrict__ partial, int count, double scale, double tol,
                               double* __restrict__ result, int* ctl, int counted) {
   __shared__ double lds[16];
-  if (ctl[0] != 0) return;
+  // the flag is read with the partials (a vector load) and tested after the sum
+  const int stopped = stop_flag(ctl);
   double acc = 0.0;
   for (int t = threadIdx.x; t < count; t += blockDim.x) acc += partial[t];
   const double r = block_sum(acc, lds);
+  if (stop_set(stopped)) return;
   if (threadIdx.x == 0) {
     const double r2 = scale * r;
     result[0] = r2;

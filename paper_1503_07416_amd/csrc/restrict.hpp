@@ -159,7 +159,9 @@ template <typename T> __device__ __forceinline__ T fw9l(const T* f, int p, int s
 }
 
 template <int MODEL, typename T, bool CORR, int RT, int NT>
-__device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
+__device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P,
+                                                    const int* halt = nullptr) {
+  const int hv = stop_flag(halt);  // tested after the load phase (nothing is stored before)
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;
@@ -198,6 +200,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
     }
   }
   __syncthreads();
+  if (stop_set(hv)) return;
   for (int w = threadIdx.x; w < CN; w += NT) {
     const int ly = w / CX, lx = w - ly * CX;
     const int fl = (1 + 2 * ly) * FX + 1 + 2 * lx;  // fine node under coarse (X0 + lx, Y0 + ly)
@@ -244,8 +247,7 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
 
 template <int MODEL, typename T, bool CORR, int RT, int NT>
 __global__ __launch_bounds__(NT) void k_restrict_fas_staged(Lvl<T> F, Lvl<T> C, Phys<T> P) {
-  if (halted(P.halt)) return;
-  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, C, P);
+  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, C, P, P.halt);
 }
 
 // Batched staged form (instance blockIdx.z; the fine iterate in g, inb = 0,

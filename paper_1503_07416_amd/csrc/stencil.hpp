@@ -52,6 +52,21 @@ template <typename T> struct Phys {
 
 __device__ __forceinline__ bool halted(const int* flag) { return flag != nullptr && *flag != 0; }
 
+// The same flag read as a vector load (an agent-scope relaxed atomic load,
+// which the compiler never turns into a scalar one), for kernels that issue it
+// with their first data loads and test it (stop_set) before their first
+// store.  halted() reads it with a scalar load at the kernel's start, and the
+// scalar loads are waited for together, so the kernel-argument loads that
+// address the data would wait for the flag: one more memory round trip ahead
+// of every load of the kernel.
+// (A missing flag reads a zero of its own: a select, not a branch, so the
+// kernel-argument loads are not split in two rounds either.)
+static __device__ int kNoStopFlag = 0;
+__device__ __forceinline__ int stop_flag(const int* flag) {
+  return __hip_atomic_load(flag != nullptr ? flag : &kNoStopFlag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool stop_set(int v) { return __builtin_amdgcn_readfirstlane(v) != 0; }
+
 // Stencil coefficients of one level: s/(4h), s/(2h), 1/h^2.
 template <typename T> struct Coef {
   T c4, c2, ih2;

@@ -321,7 +321,10 @@ __device__ __forceinline__ void tail_prolong(const Lvl<T> F, const Lvl<T> C, con
 }
 
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P) {
+__device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P, const int* halt = nullptr) {
+  // the V-cycle loop's stop flag, read with the loads below and tested after
+  // them (nothing is stored before)
+  const int hv = stop_flag(halt);
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 0;
   constexpr int NR = NCoef<MODEL>::value;
@@ -372,6 +375,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
     }
   }
   __syncthreads();
+  if (stop_set(hv)) return;
   if constexpr (!walls(MODEL)) {
     if (A.fc) tail_complete_rhs<MODEL, T, CORR>(tail_view<NCm, NB, NR, false>(S[0]), P, sm);
   }
@@ -406,8 +410,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& A, const Phys<T>& P
 
 template <int MODEL, typename T, bool CORR>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TailArgs<T> A, Phys<T> P) {
-  if (halted(P.halt)) return;
-  tail_body<MODEL, T, CORR>(A, P);
+  tail_body<MODEL, T, CORR>(A, P, P.halt);
 }
 
 // Batched form: workgroup z runs the tail of instance z, whose level

@@ -70,11 +70,14 @@ template <typename T> struct Fld {
 // launch reads it (L.f itself stays R d: the neighbouring workgroups read their
 // halo of it in the same launch).
 // res_on false skips the residual (a batched launch whose instance has this
-// level below its finest; uniform over the workgroup).
+// level below its finest; uniform over the workgroup).  halt: the V-cycle
+// loop's stop flag, read with the first loads and tested after the load phase
+// (nothing is stored before it).
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& gin, const Fld<T>& gout,
                                                  const Lvl<T>& C, const Phys<T>& P, double* partial,
-                                                 bool res_on = true) {
+                                                 bool res_on = true, const int* halt = nullptr) {
+  const int hv = stop_flag(halt);
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;  // the rows read rho^k
@@ -180,6 +183,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     }
   }
   __syncthreads();
+  if (stop_set(hv)) return;
   // LDS rows of the channel's walls (valid when inside 0..RY-1)
   const int r0 = -y0, rn = nn - y0;
   auto wall_refresh = [&]() {
@@ -410,8 +414,7 @@ template <int MODEL, typename T, bool CORR> bool fold_rhs_fits_shape(int ts) {
 template <int MODEL, typename T, int NSW, bool PRO, int RES, bool CORR, int TS = 0>
 __global__ __launch_bounds__(kTileShapes[TS].nt) void k_sweeps_tile(Lvl<T> L, Fld<T> gin, Fld<T> gout, Lvl<T> C,
                                                                     Phys<T> P, double* partial) {
-  if (halted(P.halt)) return;
-  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial);
+  sweeps_tile_body<MODEL, T, NSW, PRO, RES, CORR, TS>(L, gin, gout, C, P, partial, true, P.halt);
 }
 
 // Batched form: instance blockIdx.z of the instances that have a level of this
