@@ -85,8 +85,9 @@
  *                         that folds its restriction too and its tiles fit LDS)
  *    HFZ_MP_INNER=<1..8>  FP32 V-cycles per outer FP64 iteration (mixed)
  *    HFZ_BATCH_TILE=<0|2> tile shape of the batched smoother
- *    HFZ_BATCH_RESTRICT=0 batched FAS restriction by the direct kernel (default:
- *                         the staged one)
+ *    HFZ_BATCH_RESTRICT=<0..3> batched FAS restriction: 0 the direct kernel, 1-3
+ *                         the staged one with coarse tiles of 8 / 256 threads,
+ *                         16 / 256, 16 / 512 (default 3)
  *    HFZ3_TILES=<n>       smallest 3D level swept by the tiled kernel (0: none)
  *    HFZ3_TAIL=0          no one-workgroup tail in 3D
  *    HFZ_VERBOSE=1        the choices made, on stderr

@@ -1192,7 +1192,10 @@ struct hfz_batch {
   int count = 0;
   hfz_params p{};  // model, precision, nu1, nu2, coarsest_n, coarse_sweeps, continuity_fix: shared
   int tile_force = -1;  // smoother tile shape forced by HFZ_BATCH_TILE at init (-1: by level size)
-  bool restrict_staged = true;  // staged FAS restriction (HFZ_BATCH_RESTRICT=0: the direct kernel)
+  // FAS restriction (HFZ_BATCH_RESTRICT): 3 the staged kernel with coarse
+  // tiles of 16 and 512 threads; 2 the same with 256 threads, 1 with tiles of
+  // 8 and 256 threads; 0 the direct kernel
+  int restrict_mode = 3;
   hipStream_t stream = nullptr;
   std::vector<hfz_handle*> inst;  // by slot
   std::vector<int> slot_of;       // user index -> slot
@@ -1379,9 +1382,15 @@ void bvcycle_depth(hfz_batch* B, Lvl<T>* D, Lvl<T>* Tl, Phys<T>* Ps, size_t lds_
     }
   };
   sweeps(K.nu1, false, 1);
-  // the FAS restriction: the staged kernel (coarse tiles of 8 through LDS), or
-  // the direct one (HFZ_BATCH_RESTRICT=0)
-  if (B->restrict_staged && nc % 8 == 0)
+  // the FAS restriction: the staged kernel (coarse tiles through LDS), or the
+  // direct one (HFZ_BATCH_RESTRICT=0)
+  if (B->restrict_mode == 2 && nc % 16 == 0)
+    k_restrict_fas_staged_b<MODEL, T, CORR, 16, 256><<<dim3(nc / 16, nc / 16, cz), 256, 0, K.stream>>>(
+        Dl, Dc, Ps, B->active, inb);
+  else if (B->restrict_mode == 3 && nc % 16 == 0)
+    k_restrict_fas_staged_b<MODEL, T, CORR, 16, 512><<<dim3(nc / 16, nc / 16, cz), 512, 0, K.stream>>>(
+        Dl, Dc, Ps, B->active, inb);
+  else if (B->restrict_mode != 0 && nc % 8 == 0)
     k_restrict_fas_staged_b<MODEL, T, CORR, 8, 256><<<dim3(nc / 8, nc / 8, cz), 256, 0, K.stream>>>(
         Dl, Dc, Ps, B->active, inb);
   else
@@ -1540,7 +1549,7 @@ int hfz_batch_init(const hfz_params* params, int count, void* dev_ws, size_t ws_
   B->count = count;
   B->p = params[G.order[0]];
   if (const char* e = std::getenv("HFZ_BATCH_TILE")) B->tile_force = std::atoi(e);
-  if (const char* e = std::getenv("HFZ_BATCH_RESTRICT")) B->restrict_staged = std::atoi(e) != 0;
+  if (const char* e = std::getenv("HFZ_BATCH_RESTRICT")) B->restrict_mode = std::max(0, std::min(3, std::atoi(e)));
   B->stream = static_cast<hipStream_t>(hip_stream);
   char* base = static_cast<char*>(dev_ws);
   B->slot_of.assign(count, 0);

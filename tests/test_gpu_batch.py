@@ -193,22 +193,24 @@ def test_uneven_batch_release_and_refill():
                                              ("cdft", "mixed")])
 def test_batch_restriction_variants_agree(model, precision, monkeypatch):
     """The batched FAS restriction runs the staged kernel (the fine data under
-    a coarse tile through LDS); HFZ_BATCH_RESTRICT=0 (read at batch init)
-    runs the direct kernel.  The same arithmetic in the same order: three
-    steps of an uneven batch agree to rounding, with the same V-cycle
-    counts."""
+    a coarse tile through LDS; HFZ_BATCH_RESTRICT=3, the default: coarse tiles
+    of 16 and 512 threads; 2: 16 and 256; 1: 8 and 256) or the direct kernel
+    (0); the variable is read at batch init.  The same arithmetic in the same
+    order: three steps of an uneven batch agree to rounding, with the same
+    V-cycle counts."""
     import paper_1503_07416_amd as pkg
     inst = uneven(model, [64, 256, 32, 128, 256], precision, seed=17)
     out = {}
-    for staged in ("1", "0"):
-        monkeypatch.setenv("HFZ_BATCH_RESTRICT", staged)
+    for mode in ("3", "2", "1", "0"):
+        monkeypatch.setenv("HFZ_BATCH_RESTRICT", mode)
         B = pkg.Batch([c for c, _, _, _ in inst])
         for i, (c, r, u, v) in enumerate(inst):
             B.set_state(i, r, u, v)
         stats = B.step(3)
-        out[staged] = ([s.cycles_total for s in stats], [[np_(x) for x in B.get_state(i)] for i in range(len(inst))])
+        out[mode] = ([s.cycles_total for s in stats], [[np_(x) for x in B.get_state(i)] for i in range(len(inst))])
         B.close()
-    assert out["1"][0] == out["0"][0]
-    for a, b in zip(out["1"][1], out["0"][1]):
-        for x, y in zip(a, b):
-            assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-300)
+    for mode in ("3", "2", "1"):
+        assert out[mode][0] == out["0"][0], mode
+        for a, b in zip(out[mode][1], out["0"][1]):
+            for x, y in zip(a, b):
+                assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-300), mode
