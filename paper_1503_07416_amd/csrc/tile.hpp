@@ -117,8 +117,16 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   T(*se)[CRN] = reinterpret_cast<T(*)[CRN]>(sx);
   T* sm = sx;
   const int m = L.n - 1, lg = L.lg, nn = L.n;
+  // XCD-contiguous tile numbering: the workgroups of a launch are dealt to the
+  // 8 XCDs in turn, and tile tb = (b % 8) (nb / 8) + b / 8 of workgroup b gives
+  // each XCD a contiguous band of tile rows, whose shared halos are then read
+  // through one L2 (tb is also the index of the block's stop-test partial sum)
+  const int gx = (int)gridDim.x, nb = gx * (int)gridDim.y;
+  const int bid = (int)blockIdx.y * gx + (int)blockIdx.x;
+  const int tb = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int bx = tb % gx, by = tb / gx;
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
-  const int x0 = (int)blockIdx.x * TILE_X - H, y0 = (int)blockIdx.y * TILE_Y - H;
+  const int x0 = bx * TILE_X - H, y0 = by * TILE_Y - H;
   const int X0c = x0 >> 1, Y0c = y0 >> 1;  // floor halves (arithmetic shift)
   if constexpr (PRO) {
     const int mc = C.n - 1;
@@ -337,7 +345,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     if (res_on) {
       __shared__ double red[TILE_THREADS / 64];
       const double r = block_sum(acc, red);
-      if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+      if (threadIdx.x == 0) partial[tb] = r;
     }
   }
   if constexpr (FR) {
@@ -367,7 +375,7 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
     __syncthreads();
     // the block's coarse nodes: R g into C.g and C.g0, R d into C.f
     constexpr int CX = TILE_X / 2, CN = CX * (TILE_Y / 2);
-    const int I0 = (int)blockIdx.x * CX, J0 = (int)blockIdx.y * (TILE_Y / 2);
+    const int I0 = bx * CX, J0 = by * (TILE_Y / 2);
     for (int w = threadIdx.x; w < CN; w += TILE_THREADS) {
       const int cy = w / CX, cx = w - cy * CX;
       const int pc = ((J0 + cy) << C.lg) + I0 + cx;
