@@ -235,17 +235,21 @@ template <int MODEL, typename T, bool CORR> bool level_tiled(const Hier<T>& H, c
          H.L[l].n >= TILE_X && H.L[l + 1].n >= RTILE;
 }
 
-// Whether tiled level l, its right-hand side left as R d by a restriction
-// folded into level l - 1, can complete it in its own pre-sweep launch when
-// that launch folds its restriction too: one launch of two sweeps (nu1 = 2)
-// in a tile shape whose RES = 4 arrays fit the LDS.
-template <int MODEL, typename T, bool CORR> bool fold_rhs_possible(const Hier<T>& H, const Cycle& K, int l) {
+// Whether tiled level l (below the finest), given its right-hand side as R d,
+// could complete it in its own pre-sweep launch if that launch folded its
+// restriction too: one launch of two sweeps (nu1 = 2) in a tile shape whose
+// RES = 4 arrays fit the LDS.
+template <int MODEL, typename T, bool CORR> bool fold_rhs_capable(const Hier<T>& H, const Cycle& K, int l) {
   if constexpr (walls(MODEL)) return false;
-  if (!H.fold_rhs || l < 1 || !level_fused(H, K, l - 1) || !level_tiled<MODEL, T, CORR>(H, K, l)) return false;
+  if (!H.fold_rhs || l < 1 || !level_tiled<MODEL, T, CORR>(H, K, l)) return false;
   const int fuse = l < (int)H.sweep_fuse.size() ? H.sweep_fuse[l] : 2;
   int ts = l < (int)H.tile_shape.size() ? H.tile_shape[l] : 0;
   if (!tile_shape_fits(ts, H.L[l].n)) ts = 0;
   return K.nu1 == 2 && fuse >= 2 && fold_rhs_fits_shape<MODEL, T, CORR>(ts);
+}
+// ... and whether it gets it as R d: the restriction into it is folded.
+template <int MODEL, typename T, bool CORR> bool fold_rhs_possible(const Hier<T>& H, const Cycle& K, int l) {
+  return fold_rhs_capable<MODEL, T, CORR>(H, K, l) && level_fused(H, K, l - 1);
 }
 template <int MODEL, typename T, bool CORR> bool level_fold_rhs(const Hier<T>& H, const Cycle& K, int l) {
   return level_fused(H, K, l) && fold_rhs_possible<MODEL, T, CORR>(H, K, l);

@@ -249,8 +249,10 @@ template <int MODEL, typename T>
 __global__ void k_residual_partial(Lvl<T> L, Phys<T> P, double* __restrict__ partial) {
   if (halted(P.halt)) return;
   __shared__ double lds[16];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int bx, by;
+  const int tb = xcd_block(bx, by);  // XCD-contiguous block numbering
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   double acc = 0.0;
   if (i < L.n && j < L.ny && !(walls(MODEL) && (j == 0 || j == L.n))) {
     constexpr int NCm = NC<MODEL>::value;
@@ -264,7 +266,7 @@ __global__ void k_residual_partial(Lvl<T> L, Phys<T> P, double* __restrict__ par
     }
   }
   const double r = block_sum(acc, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[tb] = r;
 }
 
 // Sums `count` partials (stride `stride` doubles apart, `nq` quantities laid
@@ -387,8 +389,10 @@ template <int MODEL>
 __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double* __restrict__ partial) {
   if (halted(P.halt)) return;
   __shared__ double lds[16];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int bx, by;
+  const int tb = xcd_block(bx, by);  // XCD-contiguous block numbering
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   double acc = 0.0;
   if (i < L.n && j < L.n) {
     constexpr int NCm = NC<MODEL>::value;
@@ -406,7 +410,7 @@ __global__ void k_mp_prepare(Lvl<double> L, Phys<double> P, Lvl<float> E, double
     for (int c = 0; c < NBase<MODEL>::value; ++c) E.bg[c][q.p] = (float)L.g[c][q.p];
   }
   const double r = block_sum(acc, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = r;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[tb] = r;
 }
 
 // After the inner V-cycle: g += e (the FP32 correction added in FP64).

@@ -25,7 +25,8 @@ __device__ __forceinline__ T fw9g(const T* f, int i, int j, int n, int lg) {
 // F.g must point at the current fine iterate and F.d at f - N(g) of it.  In
 // the correction form the coarse base C.bg = R F.bg is written here too.
 template <int MODEL, typename T, bool CORR>
-__device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P) {
+__device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P,
+                                                  bool remap = true) {
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
   constexpr bool RK = NCoef<MODEL>::value > 0;
@@ -39,7 +40,9 @@ __device__ __forceinline__ void restrict_fas_body(const Lvl<T>& F, const Lvl<T>&
   // 1..F.n-1, and f_c only there
   constexpr bool WL = walls(MODEL);
   const int mc = C.n - 1;
-  const int X0 = (int)blockIdx.x * RTILE - 1, Y0 = (int)blockIdx.y * RTILE - 1;
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (remap) xcd_block(bx, by);  // XCD-contiguous block numbering
+  const int X0 = bx * RTILE - 1, Y0 = by * RTILE - 1;
   for (int w = threadIdx.x; w < RN; w += RTILE * RTILE) {
     const int ly = w / RX, lx = w - ly * RX;
     const int I = (X0 + lx) & mc;
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(RTILE* RTILE) void k_restrict_fas_tile_b(const Lvl<
 #pragma unroll
     for (int c = 0; c < 5; ++c) F.g[c] = F.gb[c];
   }
-  restrict_fas_body<MODEL, T, CORR>(F, lvl_global(Cs[z]), Ps[z]);
+  restrict_fas_body<MODEL, T, CORR>(F, lvl_global(Cs[z]), Ps[z], false);
 }
 
 // Staged form: the fine iterate under the stencils of a coarse tile and its
@@ -160,7 +163,7 @@ template <typename T> __device__ __forceinline__ T fw9l(const T* f, int p, int s
 
 template <int MODEL, typename T, bool CORR, int RT, int NT>
 __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T>& C, const Phys<T>& P,
-                                                    const int* halt = nullptr) {
+                                                    const int* halt = nullptr, bool remap = true) {
   const int hv = stop_flag(halt);  // tested after the load phase (nothing is stored before)
   constexpr int NCm = NC<MODEL>::value;
   constexpr int NB = CORR ? NBase<MODEL>::value : 1;
@@ -175,7 +178,9 @@ __device__ __forceinline__ void restrict_fas_staged(const Lvl<T>& F, const Lvl<T
   __shared__ T sb[NB][CORR ? CN : 1];
   __shared__ T srk[RK ? CN : 1];
   const int mc = C.n - 1, mf = F.n - 1;
-  const int X0 = (int)blockIdx.x * RT - 1, Y0 = (int)blockIdx.y * RT - 1;  // coarse ring origin
+  int bx = (int)blockIdx.x, by = (int)blockIdx.y;
+  if (remap) xcd_block(bx, by);                  // XCD-contiguous block numbering
+  const int X0 = bx * RT - 1, Y0 = by * RT - 1;  // coarse ring origin
   const int fx0 = 2 * X0 - 1, fy0 = 2 * Y0 - 1;                              // fine origin of fg
   for (int w = threadIdx.x; w < FN; w += NT) {
     const int ly = w / FX, lx = w - ly * FX;
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_restrict_fas_staged_b(const Lvl<T>* Fs, 
 #pragma unroll
     for (int c = 0; c < 5; ++c) F.g[c] = F.gb[c];
   }
-  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, lvl_global(Cs[z]), Ps[z]);
+  restrict_fas_staged<MODEL, T, CORR, RT, NT>(F, lvl_global(Cs[z]), Ps[z], nullptr, false);
 }
 
 // Restriction variants the tuner chooses from: 0 the direct kernel (coarse

@@ -67,6 +67,21 @@ __device__ __forceinline__ int stop_flag(const int* flag) {
 }
 __device__ __forceinline__ bool stop_set(int v) { return __builtin_amdgcn_readfirstlane(v) != 0; }
 
+// XCD-contiguous numbering of a 2D grid of workgroups (blockIdx.z, if used,
+// numbers independent slices): the workgroups of a launch are dealt to the 8
+// XCDs in turn, and block tb = (b % 8) (nb / 8) + b / 8 for workgroup b of a
+// slice of nb gives each XCD a contiguous band of block rows, whose shared
+// halos are then read through one L2.  Returns tb (a bijection of the slice's
+// blocks; the index of the block's partial sums) and its coordinates.
+__device__ __forceinline__ int xcd_block(int& bx, int& by) {
+  const int gx = (int)gridDim.x, nb = gx * (int)gridDim.y;
+  const int bid = (int)blockIdx.y * gx + (int)blockIdx.x;
+  const int tb = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+  bx = tb % gx;
+  by = tb / gx;
+  return tb;
+}
+
 // Stencil coefficients of one level: s/(4h), s/(2h), 1/h^2.
 template <typename T> struct Coef {
   T c4, c2, ih2;

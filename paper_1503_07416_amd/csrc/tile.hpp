@@ -117,14 +117,9 @@ __device__ __forceinline__ void sweeps_tile_body(const Lvl<T>& L, const Fld<T>& 
   T(*se)[CRN] = reinterpret_cast<T(*)[CRN]>(sx);
   T* sm = sx;
   const int m = L.n - 1, lg = L.lg, nn = L.n;
-  // XCD-contiguous tile numbering: the workgroups of a launch are dealt to the
-  // 8 XCDs in turn, and tile tb = (b % 8) (nb / 8) + b / 8 of workgroup b gives
-  // each XCD a contiguous band of tile rows, whose shared halos are then read
-  // through one L2 (tb is also the index of the block's stop-test partial sum)
-  const int gx = (int)gridDim.x, nb = gx * (int)gridDim.y;
-  const int bid = (int)blockIdx.y * gx + (int)blockIdx.x;
-  const int tb = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
-  const int bx = tb % gx, by = tb / gx;
+  // XCD-contiguous tile numbering (tb also indexes the stop-test partial sum)
+  int bx, by;
+  const int tb = xcd_block(bx, by);
   // x0 + y0 is even for any H, so the colour of region node (lx, ly) is (lx + ly) & 1
   const int x0 = bx * TILE_X - H, y0 = by * TILE_Y - H;
   const int X0c = x0 >> 1, Y0c = y0 >> 1;  // floor halves (arithmetic shift)

@@ -13,6 +13,9 @@
 // writes only the second iterate buffer and the residual scratch of the level.
 // The restriction variants (restrict.hpp) are timed the same way per level,
 // and so is the sweep schedule: two sweeps fused per launch or one per launch.
+// Whether each level folds its restriction into its pre-sweep launch is then
+// chosen for all levels together (tune_fold_chain), since a folded
+// restriction leaves the next level's right-hand side to complete.
 // Choices are cached per (model, arithmetic type, form, level size) for the
 // life of the process.  HFZ_TILE=<shape> forces one shape where it fits,
 // HFZ_RESTRICT=<variant> one restriction variant, HFZ_SWEEPS=1 one sweep per
@@ -163,38 +166,30 @@ float time_schedule(Hier<T>& H, Cycle& K, int l, int fuse, int reps) {
   return ms;
 }
 
-// Average time (ms) of `reps` pre-smoothing passes of level l (two sweeps)
-// with the FAS restriction to level l + 1 after them: folded into the sweep
-// launch (fused, with f_c completed by k_fas_rhs unless the next level is the
-// tail, whose completion costs a phase of the tail kernel) or as the
-// restriction launch of variant rs.  Where level l's own right-hand side
-// arrives as R d and the folded launch could complete it (RES = 4), the two
-// candidates are a RES = 4 launch against k_fas_rhs on level l followed by
-// the separate pre-sweep and restriction launches.
+// Average time (ms) of `reps` launches of what level l's pre-smoothing and
+// restriction can cost (two sweeps per launch), after one untimed launch:
+// what 0 the pre-sweep launch with the restriction folded in (RES = 3),
+// 1 the same after completing the level's own right-hand side (RES = 4),
+// 2 the pre-sweep launch with the residual field and the restriction launch
+// of variant rs, 3 k_fas_rhs completing level l's right-hand side.  Negative
+// on a HIP error.
 template <int MODEL, typename T, bool CORR>
-float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int reps) {
+float time_restriction_part(Hier<T>& H, Cycle& K, int l, int what, int rs, int reps) {
   const Lvl<T>& L = H.L[l];
   const Lvl<T>& C = H.L[l + 1];
   const Fld<T> a = fld<T>(L.g), b = fld<T>(L.gb);
   const int ts = H.tile_shape[l];
-  const bool tail_next = C.n <= K.tail_n;
-  const bool rhs_here = fold_rhs_possible<MODEL, T, CORR>(H, K, l);
   auto pass = [&]() {
-    if (fused) {
-      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, rhs_here ? 4 : 3, ts);
-      if (!tail_next) {
-        const dim3 bl = block2(C.n, C.n);
-        k_fas_rhs<MODEL, T, CORR><<<grid2(C.n, C.n, bl), bl, 0, K.stream>>>(C, H.P);
-      }
-    } else {
-      if (rhs_here) {
-        const dim3 bl = block2(L.n, L.n);
-        k_fas_rhs<MODEL, T, CORR><<<grid2(L.n, L.n, bl), bl, 0, K.stream>>>(L, H.P);
-      }
+    if (what == 0 || what == 1) {
+      tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, what == 0 ? 3 : 4, ts);
+    } else if (what == 2) {
       tile_launch<MODEL, T, CORR, 2, false>(H, K, L, a, b, C, 1, ts);
       Lvl<T> F = L;
       for (int c = 0; c < 5; ++c) F.g[c] = b.c[c];
       restrict_launch<MODEL, T, CORR>(H, K, F, C, rs);
+    } else {
+      const dim3 bl = block2(L.n, L.n);
+      k_fas_rhs<MODEL, T, CORR><<<grid2(L.n, L.n, bl), bl, 0, K.stream>>>(L, H.P);
     }
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -214,6 +209,76 @@ float time_restriction_mode(Hier<T>& H, Cycle& K, int l, bool fused, int rs, int
   if (e1) (void)hipEventDestroy(e1);
   (void)hipGetLastError();
   return ms;
+}
+
+// Best of three rounds of time_restriction_part (a large value if it fails).
+template <int MODEL, typename T, bool CORR>
+float restriction_cost(Hier<T>& H, Cycle& K, int l, int what) {
+  float best = -1.0f;
+  for (int round = 0; round < 3; ++round) {
+    const float t = time_restriction_part<MODEL, T, CORR>(H, K, l, what, H.restrict_shape[l], 8);
+    if (t > 0.0f && (best < 0.0f || t < best)) best = t;
+  }
+  return best > 0.0f ? best : 1e9f;
+}
+
+// The restriction of every tiled level folded or not, chosen jointly: level
+// l's cost depends on its own choice and on whether the level above folded
+// (then l's right-hand side arrives as R d, completed by l's RES = 4 launch
+// if l folds and can, else by k_fas_rhs), so the cheapest assignment is a
+// shortest path over the levels with two states.  Levels whose choice is
+// fixed (fixed[l]) keep H.fused[l].
+template <int MODEL, typename T, bool CORR>
+void tune_fold_chain(Hier<T>& H, Cycle& K, const std::vector<char>& fixed, int verbose) {
+  int nt = 0;
+  while (nt + 1 < (int)H.L.size() && level_tiled<MODEL, T, CORR>(H, K, nt)) ++nt;
+  if (nt == 0) return;
+  // cost[l][s][p]: level l folds (s = 1) or not, the level above folded (p = 1) or not
+  std::vector<float> c3(nt), c4(nt, 1e9f), csep(nt), crhs(nt, 0.0f);
+  std::vector<char> cap(nt, 0);
+  for (int l = 0; l < nt; ++l) {
+    c3[l] = restriction_cost<MODEL, T, CORR>(H, K, l, 0);
+    csep[l] = restriction_cost<MODEL, T, CORR>(H, K, l, 2);
+    if (l > 0) crhs[l] = restriction_cost<MODEL, T, CORR>(H, K, l, 3);
+    cap[l] = (char)fold_rhs_capable<MODEL, T, CORR>(H, K, l);
+    if (cap[l]) c4[l] = restriction_cost<MODEL, T, CORR>(H, K, l, 1);
+  }
+  auto cost = [&](int l, int s, int p) -> float {
+    if (s == 1) return p ? (cap[l] ? c4[l] : crhs[l] + c3[l]) : c3[l];
+    return (p ? crhs[l] : 0.0f) + csep[l];
+  };
+  std::vector<float> best(2 * nt);
+  std::vector<int> from(2 * nt, 0);
+  for (int l = 0; l < nt; ++l)
+    for (int s = 0; s < 2; ++s) {
+      float b = 1e30f;
+      if (!(fixed[l] && H.fused[l] != s)) {
+        if (l == 0) {
+          b = cost(0, s, 0);
+        } else {
+          for (int p = 0; p < 2; ++p) {
+            const float v = best[2 * (l - 1) + p] + cost(l, s, p);
+            if (v < b) {
+              b = v;
+              from[2 * l + s] = p;
+            }
+          }
+        }
+      }
+      best[2 * l + s] = b;
+    }
+  int s = best[2 * (nt - 1) + 1] < best[2 * (nt - 1)] ? 1 : 0;
+  for (int l = nt - 1; l >= 0; --l) {
+    H.fused[l] = (char)s;
+    s = from[2 * l + s];
+  }
+  if (verbose) {
+    std::fprintf(stderr, "hfz tune restriction folded (us: RES3 / RES4 / separate / rhs):");
+    for (int l = 0; l < nt; ++l)
+      std::fprintf(stderr, " n=%d %.2f/%.2f/%.2f/%.2f->%d", H.L[l].n, c3[l] * 1e3f, cap[l] ? c4[l] * 1e3f : -1.0f,
+                   csep[l] * 1e3f, crhs[l] * 1e3f, (int)H.fused[l]);
+    std::fprintf(stderr, "\n");
+  }
 }
 
 // Index of the fastest of `count` candidates timed by `time(k)` (best of
@@ -265,6 +330,7 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
   if (const char* e = std::getenv("HFZ_TILE")) forced = std::atoi(e);
   bool tune = true;
   if (const char* e = std::getenv("HFZ_TUNE")) tune = std::atoi(e) != 0;
+  std::vector<char> pending(nlev, 0);  // levels whose fold choice is timed (tune_fold_chain)
   for (int l = 0; l + 1 < nlev; ++l) {
     const int n = H.L[l].n, nc = H.L[l + 1].n;
     if (n < TILE_X || nc < RTILE || H.L[l].gb[0] == nullptr) continue;
@@ -301,17 +367,24 @@ template <int MODEL, typename T, bool CORR> void tune_tile_shapes(Hier<T>& H, Cy
     const int fs = pick_fastest(
         2, [&](int k) { return time_schedule<MODEL, T, CORR>(H, K, l, k == 0 ? 2 : 1, 8); }, "sweeps", n);
     if (forced_f < 0) H.sweep_fuse[l] = fs == 0 ? 2 : 1;
-    // the restriction: a launch of its own, or folded into the last pre-sweep
-    // launch (candidate 1; never for the channel)
-    int fx = 0;
+    // the restriction folded or not: decided for all timed levels together
+    // below (never folded for the channel)
+    if (forced_x < 0) pending[l] = 1;
+  }
+  bool any = false;
+  for (int l = 0; l < nlev; ++l) any = any || pending[l];
+  if (any) {
     if constexpr (!walls(MODEL)) {
-      fx = pick_fastest(
-          2, [&](int k) { return time_restriction_mode<MODEL, T, CORR>(H, K, l, k == 1, H.restrict_shape[l], 8); },
-          "restriction folded", n);
+      std::vector<char> fixed(nlev);
+      for (int l = 0; l < nlev; ++l) fixed[l] = !pending[l];
+      tune_fold_chain<MODEL, T, CORR>(H, K, fixed, std::getenv("HFZ_VERBOSE") != nullptr);
     }
-    if (forced_x < 0) H.fused[l] = (char)fx;
     std::lock_guard<std::mutex> g(tune_mutex());
-    tune_cache()[key] = std::make_tuple(ts, rs, fs == 0 ? 2 : 1, fx);
+    for (int l = 0; l < nlev; ++l) {
+      if (!pending[l]) continue;
+      tune_cache()[std::make_tuple(MODEL, (int)sizeof(T), (int)CORR, H.L[l].n)] =
+          std::make_tuple(H.tile_shape[l], H.restrict_shape[l], H.sweep_fuse[l], (int)H.fused[l]);
+    }
     tune_cache_save();
   }
 }
