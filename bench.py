@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--conv-sizes", default="16,32,64,128,256,512")
     ap.add_argument("--conv-tf", type=float, default=10.0)
     ap.add_argument("--probe-tile-shape", type=int, default=9,
-                    help="tile shape of the counter probe (the one the tuner picks at 512^2)")
+                    help="tile shape of the counter probe (9: 64x16/1024, 8: 32x32/1024, the two the "
+                         "tuner picks between at 512^2)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="only launch the smoother and a reference copy kernel (for counter runs)")
     return ap.parse_args()
@@ -130,18 +131,24 @@ def committed_traffic_3d(n):
 
 
 def committed_traffic(shape):
-    """HBM bytes per smoother launch from the committed counter summary, or
-    None if it is missing, was taken from other kernel sources or from
-    another tile shape."""
+    """HBM bytes per smoother launch in tile shape `shape` ("64x16x1024") from
+    the committed counter summary (a line traffic_bytes_per_launch_<shape>,
+    or tile_shape + traffic_bytes_per_launch), or None if it is missing, was
+    taken from other kernel sources or for another tile shape."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             text = f.read()
     except OSError:
         return None
     m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    t = re.search(r"traffic_bytes_per_launch_%s:\s*([0-9.eE+]+)" % re.escape(shape), text)
+    if t:
+        return float(t.group(1))
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     sh = re.search(r"tile_shape:\s*([0-9x]+)", text)
-    if not m or not t or not sh or m.group(1) != source_hash() or sh.group(1) != shape:
+    if not t or not sh or sh.group(1) != shape:
         return None
     return float(t.group(1))
 
