@@ -78,7 +78,8 @@
  *    HFZ_GRAPH=0          no HIP graph capture of the V-cycle
  *    HFZ_FUSE=<0|1>       FAS restriction as a launch of its own (0) or folded
  *                         into the last pre-sweep launch of a level (1) on every
- *                         level where it can be (default: timed per level)
+ *                         level where it can be (default: timed, the choices of
+ *                         all levels made together)
  *    HFZ_FOLD_RHS=0       a coarse level whose right-hand side a folded
  *                         restriction left as R d has it completed by a launch
  *                         of its own (default: by its own pre-sweep launch where

@@ -306,7 +306,8 @@ template <typename F> int pick_fastest(int count, F&& time, const char* what = n
 // levels the tiled V-cycle visits (size >= 32 with a coarser level of >= 16,
 // above the tail).  HFZ_RESTRICT=<variant> forces a restriction variant where
 // it fits; HFZ_FUSE=0 / 1 keeps the restriction launches separate / folds
-// them into the sweeps wherever it can (default: whichever times faster).
+// them into the sweeps wherever it can (default: the cheapest assignment over
+// all levels, tune_fold_chain).
 // HFZ_FOLD_RHS=0 leaves the completion of a folded level's coarse right-hand
 // side to k_fas_rhs everywhere (default: the coarse level's RES = 4 launch
 // where level_fold_rhs allows it).
