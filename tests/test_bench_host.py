@@ -41,6 +41,22 @@ def test_committed_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.committed_traffic("64x16x512") is None
 
 
+def test_committed_traffic_per_shape_lines(tmp_path, monkeypatch):
+    """A summary may carry one traffic line per tile shape
+    (traffic_bytes_per_launch_<shape>); each shape reads its own, a shape
+    without a line gets None, and a stale hash voids them all."""
+    h = bench.source_hash()
+    p = tmp_path / "multi.md"
+    p.write_text(f"source_hash: {h}\ntraffic_bytes_per_launch_64x16x1024: 38515727\n"
+                 "traffic_bytes_per_launch_32x32x1024: 38505275\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(p))
+    assert bench.committed_traffic("64x16x1024") == 38515727.0
+    assert bench.committed_traffic("32x32x1024") == 38505275.0
+    assert bench.committed_traffic("32x16x512") is None
+    p.write_text("source_hash: 0123456789abcdef\ntraffic_bytes_per_launch_64x16x1024: 1\n")
+    assert bench.committed_traffic("64x16x1024") is None
+
+
 def test_committed_traffic_3d_follows_the_source_hash(tmp_path, monkeypatch):
     h = bench.source_hash(bench.KERNEL_SOURCES_3D)
     assert h != bench.source_hash()
